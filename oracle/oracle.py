@@ -1,0 +1,230 @@
+"""ctypes binding of the FP64 CPU oracle (``nopcs_oracle.c``).
+
+Test infrastructure only.  The library is compiled from source by ``build()``
+(gcc, ``-O2 -ffp-contract=off -fno-fast-math -fopenmp``) when it is missing.
+All arrays are C-contiguous float64 numpy arrays; 3D fields are indexed
+``[k][j][i]`` (x fastest) and a state is ``Q[5, nz, ny, nx]`` holding
+``[rho, rho u, rho v, rho w, E']`` with ``E' = rho e_t - Rh/(gamma-1)``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nopcs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libnopcs_oracle.so")
+_lib = None
+
+__all__ = [
+    "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
+    "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
+    "scales", "segment_starts",
+]
+
+
+def build(force=False):
+    """Compile the oracle shared library with gcc."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OraParams(ctypes.Structure):
+    """SI parameters (Section 2); the oracle non-dimensionalizes them itself."""
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("gamma", "R_gas", "g", "L", "T_s", "rho_s", "Pr", "mu_ref", "T_ref", "S_suth", "mub_a", "mub_b")] + \
+               [("viscous", ctypes.c_int32), ("gravity", ctypes.c_int32)]
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{k: d[k] for k, _ in cls._fields_})
+
+
+_D = ctypes.c_double
+_I = ctypes.c_int
+_P = ctypes.c_void_p
+_PD = ctypes.c_ssize_t
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        for name in ("ora_alpha", "ora_b1", "ora_b2"):
+            getattr(L, name).restype = _D
+            getattr(L, name).argtypes = []
+        L.ora_nb.restype = _I
+        L.ora_thomas.argtypes = [_I, _P, _P, _P, _P, _P, _P]
+        L.ora_d1_line.argtypes = [_I, _D, _P, _PD, _P, _PD, _P]
+        L.ora_equiv_row.argtypes = [_I, _I, _P, _P]
+        L.ora_d1_line_seg.argtypes = [_I, _D, _I, _P, _P, _PD, _P, _PD, _P]
+        L.ora_d1_3d.argtypes = [_P, _P, _I, _P, _P]
+        L.ora_d1_3d_seg.argtypes = [_P, _P, _I, _I, _P, _P, _P]
+        L.ora_d2_3d.argtypes = [_P, _P, _I, _P, _P]
+        L.ora_rhs.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _P]
+        L.ora_rhs_points.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _I, _P, _P]
+        L.ora_apply_bc.argtypes = [ctypes.POINTER(OraParams), _P, _P]
+        L.ora_rk4.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _D, _I]
+        L.ora_rk4_linear.argtypes = [_D, _D, _D, _I]
+        L.ora_rk4_linear.restype = _D
+        L.ora_scales.argtypes = [ctypes.POINTER(OraParams), _P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dims(shape):
+    """(nz, ny, nx) -> int32[3] = (nx, ny, nz)."""
+    nz, ny, nx = shape
+    return np.array([nx, ny, nz], dtype=np.int32)
+
+
+def _lens(length):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(length, dtype=np.float64), (3,)))
+
+
+def alpha():
+    return lib().ora_alpha()
+
+
+def b1():
+    return lib().ora_b1()
+
+
+def b2():
+    return lib().ora_b2()
+
+
+def nb():
+    return lib().ora_nb()
+
+
+def thomas(sub, dia, sup, rhs):
+    """General tridiagonal solve (sub[0], sup[-1] ignored)."""
+    sub, dia, sup, rhs = (_f64(a) for a in (sub, dia, sup, rhs))
+    m = len(dia)
+    x = np.empty(m)
+    w = np.empty(m)
+    lib().ora_thomas(m, _ptr(sub), _ptr(dia), _ptr(sup), _ptr(rhs), _ptr(x), _ptr(w))
+    return x
+
+
+def d1_line(f, h=1.0):
+    f = _f64(f)
+    n = len(f)
+    out = np.empty(n)
+    w = np.empty(8 * n)
+    lib().ora_d1_line(n, 1.0 / h, _ptr(f), 1, _ptr(out), 1, _ptr(w))
+    return out
+
+
+def equiv_row(n, e):
+    """Row e of the global C = A^-1 B with h = 1 (length n)."""
+    row = np.empty(n)
+    w = np.empty(8 * n)
+    lib().ora_equiv_row(n, e, _ptr(row), _ptr(w))
+    return row
+
+
+def segment_starts(n, nseg):
+    """Near-equal split of n points into nseg segments (remainder to the first ones)."""
+    base, rem = divmod(n, nseg)
+    starts, s = [], 0
+    for k in range(nseg):
+        starts.append(s)
+        s += base + (1 if k < rem else 0)
+    return np.array(starts, dtype=np.int32)
+
+
+def d1_line_seg(f, seg_lo, h=1.0):
+    f = _f64(f)
+    n = len(f)
+    seg_lo = np.ascontiguousarray(seg_lo, dtype=np.int32)
+    out = np.empty(n)
+    w = np.empty(16 * n)
+    lib().ora_d1_line_seg(n, 1.0 / h, len(seg_lo), _ptr(seg_lo), _ptr(f), 1, _ptr(out), 1, _ptr(w))
+    return out
+
+
+def d1(f, direction, length=1.0):
+    """First derivative of a 3D field f[k, j, i] along direction 0 (x), 1 (y) or 2 (z)."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().ora_d1_3d(_ptr(_dims(f.shape)), _ptr(_lens(length)), int(direction), _ptr(f), _ptr(out))
+    return out
+
+
+def d1_seg(f, direction, seg_lo, length=1.0):
+    f = _f64(f)
+    out = np.empty_like(f)
+    seg_lo = np.ascontiguousarray(seg_lo, dtype=np.int32)
+    lib().ora_d1_3d_seg(_ptr(_dims(f.shape)), _ptr(_lens(length)), int(direction), len(seg_lo), _ptr(seg_lo),
+                        _ptr(f), _ptr(out))
+    return out
+
+
+def d2(f, direction, length=1.0):
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().ora_d2_3d(_ptr(_dims(f.shape)), _ptr(_lens(length)), int(direction), _ptr(f), _ptr(out))
+    return out
+
+
+def rhs(params, Q, length=1.0):
+    """Right-hand side R(Q) of ge17 for a state Q[5, nz, ny, nx]."""
+    Q = _f64(Q)
+    R = np.empty_like(Q)
+    p = OraParams.from_dict(params)
+    lib().ora_rhs(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), _ptr(R))
+    return R
+
+
+def rhs_points(params, Q, pts, length=1.0):
+    """R(Q) at the points pts[m, 3] = (i, j, k); returns [5, m]."""
+    Q = _f64(Q)
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    out = np.empty((5, len(pts)))
+    p = OraParams.from_dict(params)
+    lib().ora_rhs_points(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), len(pts),
+                         _ptr(pts), _ptr(out))
+    return out
+
+
+def apply_bc(params, Q):
+    Q = _f64(Q).copy()
+    p = OraParams.from_dict(params)
+    lib().ora_apply_bc(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(Q))
+    return Q
+
+
+def rk4(params, Q, dt, nsteps, length=1.0):
+    """Advance Q by nsteps classical RK4 steps of size dt (returns a new array)."""
+    Q = _f64(Q).copy()
+    p = OraParams.from_dict(params)
+    lib().ora_rk4(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), float(dt), int(nsteps))
+    return Q
+
+
+def rk4_linear(q0, lam, dt, nsteps):
+    return lib().ora_rk4_linear(float(q0), float(lam), float(dt), int(nsteps))
+
+
+def scales(params):
+    """(U_s, t_s, Rh, M, Re, mu_s) as computed by the oracle."""
+    out = np.empty(6)
+    p = OraParams.from_dict(params)
+    lib().ora_scales(ctypes.byref(p), _ptr(out))
+    return tuple(out)
