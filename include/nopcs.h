@@ -1,0 +1,169 @@
+/*
+ * nopcs.h -- C ABI of libnopcs.so, the MI355X (gfx950) implementation of the
+ * non-overlapping parallel compact scheme (NOHAP closure on OUCS3) and of the
+ * compressible Navier-Stokes stepping that consumes it, after "Ultrasound
+ * Triggering of Rayleigh-Taylor Instability: Solution of Compressible
+ * Navier-Stokes Equation by a Non-Overlapping Parallel Compact Scheme"
+ * (Sundaram, Sengupta & Sengupta).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Fields live in device memory (HBM), FP64, structure-of-arrays, x fastest:
+ *    element (i, j, k) of a field is at offset i + n[0] * (j + n[1] * k).
+ *    y is the vertical direction; gravity acts along -y.
+ *  - A state Q holds 5 such fields back to back: rho, rho u, rho v, rho w, E',
+ *    non-dimensional (Section 2, eqs. ge14-ge15; velocity scale sqrt(g L),
+ *    pressure scale rho_s g L).  E' = rho e_t - Rh / (gamma - 1) with
+ *    Rh = R T_s / (g L): the total energy minus the constant energy of the
+ *    reference state p = Rh (an exact shift that keeps low-Mach round-off small).
+ *  - Nodes sit on the walls: the spacing along d is h_d = len[d] / (n[d] - 1).
+ *  - Every call is asynchronous on the HIP stream passed in (NULL = the null
+ *    stream); the caller owns all buffers passed in and must keep them alive
+ *    until the stream has run the work.  The library never frees them.
+ *  - Return value: NOPCS_OK (0) or a negative NOPCS_E* code; nothing throws
+ *    across the ABI.  Argument errors are reported synchronously and launch
+ *    nothing; nopcs_last_error() gives a message for the calling thread.
+ *    Device faults surface at the next synchronising call.
+ *  - The library owns cached per-grid plans (segment tables, closure rows,
+ *    elimination tables) in device memory; nopcs_release_plans() frees them.
+ */
+#ifndef NOPCS_H
+#define NOPCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NOPCS_OK = 0,
+    NOPCS_EINVAL = -1,     /* invalid argument (sizes, segments, pointers, precision) */
+    NOPCS_ENOMEM = -2,     /* device or host allocation failed, or over the HBM budget */
+    NOPCS_EDEVICE = -3,    /* a HIP runtime call failed */
+    NOPCS_EAGAIN = -4,     /* request still pending (solver_poll) */
+    NOPCS_ENOTFOUND = -5,  /* unknown or already released request id */
+    NOPCS_ENONFINITE = -6, /* a request's final state holds NaN or Inf */
+    NOPCS_EBUSY = -7       /* request queue full */
+};
+
+enum {
+    NOPCS_FP64 = 0,   /* every step in FP64 */
+    NOPCS_MIXED = 1   /* FP32 interior sweeps and fluxes; FP64 closure rows, wall rows,
+                         RHS accumulation and RK registers */
+};
+
+/* Uniform box.  n[d] >= 8 points along x, y, z; len[d] > 0 non-dimensional edge
+ * (units of L); nseg[d] >= 1 non-overlapping segments along d (Section 3, Fig. 2),
+ * split as evenly as possible (the first n % nseg segments get one extra point),
+ * each segment at least 4 points long. */
+typedef struct {
+    int32_t n[3];
+    double len[3];
+    int32_t nseg[3];
+} nopcs_grid;
+
+/* Physical parameters in SI units (Section 2); the library non-dimensionalizes:
+ * U_s = sqrt(g L), Rh = R_gas T_s / (g L), M^2 = g L / (gamma R_gas T_s),
+ * mu_s = Sutherland(T_s) with (mu_ref, T_ref, S_suth), Re = rho_s U_s L / mu_s,
+ * bulk viscosity mu_b = mub_a T* - mub_b [Pa s] (eq. reg: mub_a = 3.381e-4,
+ * mub_b = 7.383e-4).  viscous = 0 drops the viscous fluxes, gravity = 0 the
+ * source term ge8a. */
+typedef struct {
+    double gamma, R_gas, g, L, T_s, rho_s, Pr, mu_ref, T_ref, S_suth, mub_a, mub_b;
+    int32_t viscous, gravity;
+} nse_params;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nopcs_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int nopcs_version(void);
+
+/* Free every cached plan on the current device (not thread-safe against
+ * concurrent calls). */
+int nopcs_release_plans(void);
+
+/* Workspace (device bytes) needed by nse_rhs (0) and rk_step (three 5-field
+ * registers: the RK4 accumulator, the stage state and the right-hand side)
+ * for this grid and precision.  Returns 0 on invalid input. */
+size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision);
+
+/*
+ * nopcs_line_plan -- host-only introspection of the segmented line plan that
+ * nopcs_derivative uses along a line of n points cut into nseg segments
+ * (Section 3, Fig. 2), each further cut into pieces of at most piece_len points
+ * (0: no extra cuts; -1: the library's own choice for this n).
+ * Outputs (each may be NULL; cap bounds every array):
+ *   *nrun, runs[2*r] = (lo, hi): known rows bounding each Thomas run (unknowns lo+1..hi-1);
+ *   *ncl, rows[q]: closure rows; coef[97*q + t]: C_{e, e-48+t} * h (0 outside the line)
+ *   with C the global A^-1 B (Eqs. CS:fpCf, CS:fpCf_i).
+ * Returns NOPCS_OK, NOPCS_EINVAL (bad n/nseg) or NOPCS_ENOMEM (cap too small).
+ * Touches no device.
+ */
+int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int32_t *nrun, int32_t *runs,
+                    int32_t *ncl, int32_t *rows, double *coef);
+
+/*
+ * nopcs_derivative -- first and/or second derivative along one direction.
+ *
+ * Computes f' from the OUCS3 compact scheme [A]{f'} = [B]{f} (Section 3,
+ * Eq. CS:AfpBf; interior A = (alpha, 1, alpha), B antisymmetric with b1, b2)
+ * with the NOHAP sub-domain closure: each line along `dir` is cut into
+ * grid->nseg[dir] non-overlapping segments; the first and last point of every
+ * segment that is not a wall row take the truncated equivalent explicit value
+ * f'_e = sum_{|k|<=48} C_{e,e+k} f_{e+k} with C the row of the global
+ * A^-1 B (Eqs. CS:fpCf and CS:fpCf_i), and the remaining rows of each segment
+ * are solved independently by the Thomas algorithm.  The result equals the
+ * sequential single-domain solve up to round-off (Section 3).  Rows 0 and
+ * n-1 use the second-order one-sided difference and rows 1 and n-2 the
+ * second-order central difference (the physical-boundary closure, which the
+ * paper cites without giving).  The second derivative is the same operator
+ * applied twice.  The library may cut segments further into shorter
+ * independent pieces with the same closure; results change by round-off only.
+ *
+ * dir: 0 = x, 1 = y, 2 = z.  precision: NOPCS_FP64 or NOPCS_MIXED.
+ * f: device, n0*n1*n2 doubles (read only).  d1, d2: device outputs of the same
+ * size, either may be NULL but not both; they must not overlap f.
+ */
+int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const double *f, double *d1, double *d2,
+                     void *hip_stream);
+
+/*
+ * nse_rhs -- right-hand side of the non-dimensional compressible NSE (ge17):
+ *   R = dEv/dx + dFv/dy + dGv/dz + S - (dE/dx + dF/dy + dG/dz)
+ * with convective fluxes ge3-ge5 differentiated by the NOHAP compact scheme
+ * (as nopcs_derivative), viscous fluxes ge6-ge8 with the stresses of ge19 and
+ * bv1-bv3 (bulk viscosity from eq. reg, no Stokes hypothesis), heat flux ge20
+ * and gravity source ge8a, the viscous terms by second-order explicit
+ * differences (Section 4), central inside and one-sided on wall nodes.
+ *
+ * Q: device state (5 fields, read only); R: device output (5 fields), must not
+ * overlap Q.  ws/ws_bytes: unused for NOPCS_FP64 (may be NULL/0).
+ */
+int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R, void *ws,
+            size_t ws_bytes, void *hip_stream);
+
+/*
+ * rk_step -- advance Q by nsteps steps of the classical four-stage RK4
+ * (Section 4) at fixed dt (non-dimensional time, units of sqrt(L/g)):
+ *   k1 = R(Q), k2 = R(Q + dt/2 k1), k3 = R(Q + dt/2 k2), k4 = R(Q + dt k3),
+ *   Q <- Q + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+ * applying the wall conditions of the closed, adiabatic box (Section 2) to
+ * every stage state and to the new state: zero momentum; wall temperature
+ * from the one-sided second-order normal derivative of T set to zero; wall
+ * density evolved by continuity; E' from the equation of state.  Faces are
+ * treated in the order x, y, z.
+ *
+ * Q: device state, in/out.  ws: device workspace of at least
+ * nopcs_workspace_bytes(grid, precision) bytes, 256-byte aligned.
+ */
+int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
+            void *ws, size_t ws_bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NOPCS_H */

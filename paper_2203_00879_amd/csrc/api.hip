@@ -1,0 +1,223 @@
+// api.hip -- C ABI entry points of libnopcs (declared in include/nopcs.h).
+#include <cmath>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace nopcs {
+
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string &msg) { g_err = msg; }
+const char *get_error() { return g_err.c_str(); }
+
+// Length of the extra cuts inside each user segment.  Short lines keep a single
+// run per segment (sequential Thomas order); long lines are cut so that a pencil
+// has enough independent runs for its threads.  Overridable for tuning.
+static int g_piece_len[3] = {-1, -1, -1};
+
+int piece_length(int dir, int n) {
+    if (g_piece_len[dir] >= 0) return g_piece_len[dir];
+    if (n <= 64) return 0;
+    const int P = sweep_lines_per_block(dir, n), NT = sweep_threads_per_block(dir, n);
+    // runs needed so that P * runs >= NT / 2
+    const int runs = (NT / 2 + P - 1) / P;
+    int len = n / (runs > 0 ? runs : 1);
+    if (len < 12) len = 12;
+    return len;
+}
+
+static bool check_grid(const nopcs_grid *g) {
+    if (!g) { set_error("grid is NULL"); return false; }
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 8 || g->n[d] > 1024) {
+            set_error("grid n[" + std::to_string(d) + "] must be in [8, 1024], got " + std::to_string(g->n[d]));
+            return false;
+        }
+        if (!(g->len[d] > 0.0) || !std::isfinite(g->len[d])) {
+            set_error("grid len[" + std::to_string(d) + "] must be positive and finite");
+            return false;
+        }
+        if (g->nseg[d] < 1 || g->n[d] < 4 * g->nseg[d]) {
+            set_error("grid nseg[" + std::to_string(d) + "] must be >= 1 with segments of >= 4 points");
+            return false;
+        }
+    }
+    return true;
+}
+
+static bool check_params(const nse_params *p) {
+    if (!p) { set_error("params is NULL"); return false; }
+    const double v[] = {p->gamma, p->R_gas, p->g, p->L, p->T_s, p->rho_s, p->Pr, p->mu_ref, p->T_ref};
+    for (double x : v)
+        if (!(x > 0.0) || !std::isfinite(x)) {
+            set_error("physical parameters must be positive and finite");
+            return false;
+        }
+    if (!(p->gamma > 1.0)) { set_error("gamma must exceed 1"); return false; }
+    if (!std::isfinite(p->S_suth) || !std::isfinite(p->mub_a) || !std::isfinite(p->mub_b)) {
+        set_error("viscosity constants must be finite");
+        return false;
+    }
+    return true;
+}
+
+static int get_plans(const nopcs_grid *g, LinePlanDev pl[3]) {
+    for (int d = 0; d < 3; ++d) {
+        const int rc = get_line_plan(g->n[d], g->nseg[d], piece_length(d, g->n[d]), g->len[d], &pl[d]);
+        if (rc != NOPCS_OK) return rc;
+        const int P = sweep_lines_per_block(d, g->n[d]), NT = sweep_threads_per_block(d, g->n[d]);
+        if ((long long)P * pl[d].ncl > 4LL * NT) {
+            set_error("too many closure rows for one pencil (shorten the segment count)");
+            return NOPCS_EINVAL;
+        }
+    }
+    return NOPCS_OK;
+}
+
+static size_t field_elems(const nopcs_grid *g) { return (size_t)g->n[0] * g->n[1] * g->n[2]; }
+
+}  // namespace nopcs
+
+using namespace nopcs;
+
+extern "C" {
+
+const char *nopcs_last_error(void) { return get_error(); }
+
+int nopcs_version(void) { return 100; }
+
+int nopcs_release_plans(void) {
+    release_line_plans();
+    return NOPCS_OK;
+}
+
+size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision) {
+    if (!check_grid(grid) || (precision != NOPCS_FP64 && precision != NOPCS_MIXED)) return 0;
+    const size_t N = field_elems(grid);
+    const size_t reg = ((5 * N * sizeof(double)) + 255) & ~(size_t)255;
+    return 3 * reg;
+}
+
+int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int32_t *nrun, int32_t *runs,
+                    int32_t *ncl, int32_t *rows, double *coef) {
+    if (piece_len < -1) { set_error("piece_len must be >= -1"); return NOPCS_EINVAL; }
+    LinePlanHost P;
+    std::string err;
+    const int len = piece_len == -1 ? piece_length(1, n) : piece_len;
+    if (!build_line_plan(n, nseg, len, P, err)) { set_error(err); return NOPCS_EINVAL; }
+    const int nr = (int)P.runs.size(), nc = (int)P.cl_row.size();
+    if (nrun) *nrun = nr;
+    if (ncl) *ncl = nc;
+    if ((runs && nr > cap) || ((rows || coef) && nc > cap)) { set_error("cap too small"); return NOPCS_ENOMEM; }
+    if (runs)
+        for (int r = 0; r < nr; ++r) { runs[2 * r] = P.runs[r].x; runs[2 * r + 1] = P.runs[r].y; }
+    if (rows)
+        for (int q = 0; q < nc; ++q) rows[q] = P.cl_row[q];
+    if (coef)
+        for (int q = 0; q < nc; ++q) {
+            const int e = P.cl_row[q];
+            for (int t = 0; t < kTaps; ++t) {
+                const int j = e - kNb + t;
+                coef[(size_t)q * kTaps + t] =
+                    (j < P.cl_j0[q] || j >= P.cl_j0[q] + P.cl_len[q]) ? 0.0 : P.cl_coef[(size_t)q * kTaps + (j - P.cl_j0[q])];
+            }
+        }
+    return NOPCS_OK;
+}
+
+int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const double *f, double *d1, double *d2,
+                     void *hip_stream) {
+    if (!check_grid(grid)) return NOPCS_EINVAL;
+    if (dir < 0 || dir > 2) { set_error("dir must be 0, 1 or 2"); return NOPCS_EINVAL; }
+    if (precision != NOPCS_FP64) { set_error("nopcs_derivative: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
+    if (!f || (!d1 && !d2)) { set_error("f and at least one of d1, d2 must be non-NULL"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    const SweepGeom g = sweep_geom(grid->n, dir);
+    NOPCS_HIP_CHECK(launch_deriv(dir, f, d1, d2, g, pl[dir], (hipStream_t)hip_stream));
+    return NOPCS_OK;
+}
+
+static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev pl[3], const double *Q, double *R,
+                    hipStream_t st) {
+    double ih[3];
+    for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
+    NOPCS_HIP_CHECK(launch_visc(Q, R, grid->n, ih, c, st));
+    NseSweepArgs a{};
+    a.Qin = Q;
+    a.R = R;
+    a.N3 = (long long)field_elems(grid);
+    a.c = c;
+    for (int d = 0; d < 3; ++d)
+        NOPCS_HIP_CHECK(launch_nse_sweep(d, MODE_ACCUM, a, sweep_geom(grid->n, d), pl[d], st));
+    return NOPCS_OK;
+}
+
+int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R, void *ws,
+            size_t ws_bytes, void *hip_stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (precision != NOPCS_FP64) { set_error("nse_rhs: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
+    if (!Q || !R) { set_error("Q and R must be non-NULL"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    return rhs_into(make_nd(*params), grid, pl, Q, R, (hipStream_t)hip_stream);
+}
+
+int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
+            void *ws, size_t ws_bytes, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (precision != NOPCS_FP64) { set_error("rk_step: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
+    if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
+    if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
+    const size_t need = nopcs_workspace_bytes(grid, precision);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return NOPCS_EINVAL;
+    }
+    if (((uintptr_t)ws & 255) != 0) { set_error("workspace must be 256-byte aligned"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    const NdConst c = make_nd(*params);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t N = field_elems(grid);
+    const size_t reg = need / 3;
+    double *K = reinterpret_cast<double *>(ws);
+    double *Qs = reinterpret_cast<double *>(static_cast<char *>(ws) + reg);
+    double *R = reinterpret_cast<double *>(static_cast<char *>(ws) + 2 * reg);
+    double ih[3];
+    for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
+    NseSweepArgs a{};
+    a.R = R;
+    a.Qn = Q;
+    a.K = K;
+    a.Qs = Qs;
+    a.N3 = (long long)N;
+    a.c = c;
+    a.dt = dt;
+    a.half_dt = 0.5 * dt;
+    a.sixth_dt = dt / 6.0;
+    for (int step = 0; step < nsteps; ++step) {
+        for (int stage = 0; stage < 4; ++stage) {
+            const double *Qin = stage == 0 ? Q : Qs;
+            a.Qin = Qin;
+            a.stage = stage;
+            NOPCS_HIP_CHECK(launch_visc(Qin, R, grid->n, ih, c, st));
+            NOPCS_HIP_CHECK(launch_nse_sweep(0, MODE_ACCUM, a, sweep_geom(grid->n, 0), pl[0], st));
+            NOPCS_HIP_CHECK(launch_nse_sweep(1, MODE_ACCUM, a, sweep_geom(grid->n, 1), pl[1], st));
+            NOPCS_HIP_CHECK(launch_nse_sweep(2, MODE_RK, a, sweep_geom(grid->n, 2), pl[2], st));
+            double *Qout = stage < 3 ? Qs : Q;
+            for (int d = 0; d < 3; ++d) NOPCS_HIP_CHECK(launch_bc(Qout, grid->n, d, c, st));
+        }
+    }
+    return NOPCS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// kernels.hpp -- kernel argument blocks and host launchers of libnopcs.
+#pragma once
+
+#include "common.hpp"
+#include "plan.hpp"
+#include "sweep.hpp"
+
+namespace nopcs {
+
+enum { MODE_ACCUM = 0, MODE_RK = 1 };
+
+struct NseSweepArgs {
+    const double *Qin;  // stage input state (5 fields)
+    double *R;          // right-hand side accumulator (5 fields)
+    double *Qn;         // RK: state at the start of the step (in/out at the last stage)
+    double *K;          // RK: k1 + 2 k2 + 2 k3 accumulator
+    double *Qs;         // RK: next stage state
+    long long N3;       // points per field
+    int stage;          // 0..3
+    double dt, half_dt, sixth_dt;
+    NdConst c;
+};
+
+int nmax_class(int n);
+int sweep_lines_per_block(int dir, int n);
+int sweep_threads_per_block(int dir, int n);
+
+hipError_t launch_deriv(int dir, const double *f, double *d1, double *d2, const SweepGeom &g, const LinePlanDev &pl,
+                        hipStream_t st);
+hipError_t launch_nse_sweep(int dir, int mode, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
+                            hipStream_t st);
+
+// Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
+hipError_t launch_visc(const double *Q, double *R, const int n[3], const double ih[3], const NdConst &c,
+                       hipStream_t st);
+
+// Wall conditions on one face pair (dir 0, 1, 2) of state Q.
+hipError_t launch_bc(double *Q, const int n[3], int dir, const NdConst &c, hipStream_t st);
+
+}  // namespace nopcs

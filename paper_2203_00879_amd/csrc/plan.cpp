@@ -1,0 +1,280 @@
+// plan.cpp -- host construction of NOHAP line plans and their device copies.
+//
+// A line of n points (nodes on both walls) is cut into the user's segments
+// (Section 3, Fig. 2) and, optionally, each segment into shorter pieces.  Every
+// piece boundary contributes two closure rows (the last point of one piece and
+// the first of the next) whose derivative is the truncated equivalent explicit
+// sum with the row of the global C = A^-1 B (Eqs. CS:fpCf, CS:fpCf_i).  Rows
+// 0, 1, n-2 and n-1 are explicit second-order wall rows.  The compact rows left
+// between known rows form independent constant-coefficient tridiagonal runs.
+#include "plan.hpp"
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace nopcs {
+
+std::vector<int> even_segments(int n, int nseg) {
+    std::vector<int> lo(nseg);
+    const int base = n / nseg, rem = n % nseg;
+    int s = 0;
+    for (int k = 0; k < nseg; ++k) {
+        lo[k] = s;
+        s += base + (k < rem ? 1 : 0);
+    }
+    return lo;
+}
+
+// Column j of the global C = A^-1 B (h = 1), in long double: solve A x = B e_j.
+static void global_column(int n, int j, std::vector<long double> &x, std::vector<long double> &work) {
+    const long double a = kAlpha, b1 = kB1, b2 = kB2;
+    std::vector<long double> &rhs = x;
+    std::fill(rhs.begin(), rhs.end(), 0.0L);
+    auto put = [&](int row, long double v) {
+        if (row >= 0 && row < n) rhs[row] += v;
+    };
+    // B e_j: entries B_{i,j} of every row i that touches column j
+    if (j <= 2) {  // row 0: (-3/2, 2, -1/2) on columns 0..2
+        const long double w0[3] = {-1.5L, 2.0L, -0.5L};
+        put(0, w0[j]);
+    }
+    if (j == 0) put(1, -0.5L);
+    if (j == 2) put(1, 0.5L);
+    for (int i = j - 2; i <= j + 2; ++i) {
+        if (i < 2 || i > n - 3) continue;
+        const int k = j - i;
+        const long double v = k == -2 ? -b2 : k == -1 ? -b1 : k == 1 ? b1 : k == 2 ? b2 : 0.0L;
+        put(i, v);
+    }
+    if (j == n - 3) put(n - 2, -0.5L);
+    if (j == n - 1) put(n - 2, 0.5L);
+    if (j >= n - 3) {  // row n-1: (1/2, -2, 3/2) on columns n-3..n-1
+        const long double w1[3] = {0.5L, -2.0L, 1.5L};
+        put(n - 1, w1[j - (n - 3)]);
+    }
+    // rows 0, 1, n-2, n-1 are explicit: x equals rhs there.  Rows 2..n-3:
+    // a x_{i-1} + x_i + a x_{i+1} = rhs_i with x_1 and x_{n-2} known.
+    const int m = n - 4;
+    if (m <= 0) return;
+    long double *cp = work.data();
+    long double *dp = work.data() + n;
+    long double prev_c = 0.0L, prev_d = 0.0L;
+    for (int k = 0; k < m; ++k) {
+        const int i = 2 + k;
+        long double r = rhs[i];
+        if (k == 0) r -= a * rhs[1];
+        if (k == m - 1) r -= a * rhs[n - 2];
+        const long double s = (k > 0) ? a : 0.0L;
+        const long double den = 1.0L - s * prev_c;
+        dp[k] = (r - s * prev_d) / den;
+        cp[k] = a / den;
+        prev_c = cp[k];
+        prev_d = dp[k];
+    }
+    x[2 + m - 1] = dp[m - 1];
+    for (int k = m - 2; k >= 0; --k) x[2 + k] = dp[k] - cp[k] * x[2 + k + 1];
+}
+
+bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string &err) {
+    if (n < 8) {
+        err = "line length must be >= 8 (got " + std::to_string(n) + ")";
+        return false;
+    }
+    if (nseg < 1 || n < 4 * nseg) {
+        err = "segments must be >= 1 and each at least 4 points long (n=" + std::to_string(n) +
+              ", nseg=" + std::to_string(nseg) + ")";
+        return false;
+    }
+    P = LinePlanHost();
+    P.n = n;
+    P.nseg = nseg;
+    P.sub_len = sub_len;
+    P.seg_lo = even_segments(n, nseg);
+    // piece starts: user segment starts plus even cuts inside each segment
+    std::vector<int> starts;
+    for (int s = 0; s < nseg; ++s) {
+        const int a = P.seg_lo[s];
+        const int e = (s + 1 < nseg) ? P.seg_lo[s + 1] - 1 : n - 1;
+        const int len = e - a + 1;
+        int pieces = 1;
+        if (sub_len > 0) pieces = (len + sub_len - 1) / sub_len;
+        while (pieces > 1 && len / pieces < 4) --pieces;
+        const std::vector<int> sub = even_segments(len, pieces);
+        for (int v : sub) starts.push_back(a + v);
+    }
+    P.row_kind.assign(n, ROW_COMPACT);
+    for (int i : {0, 1, n - 2, n - 1}) P.row_kind[i] = ROW_WALL;
+    for (size_t q = 1; q < starts.size(); ++q) {
+        const int b = starts[q];
+        for (int e : {b - 1, b})
+            if (P.row_kind[e] == ROW_COMPACT) P.row_kind[e] = ROW_CLOSURE;
+    }
+    int lo = 1;
+    for (int i = 2; i <= n - 2; ++i) {
+        if (P.row_kind[i] != ROW_COMPACT) {
+            if (i - lo >= 2) P.runs.push_back(make_int2(lo, i));
+            lo = i;
+        }
+    }
+    // closure rows of the global C (long double column solves, rounded once)
+    std::vector<int> rows;
+    for (int i = 0; i < n; ++i)
+        if (P.row_kind[i] == ROW_CLOSURE) rows.push_back(i);
+    const int ncl = (int)rows.size();
+    P.cl_row = rows;
+    P.cl_j0.resize(ncl);
+    P.cl_len.resize(ncl);
+    P.cl_coef.assign((size_t)ncl * kTaps, 0.0);
+    if (ncl > 0) {
+        std::vector<long double> col(n), work(2 * (size_t)n);
+        for (int j = 0; j < n; ++j) {
+            bool needed = false;
+            for (int e : rows)
+                if (j >= e - kNb && j <= e + kNb) { needed = true; break; }
+            if (!needed) continue;
+            global_column(n, j, col, work);
+            for (int q = 0; q < ncl; ++q) {
+                const int e = rows[q];
+                if (j < e - kNb || j > e + kNb) continue;
+                const int j0 = e - kNb < 0 ? 0 : e - kNb;
+                P.cl_coef[(size_t)q * kTaps + (j - j0)] = (double)col[e];
+            }
+        }
+        for (int q = 0; q < ncl; ++q) {
+            const int e = rows[q];
+            const int j0 = e - kNb < 0 ? 0 : e - kNb;
+            const int j1 = e + kNb > n - 1 ? n - 1 : e + kNb;
+            P.cl_j0[q] = j0;
+            P.cl_len[q] = j1 - j0 + 1;
+        }
+    }
+    // elimination tables of a constant-coefficient run, indexed by the position
+    // k = 1, 2, ... inside the run (Thomas algorithm, Section 3)
+    P.den.assign(n + 1, 0.0);
+    P.cp.assign(n + 1, 0.0);
+    double cprev = 0.0;
+    for (int k = 1; k <= n; ++k) {
+        const double s = (k > 1) ? kAlpha : 0.0;
+        const double den = 1.0 - s * cprev;
+        P.den[k] = den;
+        P.cp[k] = kAlpha / den;
+        cprev = P.cp[k];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Device cache
+// ---------------------------------------------------------------------------
+namespace {
+struct PlanEntry {
+    void *buf = nullptr;
+    LinePlanDev dev{};
+};
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int, uint64_t>, PlanEntry> g_plans;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
+    int dev = 0;
+    NOPCS_HIP_CHECK(hipGetDevice(&dev));
+    uint64_t lbits;
+    std::memcpy(&lbits, &len, sizeof lbits);
+    const auto key = std::make_tuple(dev, n, nseg, sub_len, lbits);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.dev;
+        return NOPCS_OK;
+    }
+    LinePlanHost P;
+    std::string err;
+    if (!build_line_plan(n, nseg, sub_len, P, err)) {
+        set_error(err);
+        return NOPCS_EINVAL;
+    }
+    const int nrun = (int)P.runs.size(), ncl = (int)P.cl_row.size();
+    // pack everything into one device buffer
+    size_t off = 0;
+    const size_t o_runs = off; off = align256(off + sizeof(int2) * (nrun + 1));
+    const size_t o_row = off;  off = align256(off + sizeof(int) * (ncl + 1));
+    const size_t o_j0 = off;   off = align256(off + sizeof(int) * (ncl + 1));
+    const size_t o_len = off;  off = align256(off + sizeof(int) * (ncl + 1));
+    const size_t o_coef = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
+    const size_t o_c32 = off;  off = align256(off + sizeof(float) * ((size_t)ncl * kTaps + 1));
+    const size_t o_kind = off; off = align256(off + (size_t)n);
+    const size_t o_den = off;  off = align256(off + sizeof(double) * (n + 1));
+    const size_t o_cp = off;   off = align256(off + sizeof(double) * (n + 1));
+    const size_t o_d32 = off;  off = align256(off + sizeof(float) * (n + 1));
+    const size_t o_c32b = off; off = align256(off + sizeof(float) * (n + 1));
+    std::vector<unsigned char> host(off, 0);
+    auto cpy = [&](size_t o, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(host.data() + o, src, bytes);
+    };
+    cpy(o_runs, P.runs.data(), sizeof(int2) * nrun);
+    cpy(o_row, P.cl_row.data(), sizeof(int) * ncl);
+    cpy(o_j0, P.cl_j0.data(), sizeof(int) * ncl);
+    cpy(o_len, P.cl_len.data(), sizeof(int) * ncl);
+    cpy(o_coef, P.cl_coef.data(), sizeof(double) * (size_t)ncl * kTaps);
+    std::vector<float> c32(P.cl_coef.begin(), P.cl_coef.end());
+    cpy(o_c32, c32.data(), sizeof(float) * c32.size());
+    cpy(o_kind, P.row_kind.data(), (size_t)n);
+    cpy(o_den, P.den.data(), sizeof(double) * (n + 1));
+    cpy(o_cp, P.cp.data(), sizeof(double) * (n + 1));
+    std::vector<float> d32(P.den.begin(), P.den.end()), cp32(P.cp.begin(), P.cp.end());
+    cpy(o_d32, d32.data(), sizeof(float) * (n + 1));
+    cpy(o_c32b, cp32.data(), sizeof(float) * (n + 1));
+    void *buf = nullptr;
+    if (hipMalloc(&buf, off) != hipSuccess) {
+        set_error("hipMalloc of a line plan failed");
+        return NOPCS_ENOMEM;
+    }
+    if (hipMemcpy(buf, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(buf);
+        set_error("hipMemcpy of a line plan failed");
+        return NOPCS_EDEVICE;
+    }
+    auto *b = static_cast<unsigned char *>(buf);
+    LinePlanDev d;
+    d.n = n;
+    d.nrun = nrun;
+    d.ncl = ncl;
+    d.ih = (double)(n - 1) / len;
+    d.runs = reinterpret_cast<const int2 *>(b + o_runs);
+    d.cl_row = reinterpret_cast<const int *>(b + o_row);
+    d.cl_j0 = reinterpret_cast<const int *>(b + o_j0);
+    d.cl_len = reinterpret_cast<const int *>(b + o_len);
+    d.cl_coef = reinterpret_cast<const double *>(b + o_coef);
+    d.cl_coef32 = reinterpret_cast<const float *>(b + o_c32);
+    d.row_kind = reinterpret_cast<const uint8_t *>(b + o_kind);
+    d.den = reinterpret_cast<const double *>(b + o_den);
+    d.cp = reinterpret_cast<const double *>(b + o_cp);
+    d.den32 = reinterpret_cast<const float *>(b + o_d32);
+    d.cp32 = reinterpret_cast<const float *>(b + o_c32b);
+    PlanEntry e;
+    e.buf = buf;
+    e.dev = d;
+    g_plans[key] = e;
+    *out = d;
+    return NOPCS_OK;
+}
+
+void release_line_plans() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::get<0>(it->first) == dev) {
+            (void)hipFree(it->second.buf);
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace nopcs

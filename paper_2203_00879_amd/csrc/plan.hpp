@@ -1,0 +1,58 @@
+// plan.hpp -- per-line-length plans of the NOHAP segmented compact solve.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace nopcs {
+
+// Row kinds of one line.
+enum : uint8_t { ROW_COMPACT = 0, ROW_WALL = 1, ROW_CLOSURE = 2 };
+
+// Device view of a line plan (passed by value to kernels).
+struct LinePlanDev {
+    int n;                 // points on the line
+    int nrun;              // Thomas runs (maximal sets of compact rows between known rows)
+    int ncl;               // closure rows
+    double ih;             // 1/h
+    const int2 *runs;      // [nrun] (lo, hi): known rows bounding the run; unknowns lo+1..hi-1
+    const int *cl_row;     // [ncl] row index e of each closure
+    const int *cl_j0;      // [ncl] first tap column
+    const int *cl_len;     // [ncl] number of taps (<= 97)
+    const double *cl_coef; // [ncl][97] coefficients C_{e,j} * h, taps j0 .. j0+len-1
+    const float *cl_coef32;// [ncl][97] the same rounded to FP32 (mixed precision)
+    const uint8_t *row_kind;  // [n]
+    const double *den;     // [n] elimination pivots 1 - alpha c'_{k-1}, k = 1.. (index k)
+    const double *cp;      // [n] c'_k = alpha / den_k
+    const float *den32;    // FP32 copies
+    const float *cp32;
+};
+
+// Host description (kept for tests and for building the device copy).
+struct LinePlanHost {
+    int n = 0, nseg = 0, sub_len = 0;
+    std::vector<int> seg_lo;          // user segment starts
+    std::vector<int2> runs;
+    std::vector<int> cl_row, cl_j0, cl_len;
+    std::vector<double> cl_coef;      // ncl * kTaps
+    std::vector<uint8_t> row_kind;
+    std::vector<double> den, cp;
+};
+
+// Build the plan of a line of n points cut into nseg user segments; each user
+// segment is further cut into pieces of at most sub_len points (0 = no extra cuts).
+// Returns false with an error message on invalid input.
+bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &out, std::string &err);
+
+// Segment starts of an even split (the first n % nseg segments one point longer).
+std::vector<int> even_segments(int n, int nseg);
+
+// Cached device plan for (device, n, nseg, sub_len, len) -> LinePlanDev.
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out);
+
+// Free all cached device plans of the current device.
+void release_line_plans();
+
+}  // namespace nopcs

@@ -93,11 +93,13 @@ def fourier_modes(nmodes=16, kmax=64, seed=1):
     return modes
 
 
-def fourier_field(n, modes, which=None, length=1.0, dtype=np.float64):
+def fourier_field(n, modes, which=None, length=1.0, dtype=np.float64, factor=None):
     """f = sum_m a_m cos(2 pi (kx x + ky y + kz z) + phi_m) on nodes x_i = i len/(n-1).
 
     which: None for f; (d, 1) or (d, 2) for the analytic first or second
-    derivative along d (0 = x, 1 = y, 2 = z).  Returns an array [nz, ny, nx].
+    derivative along d (0 = x, 1 = y, 2 = z).  factor: optional function of the
+    angular wavenumber w = 2 pi k_d that replaces w in the derivative (a Fourier
+    multiplier).  Returns an array [nz, ny, nx].
     """
     nx, ny, nz = (n, n, n) if np.isscalar(n) else n
     lx, ly, lz = (length,) * 3 if np.isscalar(length) else length
@@ -117,6 +119,8 @@ def fourier_field(n, modes, which=None, length=1.0, dtype=np.float64):
         else:
             d, order = which
             w = 2.0 * math.pi * k[d]
+            if factor is not None:
+                w = factor(w)
             if order == 1:
                 out += -a * w * e.imag
             else:
@@ -152,3 +156,38 @@ def stable_dt(n, T_max_K, params=AIR, length=1.0):
     nu = ((4.0 / 3.0) * mu_dim / mu_s + beta) / (rho_min * Re)
     dt_v = 2.785 * h * h / (3.0 * nu) if params.get("viscous", 1) else float("inf")
     return 0.5 * min(dt_ac, dt_v)
+
+
+def smooth_state(n, seed=0, amp_rho=0.2, amp_u=0.05, amp_p=0.5, kmax=3, params=AIR, length=1.0):
+    """Smooth random state from (rho, u, v, w, p') built of a few low Fourier modes.
+
+    rho = 1 + amp_rho s0, velocities amp_u s1..s3, p' = amp_p s4 with s_m smooth
+    fields of unit scale; E' = p'/(gamma - 1) + rho |V|^2 / 2.  Returns Q[5, nz, ny, nx].
+    """
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    lx, ly, lz = (length,) * 3 if np.isscalar(length) else length
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx) * (lx / (nx - 1))
+    y = np.arange(ny) * (ly / (ny - 1))
+    z = np.arange(nz) * (lz / (nz - 1))
+
+    def field():
+        out = np.zeros((nz, ny, nx))
+        for _ in range(3):
+            k = rng.integers(0, kmax + 1, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            a = rng.uniform(-1, 1) / 3.0
+            out += a * (np.cos(2 * math.pi * k[2] * z + ph[2])[:, None, None]
+                        * np.cos(2 * math.pi * k[1] * y + ph[1])[None, :, None]
+                        * np.cos(2 * math.pi * k[0] * x + ph[0])[None, None, :])
+        return out
+
+    rho = 1.0 + amp_rho * field()
+    vel = [amp_u * field() for _ in range(3)]
+    pp = amp_p * field()
+    Q = np.empty((5, nz, ny, nx))
+    Q[0] = rho
+    for d in range(3):
+        Q[1 + d] = rho * vel[d]
+    Q[4] = pp / (params["gamma"] - 1.0) + 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)
+    return Q

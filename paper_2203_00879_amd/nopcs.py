@@ -1,0 +1,159 @@
+"""Thin ctypes binding of libnopcs.so (declared in include/nopcs.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch provides device memory (tensor.data_ptr()) and streams
+(torch.cuda.current_stream().cuda_stream).  There is no CPU fallback: if the
+library cannot be loaded the import of the first call raises.
+"""
+import ctypes
+import os
+
+from . import build as _build
+
+NOPCS_OK = 0
+NOPCS_EINVAL = -1
+NOPCS_ENOMEM = -2
+NOPCS_EDEVICE = -3
+NOPCS_EAGAIN = -4
+NOPCS_ENOTFOUND = -5
+NOPCS_ENONFINITE = -6
+NOPCS_EBUSY = -7
+FP64 = 0
+MIXED = 1
+
+_ERRNAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EAGAIN", -5: "ENOTFOUND",
+             -6: "ENONFINITE", -7: "EBUSY"}
+
+
+class NopcsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("len", ctypes.c_double * 3), ("nseg", ctypes.c_int32 * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("gamma", "R_gas", "g", "L", "T_s", "rho_s", "Pr", "mu_ref", "T_ref", "S_suth", "mub_a", "mub_b")] + \
+               [("viscous", ctypes.c_int32), ("gravity", ctypes.c_int32)]
+
+
+class SolverConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class SolveRequest(ctypes.Structure):
+    _fields_ = [("params", Params), ("grid", Grid), ("nsteps", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("Q0_host", ctypes.c_void_p)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("steps_done", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+_lib = None
+_V = ctypes.c_void_p
+_I = ctypes.c_int
+
+
+def library_path():
+    return _build.LIB
+
+
+def lib():
+    """Load libnopcs.so (built in-tree; built once if missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.nopcs_last_error.restype = ctypes.c_char_p
+        L.nopcs_version.restype = _I
+        L.nopcs_release_plans.restype = _I
+        L.nopcs_workspace_bytes.restype = ctypes.c_size_t
+        L.nopcs_workspace_bytes.argtypes = [ctypes.POINTER(Grid), _I]
+        L.nopcs_derivative.argtypes = [ctypes.POINTER(Grid), _I, _I, _V, _V, _V, _V]
+        L.nse_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V, ctypes.c_size_t, _V]
+        L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
+                              _V, ctypes.c_size_t, _V]
+        if hasattr(L, "solver_create"):
+            L.solver_create.argtypes = [ctypes.POINTER(SolverConfig), ctypes.POINTER(_V)]
+            L.solver_submit.argtypes = [_V, ctypes.POINTER(SolveRequest), ctypes.POINTER(ctypes.c_uint64)]
+            L.solver_poll.argtypes = [_V, ctypes.c_uint64, _V, ctypes.POINTER(SolveResult)]
+            L.solver_destroy.argtypes = [_V]
+            L.solver_now.argtypes = [_V]
+            L.solver_now.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().nopcs_last_error().decode()
+
+
+def _check(rc):
+    if rc != NOPCS_OK:
+        raise NopcsError(rc, last_error())
+    return rc
+
+
+def make_grid(n, nseg=1, length=1.0):
+    n3 = (n, n, n) if isinstance(n, int) else tuple(n)
+    s3 = (nseg, nseg, nseg) if isinstance(nseg, int) else tuple(nseg)
+    l3 = (length,) * 3 if isinstance(length, (int, float)) else tuple(length)
+    g = Grid()
+    for d in range(3):
+        g.n[d] = int(n3[d])
+        g.nseg[d] = int(s3[d])
+        g.len[d] = float(l3[d])
+    return g
+
+
+def make_params(d):
+    return Params(**{k: d[k] for k, _ in Params._fields_})
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def workspace_bytes(grid, precision=FP64):
+    return lib().nopcs_workspace_bytes(ctypes.byref(grid), precision)
+
+
+def nopcs_derivative(grid, direction, f, d1=None, d2=None, precision=FP64, stream=None):
+    """D1 and/or D2 of a device field f (float64 tensor of n0*n1*n2 elements)."""
+    _check(lib().nopcs_derivative(ctypes.byref(grid), int(direction), int(precision), _ptr(f), _ptr(d1), _ptr(d2),
+                                  _stream(stream)))
+
+
+def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(lib().nse_rhs(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(R), _ptr(ws),
+                         nbytes, _stream(stream)))
+
+
+def rk_step(params, grid, Q, dt, nsteps, ws, precision=FP64, stream=None):
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().rk_step(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), float(dt), int(nsteps),
+                         _ptr(ws), nbytes, _stream(stream)))
+
+
+def alloc_workspace(grid, precision=FP64, device="cuda"):
+    import torch
+    nb = workspace_bytes(grid, precision)
+    if nb == 0:
+        raise NopcsError(NOPCS_EINVAL, last_error())
+    return torch.empty(nb, dtype=torch.uint8, device=device)
