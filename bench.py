@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the NOHAP/OUCS3 compressible-NSE hot path on one MI355X.
+
+One "step" = one classical RK4 time step (4 stages) of the whole path: viscous
+fluxes + gravity, NOHAP compact convective derivatives along x, y, z, the RK4
+register update and the wall conditions, on a Rayleigh-Taylor box resident in
+HBM (synthetic, seeded).  Default workload: 512^3 points, FP64, 4 segments per
+direction, dt = 1e-6.
+
+Prints ONE JSON line:
+  metric/value/unit : Mpoint-stage updates/s (points x 4 stages x steps / s / 1e6)
+  roofline          : dominant kernel, algorithmic bytes per launch / its mean
+                      duration (HIP events on its stream, over the timed region)
+  cpu_baseline      : the FP64 oracle timed on the host cores on a bounded sample
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+
+KERNEL_NAMES = ["viscous", "sweep_x", "sweep_y", "sweep_z", "wall", "derivative", "rk_update"]
+KERNEL_SOURCES = {
+    "viscous": ["visc.hip", "common.hpp", "kernels.hpp"],
+    "sweep_x": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
+    "sweep_y": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
+    "sweep_z": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
+    "rk_update": ["sweep.hip"],
+    "wall": ["visc.hip", "common.hpp"],
+}
+
+
+def kernel_bytes_per_point(name, precision):
+    """Compulsory HBM bytes per grid point of one launch (each operand read or written once)."""
+    w = 8  # FP64
+    if name == "viscous":
+        return 5 * w + 5 * w                       # read stage state, write R
+    if name in ("sweep_x", "sweep_y", "sweep_z"):
+        return 5 * w + 5 * w + 5 * w               # read state, read R, write R
+    if name == "rk_update":
+        # stage 0: R, Qn -> K, Qs; stages 1, 2: R, Qn, K -> K, Qs; stage 3: R, Qn, K -> Qn
+        return (4 * 5 * w + 2 * 5 * 5 * w + 4 * 5 * w) / 4.0
+    return 0.0
+
+
+def source_hash(name):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(name, []):
+        p = os.path.join(ROOT, "paper_2203_00879_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name, workload_key):
+    """HBM bytes per launch from committed counter runs, if taken on the current source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        rec = d.get(workload_key, {}).get(name)
+        if rec and rec.get("source_hash") == source_hash(name):
+            return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(n=128, steps=1):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_2203_00879_amd import inputs
+    p = dict(inputs.AIR)
+    Q = inputs.rti_state(n, seed=0)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.rk4(p, Q, 1e-6, steps)
+    dt = time.perf_counter() - t0
+    pts = n ** 3 * 4 * steps
+    return {"value": pts / dt / 1e6, "unit": "Mpoint-stage/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "RTI box %d^3, %d RK4 step(s) (%d stages), FP64 oracle, %.1f s" % (n, steps, 4 * steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nseg", type=int, default=4)
+    ap.add_argument("--dt", type=float, default=1e-6)
+    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=192)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=float, default=0.0,
+                    help="GiB: run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (one box = one MI355X); "
+              "--gpus %d is not supported." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_00879_amd import inputs, nopcs
+
+    dev = "cuda:0"
+    if args.calibrate_copy > 0:
+        nb = int(args.calibrate_copy * (1 << 30)) // 8
+        a = torch.ones(nb, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    n = args.n
+    p = dict(inputs.AIR)
+    grid = nopcs.make_grid(n, args.nseg)
+    params = nopcs.make_params(p)
+    Q0 = inputs.rti_state(n, seed=0)
+    Q = torch.from_numpy(Q0).to(dev)
+    del Q0
+    ws = nopcs.alloc_workspace(grid)
+    stream = torch.cuda.current_stream()
+    lib = nopcs.lib()
+
+    nopcs.rk_step(params, grid, Q, args.dt, args.warmup, ws)
+    torch.cuda.synchronize()
+
+    import ctypes
+    lib.nopcs_timing_enable.argtypes = [ctypes.c_int]
+    lib.nopcs_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.nopcs_timing_enable(1)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    nopcs.rk_step(params, grid, Q, args.dt, args.steps, ws)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.nopcs_timing_enable(0)
+    ms = start.elapsed_time(stop)
+    sec = ms / 1e3
+
+    per = {}
+    for k, name in enumerate(KERNEL_NAMES):
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        nopcs._check(lib.nopcs_timing_read(k, ctypes.byref(tot), ctypes.byref(cnt)))
+        if cnt.value:
+            per[name] = (tot.value, cnt.value)
+    finite = bool(torch.isfinite(Q).all().item())
+
+    N3 = n ** 3
+    pstage = N3 * 4 * args.steps
+    value = pstage / sec / 1e6
+    dom = max((k for k in per if k in KERNEL_SOURCES and kernel_bytes_per_point(k, "fp64") > 0),
+              key=lambda k: per[k][0])
+    tot_ms, cnt = per[dom]
+    avg_s = tot_ms / cnt / 1e3
+    bpl = kernel_bytes_per_point(dom, "fp64") * N3
+    achieved = bpl / avg_s / 1e9
+    workload_key = "rti_%d_fp64_seg%d" % (n, args.nseg)
+    traffic = load_traffic(dom, workload_key)
+    kernels = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
+                   "alg_GBps": (kernel_bytes_per_point(k, "fp64") * N3 / (v[0] / v[1] / 1e3) / 1e9)
+                   if kernel_bytes_per_point(k, "fp64") else None} for k, v in per.items()}
+    out = {
+        "metric": "Mpoint-stage updates/s (512^3 FP64 RK4 stepping)",
+        "value": value,
+        "unit": "Mpoint-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Rayleigh-Taylor box %d^3, FP64, %d segments/direction, RK4 dt=%g, seeded "
+                               "interface noise" % (n, args.nseg, args.dt),
+                   "points": N3, "segments_per_direction": args.nseg, "precision": "fp64"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": bpl, "mean_launch_ms": avg_s * 1e3},
+        "step_algorithmic_frac": 170.0 * pstage / sec / 1e9 / HBM_PEAK_GBS,
+        "kernels": kernels,
+        "finite": finite,
+        "wall_s": wall,
+        "paper_context": {"Mpoint_stage_per_s": 19700.0,
+                          "hardware": "19,200 Haswell cores, 4.19e9 points, FP64 (paper, other machine)"},
+    }
+    if not args.no_cpu_baseline:
+        del ws
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,30 @@ int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, con
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
             void *ws, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (instrumentation).                                           */
+/* ------------------------------------------------------------------------ */
+enum {
+    NOPCS_K_VISCOUS = 0,  /* viscous fluxes + gravity source (writes R)          */
+    NOPCS_K_SWEEP_X = 1,  /* convective x sweep (R -= D_x E)                      */
+    NOPCS_K_SWEEP_Y = 2,  /* convective y sweep (R -= D_y F)                      */
+    NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G)                      */
+    NOPCS_K_WALL = 4,     /* wall conditions (one launch per face pair)          */
+    NOPCS_K_DERIV = 5,    /* standalone derivative                                */
+    NOPCS_K_RK = 6,       /* RK4 register update of one stage                     */
+    NOPCS_K_COUNT = 7
+};
+
+/* on != 0: from now on every kernel launched by this library is bracketed by a
+ * pair of HIP events recorded on the stream it is launched on; previous records
+ * and totals are cleared.  on == 0 stops recording (totals are kept). */
+int nopcs_timing_enable(int on);
+
+/* Per-kernel totals of the recorded launches: waits for the recorded events,
+ * adds their durations and returns the totals since the last enable.
+ * kernel: one of NOPCS_K_*; total_ms, launches may be NULL. */
+int nopcs_timing_read(int32_t kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -719,3 +719,7 @@ void ora_rhs_points(const ora_params *p, const int n[3], const double len[3], co
         free(F); free(DF); free(work);
     }
 }
+
+/* Number of OpenMP threads a parallel region of the oracle uses. */
+#include <omp.h>
+int ora_num_threads(void) { return omp_get_max_threads(); }

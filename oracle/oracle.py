@@ -20,7 +20,7 @@ _lib = None
 __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
-    "scales", "segment_starts",
+    "scales", "segment_starts", "num_threads",
 ]
 
 
@@ -74,6 +74,7 @@ def lib():
         L.ora_rk4_linear.argtypes = [_D, _D, _D, _I]
         L.ora_rk4_linear.restype = _D
         L.ora_scales.argtypes = [ctypes.POINTER(OraParams), _P]
+        L.ora_num_threads.restype = _I
         _lib = L
     return _lib
 
@@ -220,6 +221,11 @@ def rk4(params, Q, dt, nsteps, length=1.0):
 
 def rk4_linear(q0, lam, dt, nsteps):
     return lib().ora_rk4_linear(float(q0), float(lam), float(dt), int(nsteps))
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().ora_num_threads()
 
 
 def scales(params):

@@ -1,6 +1,8 @@
 // api.hip -- C ABI entry points of libnopcs (declared in include/nopcs.h).
 #include <cmath>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -19,13 +21,7 @@ static int g_piece_len[3] = {-1, -1, -1};
 
 int piece_length(int dir, int n) {
     if (g_piece_len[dir] >= 0) return g_piece_len[dir];
-    if (n <= 64) return 0;
-    const int P = sweep_lines_per_block(dir, n), NT = sweep_threads_per_block(dir, n);
-    // runs needed so that P * runs >= NT / 2
-    const int runs = (NT / 2 + P - 1) / P;
-    int len = n / (runs > 0 ? runs : 1);
-    if (len < 12) len = 12;
-    return len;
+    return n <= 64 ? 0 : 32;
 }
 
 static bool check_grid(const nopcs_grid *g) {
@@ -67,9 +63,9 @@ static int get_plans(const nopcs_grid *g, LinePlanDev pl[3]) {
     for (int d = 0; d < 3; ++d) {
         const int rc = get_line_plan(g->n[d], g->nseg[d], piece_length(d, g->n[d]), g->len[d], &pl[d]);
         if (rc != NOPCS_OK) return rc;
-        const int P = sweep_lines_per_block(d, g->n[d]), NT = sweep_threads_per_block(d, g->n[d]);
-        if ((long long)P * pl[d].ncl > 4LL * NT) {
-            set_error("too many closure rows for one pencil (shorten the segment count)");
+        if (4 + pl[d].ncl > sweep_known_rows_max(g->n[d])) {
+            set_error("too many segments along direction " + std::to_string(d) + " for " +
+                      std::to_string(g->n[d]) + " points");
             return NOPCS_EINVAL;
         }
     }
@@ -77,6 +73,59 @@ static int get_plans(const nopcs_grid *g, LinePlanDev pl[3]) {
 }
 
 static size_t field_elems(const nopcs_grid *g) { return (size_t)g->n[0] * g->n[1] * g->n[2]; }
+
+// ---------------------------------------------------------------------------
+// Event timing of kernel launches (instrumentation only).
+// ---------------------------------------------------------------------------
+namespace {
+struct TimingRec {
+    int id;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+double g_total_ms[NOPCS_K_COUNT];
+long long g_launches[NOPCS_K_COUNT];
+
+int drain_timing() {
+    for (auto &r : g_recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            set_error("timing event query failed");
+            return NOPCS_EDEVICE;
+        }
+        g_total_ms[r.id] += ms;
+        g_launches[r.id] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_recs.clear();
+    return NOPCS_OK;
+}
+}  // namespace
+
+// Launch through f() bracketed by events when timing is on.
+template <class F>
+static hipError_t timed(int id, hipStream_t st, F &&f) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        on = g_timing;
+    }
+    if (!on) return f();
+    TimingRec r{id, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&r.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&r.b);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(r.a, st)) != hipSuccess) return e;
+    if ((e = f()) != hipSuccess) return e;
+    if ((e = hipEventRecord(r.b, st)) != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_recs.push_back(r);
+    return hipSuccess;
+}
 
 }  // namespace nopcs
 
@@ -137,7 +186,8 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
     const SweepGeom g = sweep_geom(grid->n, dir);
-    NOPCS_HIP_CHECK(launch_deriv(dir, f, d1, d2, g, pl[dir], (hipStream_t)hip_stream));
+    NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, (hipStream_t)hip_stream,
+                          [&] { return launch_deriv(dir, f, d1, d2, g, pl[dir], (hipStream_t)hip_stream); }));
     return NOPCS_OK;
 }
 
@@ -145,14 +195,15 @@ static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev 
                     hipStream_t st) {
     double ih[3];
     for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
-    NOPCS_HIP_CHECK(launch_visc(Q, R, grid->n, ih, c, st));
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, grid->n, ih, c, st); }));
     NseSweepArgs a{};
     a.Qin = Q;
     a.R = R;
     a.N3 = (long long)field_elems(grid);
     a.c = c;
     for (int d = 0; d < 3; ++d)
-        NOPCS_HIP_CHECK(launch_nse_sweep(d, MODE_ACCUM, a, sweep_geom(grid->n, d), pl[d], st));
+        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
+                              [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl[d], st); }));
     return NOPCS_OK;
 }
 
@@ -209,14 +260,44 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
             const double *Qin = stage == 0 ? Q : Qs;
             a.Qin = Qin;
             a.stage = stage;
-            NOPCS_HIP_CHECK(launch_visc(Qin, R, grid->n, ih, c, st));
-            NOPCS_HIP_CHECK(launch_nse_sweep(0, MODE_ACCUM, a, sweep_geom(grid->n, 0), pl[0], st));
-            NOPCS_HIP_CHECK(launch_nse_sweep(1, MODE_ACCUM, a, sweep_geom(grid->n, 1), pl[1], st));
-            NOPCS_HIP_CHECK(launch_nse_sweep(2, MODE_RK, a, sweep_geom(grid->n, 2), pl[2], st));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, grid->n, ih, c, st); }));
+            for (int d = 0; d < 3; ++d)
+                NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
+                                      [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl[d], st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
             double *Qout = stage < 3 ? Qs : Q;
-            for (int d = 0; d < 3; ++d) NOPCS_HIP_CHECK(launch_bc(Qout, grid->n, d, c, st));
+            for (int d = 0; d < 3; ++d)
+                NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
         }
     }
+    return NOPCS_OK;
+}
+
+int nopcs_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (on) {
+        for (auto &r : g_recs) {
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        g_recs.clear();
+        for (int k = 0; k < NOPCS_K_COUNT; ++k) {
+            g_total_ms[k] = 0.0;
+            g_launches[k] = 0;
+        }
+    }
+    g_timing = on != 0;
+    return NOPCS_OK;
+}
+
+int nopcs_timing_read(int32_t kernel, double *total_ms, int64_t *launches) {
+    if (kernel < 0 || kernel >= NOPCS_K_COUNT) { set_error("unknown kernel id"); return NOPCS_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_tmu);
+    const int rc = drain_timing();
+    if (rc != NOPCS_OK) return rc;
+    if (total_ms) *total_ms = g_total_ms[kernel];
+    if (launches) *launches = g_launches[kernel];
     return NOPCS_OK;
 }
 

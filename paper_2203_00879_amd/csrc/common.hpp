@@ -11,6 +11,25 @@
 
 #include "../../include/nopcs.h"
 
+// LDS index checks: nothing on the GPU; abort in the host (CPU) build of the
+// kernels that the test-suite runs under AddressSanitizer.
+#ifdef NOPCS_CPU_EMUL
+#include <cstdio>
+#include <cstdlib>
+#define NOPCS_LDS_BOUND(i, n)                                                                         \
+    do {                                                                                              \
+        if ((long long)(i) < 0 || (long long)(i) >= (long long)(n)) {                                 \
+            std::fprintf(stderr, "LDS index %lld outside [0, %lld) at %s:%d\n", (long long)(i),       \
+                         (long long)(n), __FILE__, __LINE__);                                         \
+            std::abort();                                                                             \
+        }                                                                                             \
+    } while (0)
+#else
+#define NOPCS_LDS_BOUND(i, n) \
+    do {                      \
+    } while (0)
+#endif
+
 namespace nopcs {
 
 // OUCS3 scheme with eta = 0 (Section 3, entries of A and B after Eq. CS:AfpBf):

@@ -7,8 +7,6 @@
 
 namespace nopcs {
 
-enum { MODE_ACCUM = 0, MODE_RK = 1 };
-
 struct NseSweepArgs {
     const double *Qin;  // stage input state (5 fields)
     double *R;          // right-hand side accumulator (5 fields)
@@ -24,11 +22,16 @@ struct NseSweepArgs {
 int nmax_class(int n);
 int sweep_lines_per_block(int dir, int n);
 int sweep_threads_per_block(int dir, int n);
+int sweep_known_rows_max(int n);
 
 hipError_t launch_deriv(int dir, const double *f, double *d1, double *d2, const SweepGeom &g, const LinePlanDev &pl,
                         hipStream_t st);
-hipError_t launch_nse_sweep(int dir, int mode, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
+// R <- R - D_dir(convective flux) for the 5 components (one launch per direction)
+hipError_t launch_nse_sweep(int dir, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
                             hipStream_t st);
+
+// RK4 register update of stage a.stage from R (point-wise over 5 fields)
+hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st);
 
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, double *R, const int n[3], const double ih[3], const NdConst &c,

@@ -150,6 +150,14 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
             P.cl_len[q] = j1 - j0 + 1;
         }
     }
+    // known-row slots: 0..3 for rows 0, 1, n-2, n-1; 4 + q for closure q
+    P.kslot.assign(n, (short)-1);
+    P.kslot[0] = 0;
+    P.kslot[1] = 1;
+    P.kslot[n - 2] = 2;
+    P.kslot[n - 1] = 3;
+    for (int q = 0; q < ncl; ++q) P.kslot[rows[q]] = (short)(4 + q);
+    for (const int2 &r : P.runs) P.run_slot.push_back(make_int2(P.kslot[r.x], P.kslot[r.y]));
     // elimination tables of a constant-coefficient run, indexed by the position
     // k = 1, 2, ... inside the run (Thomas algorithm, Section 3)
     P.den.assign(n + 1, 0.0);
@@ -201,6 +209,8 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     // pack everything into one device buffer
     size_t off = 0;
     const size_t o_runs = off; off = align256(off + sizeof(int2) * (nrun + 1));
+    const size_t o_rslot = off; off = align256(off + sizeof(int2) * (nrun + 1));
+    const size_t o_kslot = off; off = align256(off + sizeof(short) * (n + 1));
     const size_t o_row = off;  off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_j0 = off;   off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_len = off;  off = align256(off + sizeof(int) * (ncl + 1));
@@ -216,6 +226,8 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
         if (bytes) std::memcpy(host.data() + o, src, bytes);
     };
     cpy(o_runs, P.runs.data(), sizeof(int2) * nrun);
+    cpy(o_rslot, P.run_slot.data(), sizeof(int2) * nrun);
+    cpy(o_kslot, P.kslot.data(), sizeof(short) * n);
     cpy(o_row, P.cl_row.data(), sizeof(int) * ncl);
     cpy(o_j0, P.cl_j0.data(), sizeof(int) * ncl);
     cpy(o_len, P.cl_len.data(), sizeof(int) * ncl);
@@ -245,6 +257,8 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.ncl = ncl;
     d.ih = (double)(n - 1) / len;
     d.runs = reinterpret_cast<const int2 *>(b + o_runs);
+    d.run_slot = reinterpret_cast<const int2 *>(b + o_rslot);
+    d.kslot = reinterpret_cast<const short *>(b + o_kslot);
     d.cl_row = reinterpret_cast<const int *>(b + o_row);
     d.cl_j0 = reinterpret_cast<const int *>(b + o_j0);
     d.cl_len = reinterpret_cast<const int *>(b + o_len);

@@ -18,6 +18,9 @@ struct LinePlanDev {
     int ncl;               // closure rows
     double ih;             // 1/h
     const int2 *runs;      // [nrun] (lo, hi): known rows bounding the run; unknowns lo+1..hi-1
+    const int2 *run_slot;  // [nrun] known-row slots of lo and hi
+    const short *kslot;    // [n] known-row slot of each row (-1: compact row); slots 0..3 are the
+                           // wall rows 0, 1, n-2, n-1, slot 4 + q is closure q
     const int *cl_row;     // [ncl] row index e of each closure
     const int *cl_j0;      // [ncl] first tap column
     const int *cl_len;     // [ncl] number of taps (<= 97)
@@ -34,7 +37,8 @@ struct LinePlanDev {
 struct LinePlanHost {
     int n = 0, nseg = 0, sub_len = 0;
     std::vector<int> seg_lo;          // user segment starts
-    std::vector<int2> runs;
+    std::vector<int2> runs, run_slot;
+    std::vector<short> kslot;
     std::vector<int> cl_row, cl_j0, cl_len;
     std::vector<double> cl_coef;      // ncl * kTaps
     std::vector<uint8_t> row_kind;

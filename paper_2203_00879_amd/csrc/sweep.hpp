@@ -1,17 +1,21 @@
 // sweep.hpp -- LDS-staged pencil sweeps of the NOHAP compact first derivative.
 //
-// A workgroup stages a pencil of P lines (full length along the sweep
-// direction) of one field in LDS and evaluates the segmented compact solve
-// there (Section 3):
-//   A: every thread forms (B f)_i for the compact rows it owns and the explicit
-//      wall rows; closure threads form the truncated equivalent explicit sums
-//      f'_e = sum_j C_{e,j} (f_j - f_e) / h of the segment ends (Eq. CS:fpCf_i,
-//      global rows of C; the f_e shift is exact for the untruncated row and
-//      makes constant fields differentiate to exactly zero);
-//   B: results written back in place;
-//   C: one thread per (line, run) runs the Thomas algorithm with tabulated
-//      pivots on the compact rows between two known rows.
-// Lines along x are contiguous in HBM, lines along y and z are gathered P at a
+// A workgroup stages a pencil of P full lines along the sweep direction, for up
+// to G field components at once, in LDS and evaluates the segmented compact
+// solve of Section 3 there, in three phases separated by barriers:
+//   A  known rows: the explicit wall rows and the segment-end (closure) rows
+//      f'_e = sum_j C_{e,j} (f_j - f_e) / h with C the global A^-1 B truncated
+//      to |j - e| <= 48 (Eqs. CS:fpCf, CS:fpCf_i; the f_e shift is exact for the
+//      untruncated row and makes constant fields differentiate to exactly 0).
+//      Results go to a side array KN, so known rows of F keep their f values.
+//   C  one thread per (line, run) -- a run is the set of compact rows between
+//      two known rows -- forms (B f)_i from a five-point register window and
+//      runs the Thomas algorithm (tabulated pivots) with the known rows as
+//      boundary values, overwriting the run's rows of F with f'.  The rows just
+//      outside a run are known rows and are never overwritten, so runs need no
+//      halo exchange.
+//   E  owned points read f' (from F or KN) and apply the caller's epilogue.
+// Lines along x are contiguous in HBM; lines along y and z are gathered P at a
 // time from neighbouring x positions so every HBM access is a coalesced row.
 #pragma once
 
@@ -22,20 +26,34 @@ namespace nopcs {
 
 template <int DIR, int NMAX>
 struct SweepCfg {
-    static constexpr int P = DIR == 0 ? (NMAX <= 128 ? 16 : 2048 / NMAX) : (NMAX <= 256 ? 16 : 4096 / NMAX);
-    static constexpr int NT = DIR == 0 ? 256 : (NMAX <= 64 ? 128 : NMAX <= 128 ? 256 : 512);
-    static constexpr int PTS = (P * NMAX + NT - 1) / NT;   // points owned per thread
-    static constexpr int CLPT = 4;                          // closures per thread (max)
-    static constexpr int PITCH = NMAX + NMAX / 16 + 1;      // x layout: padded line pitch
-    static constexpr int LDS = DIR == 0 ? P * PITCH : NMAX * P;
-    __device__ static int idx(int l, int i) {
-        if (DIR == 0) return l * PITCH + i + (i >> 4);
-        return i * P + l;
+    // lines per pencil: every configuration keeps the block within 64 KB of LDS
+    static constexpr int P = NMAX <= 128 ? 1024 / NMAX : 2048 / NMAX;
+    static constexpr int NT = 256;                                   // threads per block
+    static constexpr int PTS = (P * NMAX) / NT;                      // owned slots per thread
+    static constexpr int G = 3;                                      // components per LDS pass
+    static constexpr int KMAX = NMAX <= 128 ? NMAX / 2 + 4 : NMAX / 8 + 8;
+    static constexpr int PAD = (NMAX >> 5) * 2 + 2;
+    static constexpr int PITCH = NMAX + PAD + 1;                     // x layout line pitch
+    static constexpr int FSZ = DIR == 0 ? P * PITCH : NMAX * P + PAD;
+    // LDS index of (line l, position i) inside one component buffer; the
+    // 2-double step every 32 positions spreads concurrent runs over the banks
+    __device__ static int fidx(int l, int i) {
+        const int ix = DIR == 0 ? l * PITCH + i + ((i >> 5) << 1) : i * P + l + ((i >> 5) << 1);
+        NOPCS_LDS_BOUND(l, P);
+        NOPCS_LDS_BOUND(i, NMAX);
+        NOPCS_LDS_BOUND(ix, FSZ);
+        return ix;
     }
-    // owned point s of thread t: pencil-local (line, position)
-    __device__ static void owned(int q, int n, int &l, int &i) {
-        if (DIR == 0) { l = q / n; i = q - l * n; }
-        else { i = q / P; l = q - i * P; }
+    // index of (known-row slot s, line l) inside one component of KN
+    __device__ static int kidx(int s, int l) {
+        NOPCS_LDS_BOUND(s, KMAX);
+        NOPCS_LDS_BOUND(l, P);
+        return s * P + l;
+    }
+    // owned slot q -> (line, position); valid when l < lines and i < n
+    __device__ static void owned(int q, int &l, int &i) {
+        if (DIR == 0) { l = q / NMAX; i = q % NMAX; }
+        else { l = q % P; i = q / P; }
     }
 };
 
@@ -56,107 +74,124 @@ inline SweepGeom sweep_geom(const int n[3], int dir) {
     return g;
 }
 
-// Segmented compact solve of the P staged lines in F (FP64).  All threads of
-// the block must call it; it ends with a barrier and leaves f' in F.
-template <int DIR, int NMAX>
-__device__ inline void lds_line_solve(double *F, const LinePlanDev &pl, int np) {
+// Phases A and C for NC components staged in F[c] (FP64).  Known-row values
+// land in KN(c)[slot * P + l].  All threads of the block call it; it ends with
+// a barrier; f' is then in F (compact rows) and KN (known rows).
+template <int DIR, int NMAX, int NC>
+__device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev &pl, int np) {
     using C = SweepCfg<DIR, NMAX>;
+    constexpr int KS = C::P * C::KMAX;
+    auto F = [&](int c) -> double * { return Fb + c * C::FSZ; };
+    auto KN = [&](int c) -> double * { return KNb + c * KS; };
     const int tid = threadIdx.x;
     const int n = pl.n;
     const double ih = pl.ih;
-    double dreg[C::PTS];
-    double creg[C::CLPT];
-    // ---- A: explicit parts, reading F ----
+    // ---- A: known rows (walls and closures) ----
+    const int nk = 4 + pl.ncl;
+    for (int q = tid; q < C::P * nk; q += C::NT) {
+        const int l = q % C::P, s = q / C::P;
+        if (l >= np) continue;
+        if (s < 4) {
 #pragma unroll
-    for (int s = 0; s < C::PTS; ++s) {
-        const int q = tid + s * C::NT;
-        dreg[s] = 0.0;
-        if (q < C::P * n) {
-            int l, i;
-            C::owned(q, n, l, i);
-            if (l < np) {
-                const uint8_t kind = pl.row_kind[i];
-                if (kind == ROW_COMPACT) {
-                    dreg[s] = ih * (kB1 * (F[C::idx(l, i + 1)] - F[C::idx(l, i - 1)]) +
-                                    kB2 * (F[C::idx(l, i + 2)] - F[C::idx(l, i - 2)]));
-                } else if (kind == ROW_WALL) {
-                    if (i == 0) {
-                        const double f0 = F[C::idx(l, 0)];
-                        dreg[s] = 0.5 * ih * (4.0 * (F[C::idx(l, 1)] - f0) - (F[C::idx(l, 2)] - f0));
-                    } else if (i == 1) {
-                        dreg[s] = 0.5 * ih * (F[C::idx(l, 2)] - F[C::idx(l, 0)]);
-                    } else if (i == n - 2) {
-                        dreg[s] = 0.5 * ih * (F[C::idx(l, n - 1)] - F[C::idx(l, n - 3)]);
-                    } else {
-                        const double fl = F[C::idx(l, n - 1)];
-                        dreg[s] = -0.5 * ih * (4.0 * (F[C::idx(l, n - 2)] - fl) - (F[C::idx(l, n - 3)] - fl));
-                    }
+            for (int c = 0; c < NC; ++c) {
+                const double *f = F(c);
+                double v;
+                if (s == 0) {
+                    const double f0 = f[C::fidx(l, 0)];
+                    v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
+                } else if (s == 1) {
+                    v = 0.5 * ih * (f[C::fidx(l, 2)] - f[C::fidx(l, 0)]);
+                } else if (s == 2) {
+                    v = 0.5 * ih * (f[C::fidx(l, n - 1)] - f[C::fidx(l, n - 3)]);
+                } else {
+                    const double fl = f[C::fidx(l, n - 1)];
+                    v = -0.5 * ih * (4.0 * (f[C::fidx(l, n - 2)] - fl) - (f[C::fidx(l, n - 3)] - fl));
                 }
+                KN(c)[C::kidx(s, l)] = v;
             }
-        }
-    }
+        } else {
+            const int e = s - 4;
+            const int row = pl.cl_row[e], j0 = pl.cl_j0[e], len = pl.cl_len[e];
+            const double *coef = pl.cl_coef + (size_t)e * kTaps;
+            double fe[NC], acc[NC];
 #pragma unroll
-    for (int c = 0; c < C::CLPT; ++c) {
-        const int q = tid + c * C::NT;
-        creg[c] = 0.0;
-        if (q < C::P * pl.ncl) {
-            const int l = q % C::P, e = q / C::P;
-            if (l < np) {
-                const int row = pl.cl_row[e], j0 = pl.cl_j0[e], len = pl.cl_len[e];
-                const double *coef = pl.cl_coef + (size_t)e * kTaps;
-                const double fe = F[C::idx(l, row)];
-                double acc = 0.0;
-                for (int t = 0; t < len; ++t) acc += coef[t] * (F[C::idx(l, j0 + t)] - fe);
-                creg[c] = acc * ih;
+            for (int c = 0; c < NC; ++c) {
+                fe[c] = F(c)[C::fidx(l, row)];
+                acc[c] = 0.0;
             }
+            for (int t = 0; t < len; ++t) {
+                const double w = coef[t];
+                const int ix = C::fidx(l, j0 + t);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += w * (F(c)[ix] - fe[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) KN(c)[C::kidx(s, l)] = acc[c] * ih;
         }
     }
     __syncthreads();
-    // ---- B: write back ----
-#pragma unroll
-    for (int s = 0; s < C::PTS; ++s) {
-        const int q = tid + s * C::NT;
-        if (q < C::P * n) {
-            int l, i;
-            C::owned(q, n, l, i);
-            if (l < np && pl.row_kind[i] != ROW_CLOSURE) F[C::idx(l, i)] = dreg[s];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < C::CLPT; ++c) {
-        const int q = tid + c * C::NT;
-        if (q < C::P * pl.ncl) {
-            const int l = q % C::P, e = q / C::P;
-            if (l < np) F[C::idx(l, pl.cl_row[e])] = creg[c];
-        }
-    }
-    __syncthreads();
-    // ---- C: Thomas on every run, known end rows lo and hi ----
+    // ---- C: B f and Thomas on every run ----
     for (int q = tid; q < C::P * pl.nrun; q += C::NT) {
         const int l = q % C::P, r = q / C::P;
         if (l >= np) continue;
         const int2 run = pl.runs[r];
+        const int2 slot = pl.run_slot[r];
         const int lo = run.x, hi = run.y, m = hi - lo - 1;
-        const double xlo = F[C::idx(l, lo)], xhi = F[C::idx(l, hi)];
-        double dprev = 0.0;
+        double xlo[NC], xhi[NC], w0[NC], w1[NC], w2[NC], w3[NC], w4[NC], dprev[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            xlo[c] = KN(c)[C::kidx(slot.x, l)];
+            xhi[c] = KN(c)[C::kidx(slot.y, l)];
+            // window f_{i-2} .. f_{i+2} at i = lo + 1; rows past hi + 1 are never used
+            w0[c] = F(c)[C::fidx(l, lo - 1)];
+            w1[c] = F(c)[C::fidx(l, lo)];
+            w2[c] = F(c)[C::fidx(l, lo + 1)];
+            w3[c] = F(c)[C::fidx(l, lo + 2)];
+            w4[c] = lo + 3 <= hi + 1 ? F(c)[C::fidx(l, lo + 3)] : 0.0;
+            dprev[c] = 0.0;
+        }
         for (int k = 1; k <= m; ++k) {
             const int i = lo + k;
-            double rr = F[C::idx(l, i)];
-            if (k == 1) rr = rr - kAlpha * xlo;
-            if (k == m) rr = rr - kAlpha * xhi;
-            const double dp = (rr - kAlpha * dprev) / pl.den[k];
-            F[C::idx(l, i)] = dp;
-            dprev = dp;
+            const double den = pl.den[k];
+            const int inext = i + 3;
+            const bool more = inext <= hi + 1;
+            const int ixn = C::fidx(l, more ? inext : i);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double rr = ih * (kB1 * (w3[c] - w1[c]) + kB2 * (w4[c] - w0[c]));
+                if (k == 1) rr = rr - kAlpha * xlo[c];
+                if (k == m) rr = rr - kAlpha * xhi[c];
+                const double dp = (rr - kAlpha * dprev[c]) / den;
+                const double fn = more ? F(c)[ixn] : 0.0;
+                F(c)[C::fidx(l, i)] = dp;
+                dprev[c] = dp;
+                w0[c] = w1[c];
+                w1[c] = w2[c];
+                w2[c] = w3[c];
+                w3[c] = w4[c];
+                w4[c] = fn;
+            }
         }
-        double xnext = dprev;
         for (int k = m - 1; k >= 1; --k) {
-            const int i = lo + k;
-            const double x = F[C::idx(l, i)] - pl.cp[k] * xnext;
-            F[C::idx(l, i)] = x;
-            xnext = x;
+            const int ix = C::fidx(l, lo + k);
+            const double cpk = pl.cp[k];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double x = F(c)[ix] - cpk * dprev[c];
+                F(c)[ix] = x;
+                dprev[c] = x;
+            }
         }
     }
     __syncthreads();
+}
+
+// f' of component c at (l, i) after lds_line_solve
+template <int DIR, int NMAX>
+__device__ inline double lds_result(const double *Fb, const double *KNb, int c, const LinePlanDev &pl, int l, int i) {
+    using C = SweepCfg<DIR, NMAX>;
+    const int s = pl.kslot[i];
+    return s < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(s, l)];
 }
 
 }  // namespace nopcs

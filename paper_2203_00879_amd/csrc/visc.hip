@@ -28,7 +28,12 @@ struct VArgs {
 
 struct Ring {
     double (*S)[4][VPL];
-    __device__ double at(int a, int li, int lj, int p) const { return S[p % VRING][a][lj * VLX + li]; }
+    __device__ double at(int a, int li, int lj, int p) const {
+        NOPCS_LDS_BOUND(li, VLX);
+        NOPCS_LDS_BOUND(lj, VLY);
+        NOPCS_LDS_BOUND(p, 1 << 30);
+        return S[p % VRING][a][lj * VLX + li];
+    }
 };
 
 // second-order derivative of primitive a along axis e at local node (li, lj, p)

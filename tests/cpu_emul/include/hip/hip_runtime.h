@@ -1,0 +1,132 @@
+// CPU stand-in for the subset of the HIP runtime that libnopcs uses, so the
+// library's kernels can be compiled with g++ and AddressSanitizer and run on
+// the host: every block runs as blockDim threads that meet at a std::barrier
+// for __syncthreads; __shared__ arrays become function statics (one block runs
+// at a time); device memory is host memory.  Test infrastructure only.
+#pragma once
+#include <algorithm>
+#include <barrier>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <vector>
+#include <sys/mman.h>
+#include <unistd.h>
+#include <map>
+#include <mutex>
+
+// Guarded allocation: the buffer sits between two PROT_NONE regions so that
+// any access before its start or after its end (up to the guard size) faults.
+inline std::map<void *, std::pair<void *, size_t>> &emu_allocs() {
+    static std::map<void *, std::pair<void *, size_t>> m;
+    return m;
+}
+inline std::mutex &emu_alloc_mu() {
+    static std::mutex m;
+    return m;
+}
+inline void *emu_guarded_alloc(size_t n) {
+    const size_t pg = (size_t)sysconf(_SC_PAGESIZE), guard = (size_t)4 << 20;
+    const size_t body = ((n ? n : 1) + pg - 1) / pg * pg;
+    const size_t total = guard + body + guard;
+    char *base = (char *)mmap(nullptr, total, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (base == MAP_FAILED) return nullptr;
+    mprotect(base, guard, PROT_NONE);
+    mprotect(base + guard + body, guard, PROT_NONE);
+    // end of the buffer flush with the trailing guard, start kept 256-byte aligned
+    char *p = base + guard + body - ((n + 255) & ~(size_t)255);
+    std::lock_guard<std::mutex> lk(emu_alloc_mu());
+    emu_allocs()[p] = {base, total};
+    return p;
+}
+inline void emu_guarded_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(emu_alloc_mu());
+    auto it = emu_allocs().find(p);
+    if (it != emu_allocs().end()) {
+        munmap(it->second.first, it->second.second);
+        emu_allocs().erase(it);
+    }
+}
+
+#define __global__
+#define __device__
+#define __host__
+#define __shared__ static
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __restrict__
+
+using std::max;
+using std::min;
+using std::sqrt;
+
+struct dim3 {
+    unsigned x = 1, y = 1, z = 1;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct int2 {
+    int x, y;
+};
+inline int2 make_int2(int a, int b) { return int2{a, b}; }
+
+inline thread_local dim3 threadIdx, blockIdx;
+inline dim3 gridDim, blockDim;
+inline thread_local std::barrier<> *emu_bar = nullptr;
+inline void __syncthreads() { emu_bar->arrive_and_wait(); }
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
+typedef void *hipStream_t;
+typedef struct emu_event *hipEvent_t;
+struct emu_event { std::chrono::steady_clock::time_point t; };
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost,
+                     hipMemcpyDefault };
+
+inline const char *hipGetErrorString(hipError_t) { return "emulated HIP error"; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+inline hipError_t hipSetDevice(int) { return hipSuccess; }
+inline hipError_t hipMalloc(void **p, size_t n) { *p = emu_guarded_alloc(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
+inline hipError_t hipFree(void *p) { emu_guarded_free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t) { std::memcpy(d, s, n); return hipSuccess; }
+inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
+inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new emu_event(); return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->t = std::chrono::steady_clock::now(); return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
+    *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
+    return hipSuccess;
+}
+
+template <class K, class... A>
+void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
+    gridDim = grid;
+    blockDim = block;
+    const unsigned nt = block.x * block.y * block.z;
+    for (unsigned bz = 0; bz < grid.z; ++bz)
+        for (unsigned by = 0; by < grid.y; ++by)
+            for (unsigned bx = 0; bx < grid.x; ++bx) {
+                std::barrier<> bar((std::ptrdiff_t)nt);
+                std::vector<std::thread> th;
+                th.reserve(nt);
+                for (unsigned t = 0; t < nt; ++t)
+                    th.emplace_back([&, t]() {
+                        threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+                        blockIdx = dim3(bx, by, bz);
+                        emu_bar = &bar;
+                        kernel(args...);
+                        bar.arrive_and_drop();
+                    });
+                for (auto &x : th) x.join();
+            }
+}
+#define hipLaunchKernelGGL(K, G, B, SHM, ST, ...) emu_launch(K, G, B, __VA_ARGS__)
