@@ -112,21 +112,22 @@ void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
     gridDim = grid;
     blockDim = block;
     const unsigned nt = block.x * block.y * block.z;
-    for (unsigned bz = 0; bz < grid.z; ++bz)
-        for (unsigned by = 0; by < grid.y; ++by)
-            for (unsigned bx = 0; bx < grid.x; ++bx) {
-                std::barrier<> bar((std::ptrdiff_t)nt);
-                std::vector<std::thread> th;
-                th.reserve(nt);
-                for (unsigned t = 0; t < nt; ++t)
-                    th.emplace_back([&, t]() {
-                        threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-                        blockIdx = dim3(bx, by, bz);
-                        emu_bar = &bar;
-                        kernel(args...);
-                        bar.arrive_and_drop();
-                    });
-                for (auto &x : th) x.join();
+    const unsigned nb = grid.x * grid.y * grid.z;
+    // one host thread per device thread; blocks run one after the other, separated
+    // by a barrier so that block-shared (static) arrays are reused safely
+    std::barrier<> bar((std::ptrdiff_t)nt);
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+            emu_bar = &bar;
+            for (unsigned b = 0; b < nb; ++b) {
+                blockIdx = dim3(b % grid.x, (b / grid.x) % grid.y, b / (grid.x * grid.y));
+                kernel(args...);
+                bar.arrive_and_wait();
             }
+        });
+    for (auto &x : th) x.join();
 }
 #define hipLaunchKernelGGL(K, G, B, SHM, ST, ...) emu_launch(K, G, B, __VA_ARGS__)
