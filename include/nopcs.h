@@ -163,6 +163,24 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
             void *ws, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------ */
+/* Tuning.                                                                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * nopcs_set_piece_length -- length of the extra cuts that the library makes
+ * inside every NOHAP segment along direction dir (0, 1, 2) before solving, in
+ * points: -1 restores the library's own choice (no cuts for n <= 64, else 32),
+ * 0 makes no extra cuts (one Thomas run per segment, the sequential order of
+ * Section 3), and a value >= 8 cuts every segment into pieces of at most that
+ * many points, each closed like a segment end (Eqs. CS:fpCf, CS:fpCf_i).
+ * Results change by round-off only.  The setting is process-wide and applies
+ * to calls made after it returns; plans already built for other lengths stay
+ * cached.  A later call whose grid then needs more known rows per line than a
+ * block holds fails with NOPCS_EINVAL.  Returns NOPCS_OK or NOPCS_EINVAL.
+ * Touches no device.
+ */
+int nopcs_set_piece_length(int32_t dir, int32_t piece_len);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (instrumentation).                                           */
 /* ------------------------------------------------------------------------ */
 enum {

@@ -1,4 +1,5 @@
 // api.hip -- C ABI entry points of libnopcs (declared in include/nopcs.h).
+#include <atomic>
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -17,10 +18,11 @@ const char *get_error() { return g_err.c_str(); }
 // Length of the extra cuts inside each user segment.  Short lines keep a single
 // run per segment (sequential Thomas order); long lines are cut so that a pencil
 // has enough independent runs for its threads.  Overridable for tuning.
-static int g_piece_len[3] = {-1, -1, -1};
+static std::atomic<int> g_piece_len[3] = {-1, -1, -1};
 
 int piece_length(int dir, int n) {
-    if (g_piece_len[dir] >= 0) return g_piece_len[dir];
+    const int pl = g_piece_len[dir].load();
+    if (pl >= 0) return pl;
     return n <= 64 ? 0 : 32;
 }
 
@@ -270,6 +272,16 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
                 NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
         }
     }
+    return NOPCS_OK;
+}
+
+int nopcs_set_piece_length(int32_t dir, int32_t piece_len) {
+    if (dir < 0 || dir > 2) { set_error("dir must be 0, 1 or 2"); return NOPCS_EINVAL; }
+    if (piece_len < -1 || (piece_len > 0 && piece_len < 8)) {
+        set_error("piece_len must be -1, 0 or >= 8");
+        return NOPCS_EINVAL;
+    }
+    g_piece_len[dir] = piece_len;
     return NOPCS_OK;
 }
 

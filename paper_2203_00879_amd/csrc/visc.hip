@@ -3,19 +3,29 @@
 // R = dEv/dx + dFv/dy + dGv/dz + S  (ge6-ge8, ge8a, ge19, ge20, bv1-bv3)
 // The velocity and temperature gradients inside Ev, Fv, Gv and the outer
 // divergence both use second-order differences: central inside, one-sided on
-// wall nodes (Section 4).  One block owns a TX x TY tile of an x-y plane and
-// marches along z over a chunk of planes; the primitives (u, v, w, T) of five
-// consecutive planes with a two-point halo sit in an LDS ring, so every state
-// value is read from HBM about once per block.  Tiles at the high end of x
-// and y are shifted inward (overlapping their neighbour) so that the one-sided
-// wall stencils, which reach three points inward, stay inside the halo.
+// wall nodes (Section 4).
+//
+// One block owns a CTX x CTY tile of output columns plus a two-column halo and
+// marches along z over a chunk of planes; one thread per column.  Each thread
+// keeps the primitives (u, v, w, T) of its own column for planes k-2..k+2 in
+// registers, so z differences need no shared memory.  Per plane, every column
+// publishes its primitives in LDS once; every node then evaluates its gradients,
+// mu, beta and the flux vectors it contributes (Ev at x-neighbours, Fv at
+// y-neighbours, Gv at the column itself) exactly once.  The x and y parts of
+// the divergence are taken from LDS at plane k; the z part is finished one
+// plane later from a three-plane register history of Gv.  Each state value is
+// read from HBM about 1.5 times (tile halo), each flux vector computed once.
+// Tiles at the high end of x and y are shifted inward (overlapping their
+// neighbour, which writes identical values) so that the one-sided wall
+// stencils stay inside the halo.  The summation order is that of the oracle:
+// (dEv/dx + dFv/dy) + dGv/dz, then the source.
 #include "kernels.hpp"
 
 namespace nopcs {
 
 namespace {
-constexpr int VTX = 32, VTY = 6, VLX = VTX + 4, VLY = VTY + 4, VPL = VLX * VLY, VRING = 5;
-constexpr int VNT = VTX * VTY;
+// Outputs per block (CTX x CTY) and columns per block (with a two-point halo).
+constexpr int CTX = 28, CTY = 12, CX = CTX + 4, CY = CTY + 4, CNT = CX * CY;
 
 struct VArgs {
     const double *Q;
@@ -26,164 +36,250 @@ struct VArgs {
     NdConst c;
 };
 
-struct Ring {
-    double (*S)[4][VPL];
-    __device__ double at(int a, int li, int lj, int p) const {
-        NOPCS_LDS_BOUND(li, VLX);
-        NOPCS_LDS_BOUND(lj, VLY);
-        NOPCS_LDS_BOUND(p, 1 << 30);
-        return S[p % VRING][a][lj * VLX + li];
-    }
-};
-
-// second-order derivative of primitive a along axis e at local node (li, lj, p)
-__device__ inline double grad(const Ring &r, int a, int e, int li, int lj, int p, int gidx, int n, double ih) {
-    auto f = [&](int o) -> double {
-        return e == 0 ? r.at(a, li + o, lj, p) : e == 1 ? r.at(a, li, lj + o, p) : r.at(a, li, lj, p + o);
-    };
-    if (gidx == 0) {
-        const double f0 = f(0);
-        return 0.5 * ih * (4.0 * (f(1) - f0) - (f(2) - f0));
-    }
-    if (gidx == n - 1) {
-        const double f0 = f(0);
-        return -0.5 * ih * (4.0 * (f(-1) - f0) - (f(-2) - f0));
-    }
-    return 0.5 * ih * (f(1) - f(-1));
+// second-order derivative from three values along an axis: f(-1), f(+1)
+// inside, or the one-sided form at a wall node (f0 on the wall, f1, f2 inward;
+// the high wall flips the sign)
+__device__ inline double d2c(double fm, double fp, double ih) { return 0.5 * ih * (fp - fm); }
+__device__ inline double d2w(double f0, double f1, double f2, double ih, bool high) {
+    const double v = 0.5 * ih * (4.0 * (f1 - f0) - (f2 - f0));
+    return high ? -v : v;
 }
 
-// viscous flux vector along d (Ev, Fv or Gv; components 1..4) at a local node
-__device__ inline void vflux(const Ring &r, const VArgs &A, int d, int li, int lj, int p, int gi, int gj, int gk,
-                             double out[4]) {
-    const NdConst &c = A.c;
-    const double u = r.at(0, li, lj, p), v = r.at(1, li, lj, p), w = r.at(2, li, lj, p), T = r.at(3, li, lj, p);
-    const double m = mu_of(c, T), b = beta_of(c, T);
-    const double Aa = (4.0 / 3.0) * m + b, Bb = b - (2.0 / 3.0) * m;
-    auto gx = [&](int a) { return grad(r, a, 0, li, lj, p, gi, A.nx, A.ihx); };
-    auto gy = [&](int a) { return grad(r, a, 1, li, lj, p, gj, A.ny, A.ihy); };
-    auto gz = [&](int a) { return grad(r, a, 2, li, lj, p, gk, A.nz, A.ihz); };
-    if (d == 0) {
-        const double ux = gx(0), vx = gx(1), wx = gx(2), Tx = gx(3);
-        const double uy = gy(0), vy = gy(1), uz = gz(0), wz = gz(2);
-        const double txx = (Aa * ux + Bb * (vy + wz)) * c.iRe;
-        const double txy = m * (uy + vx) * c.iRe;
-        const double txz = m * (uz + wx) * c.iRe;
-        const double qx = -c.kappa * m * Tx;
-        out[0] = txx; out[1] = txy; out[2] = txz;
-        out[3] = u * txx + v * txy + w * txz - qx;
-    } else if (d == 1) {
-        const double uy = gy(0), vy = gy(1), wy = gy(2), Ty = gy(3);
-        const double ux = gx(0), vx = gx(1), vz = gz(1), wz = gz(2);
-        const double txy = m * (uy + vx) * c.iRe;
-        const double tyy = (Aa * vy + Bb * (ux + wz)) * c.iRe;
-        const double tyz = m * (vz + wy) * c.iRe;
-        const double qy = -c.kappa * m * Ty;
-        out[0] = txy; out[1] = tyy; out[2] = tyz;
-        out[3] = u * txy + v * tyy + w * tyz - qy;
-    } else {
-        const double uz = gz(0), vz = gz(1), wz = gz(2), Tz = gz(3);
-        const double ux = gx(0), wx = gx(2), vy = gy(1), wy = gy(2);
-        const double txz = m * (uz + wx) * c.iRe;
-        const double tyz = m * (vz + wy) * c.iRe;
-        const double tzz = (Aa * wz + Bb * (ux + vy)) * c.iRe;
-        const double qz = -c.kappa * m * Tz;
-        out[0] = txz; out[1] = tyz; out[2] = tzz;
-        out[3] = u * txz + v * tyz + w * tzz - qz;
+// derivative of LDS field P at slot o along x (st = 1) or y (st = CX); g is
+// the node's global index along that axis.  WALL: the node may lie on a wall.
+template <bool WALL>
+__device__ inline double dplane(const double *P, int o, int st, int g, int n, double ih) {
+    if (WALL) {
+        if (g == 0) {
+            NOPCS_LDS_BOUND(o + 2 * st, CNT);
+            return d2w(P[o], P[o + st], P[o + 2 * st], ih, false);
+        }
+        if (g == n - 1) {
+            NOPCS_LDS_BOUND(o - 2 * st, CNT);
+            return d2w(P[o], P[o - st], P[o - 2 * st], ih, true);
+        }
     }
+    NOPCS_LDS_BOUND(o - st, CNT);
+    NOPCS_LDS_BOUND(o + st, CNT);
+    return d2c(P[o - st], P[o + st], ih);
 }
 
-// divergence contribution d(flux_d)/dx_d at the output node, all 4 components
-__device__ inline void vdiv(const Ring &r, const VArgs &A, int d, int li, int lj, int p, int gi, int gj, int gk,
-                            double acc[4]) {
-    const int gidx = d == 0 ? gi : d == 1 ? gj : gk;
-    const int n = d == 0 ? A.nx : d == 1 ? A.ny : A.nz;
-    const double ih = d == 0 ? A.ihx : d == 1 ? A.ihy : A.ihz;
-    auto node = [&](int o, double out[4]) {
-        vflux(r, A, d, li + (d == 0 ? o : 0), lj + (d == 1 ? o : 0), p + (d == 2 ? o : 0), gi + (d == 0 ? o : 0),
-              gj + (d == 1 ? o : 0), gk + (d == 2 ? o : 0), out);
-    };
-    double f0[4], f1[4], f2[4];
-    if (gidx == 0) {
-        node(0, f0); node(1, f1); node(2, f2);
-        for (int q = 0; q < 4; ++q) acc[q] = 0.5 * ih * (4.0 * (f1[q] - f0[q]) - (f2[q] - f0[q]));
-    } else if (gidx == n - 1) {
-        node(0, f0); node(-1, f1); node(-2, f2);
-        for (int q = 0; q < 4; ++q) acc[q] = -0.5 * ih * (4.0 * (f1[q] - f0[q]) - (f2[q] - f0[q]));
-    } else {
-        node(1, f1); node(-1, f0);
-        for (int q = 0; q < 4; ++q) acc[q] = 0.5 * ih * (f1[q] - f0[q]);
-    }
+// z derivative at plane k from the column window w = planes k-1, k, k+1; the
+// walls also need plane k+2 (fp2, bottom) or k-2 (fm2, top)
+__device__ inline double dz(const double w[3], double fm2, double fp2, int k, int nz, double ih) {
+    if (k == 0) return d2w(w[1], w[2], fp2, ih, false);
+    if (k == nz - 1) return d2w(w[1], w[0], fm2, ih, true);
+    return d2c(w[0], w[2], ih);
 }
 
-__global__ __launch_bounds__(VNT) void k_visc(VArgs A) {
-    const int b = blockIdx.x;
-    const int tt = b % A.ntx, rest = b / A.ntx, ty = rest % A.nty, tz = rest / A.nty;
-    const int i0 = min(tt * VTX, max(0, A.nx - VTX));
-    const int j0 = min(ty * VTY, max(0, A.ny - VTY));
-    const int k0 = tz * A.zc, k1 = min(A.nz, k0 + A.zc);
-    const int tid = threadIdx.x;
-    const int gi = i0 + tid % VTX, gj = j0 + tid / VTX;
-    const bool valid = gi < A.nx && gj < A.ny;
-    const long long N3 = A.N3;
+// One block's march over planes k0..k1-1 (see the file header).  S holds, per
+// column slot: u, v, w, T of plane k (fields 0-3), Ev (4-7) and Fv (8-11).
+// Output columns with gi < own_i or gj < own_j belong to the neighbouring tile.
+template <bool WALL>
+__device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int own_i, int own_j, int k0,
+                                  int k1) {
     const NdConst &c = A.c;
     const double *Q = A.Q;
+    const long long N3 = A.N3;
+    const long long plane = (long long)A.nx * A.ny;
+    const int tid = threadIdx.x;
+    const int ci = tid % CX, cj = tid / CX;
+    const int gi = i0 - 2 + ci, gj = j0 - 2 + cj;
+    const bool indom = !WALL || (gi >= 0 && gi < A.nx && gj >= 0 && gj < A.ny);
+    const bool inx = ci >= 2 && ci <= CTX + 1, iny = cj >= 2 && cj <= CTY + 1;
+    const bool center = indom && inx && iny && gi >= own_i && gj >= own_j;
+    const bool needE = indom && ci >= 1 && ci <= CTX + 2 && iny;   // includes every center
+    const bool needF = indom && cj >= 1 && cj <= CTY + 2 && inx;
+    const long long col = indom ? gi + (long long)A.nx * gj : 0;
+    double *const Pu = S, *const Pv = S + CNT, *const Pw = S + 2 * CNT, *const PT = S + 3 * CNT;
 
-    if (!c.viscous) {
+    // raw state of one plane of this column (a benign dummy outside the box)
+    auto load = [&](int p, double q[5]) {
+        if (indom && p >= 0 && p < A.nz) {
+            const long long o = col + plane * p;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) q[f] = Q[f * N3 + o];
+        } else {
+            q[0] = 1.0;
+            q[1] = q[2] = q[3] = q[4] = 0.0;
+        }
+    };
+    auto prim = [&](const double q[5], double &u, double &v, double &w, double &T) {
+        const Prim pr = prim_from(c, q[0], q[1], q[2], q[3], q[4]);
+        u = pr.u;
+        v = pr.v;
+        w = pr.w;
+        T = pr.T;
+    };
+    auto write_R = [&](int k, const double acc[4]) {
+        const long long o = col + plane * k;
+        A.R[o] = 0.0;
+        A.R[N3 + o] = acc[0];
+        A.R[2 * N3 + o] = acc[1] - c.ghat * Q[o];
+        A.R[3 * N3 + o] = acc[2];
+        A.R[4 * N3 + o] = acc[3] - c.ghat * Q[2 * N3 + o];
+    };
+
+    // planes whose node fluxes are needed: k0-1 .. k1, and nz-3 for the top wall
+    const int kb = max(0, min(k0 - 1, A.nz - 3)), ke = min(A.nz - 1, k1);
+    // window before the first shift: planes kb-2, kb-1, kb; raw state of kb+1
+    double wu[3], wv[3], ww[3], wT[3], raw[5];
+#pragma unroll
+    for (int s = 1; s < 3; ++s) {
+        load(kb - 2 + s, raw);
+        prim(raw, wu[s], wv[s], ww[s], wT[s]);
+    }
+    load(kb + 1, raw);
+    // G history (planes k-2, k-1, k) and the pending dEv/dx + dFv/dy of plane k-1
+    double G[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    double partPrev[4] = {0, 0, 0, 0};
+
+#pragma nounroll
+    for (int k = kb; k <= ke; ++k) {
+        // window -> planes k-1, k, k+1; the raw state of k+2 stays in flight
+        // while this plane is processed
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            wu[s] = wu[s + 1];
+            wv[s] = wv[s + 1];
+            ww[s] = ww[s + 1];
+            wT[s] = wT[s + 1];
+        }
+        prim(raw, wu[2], wv[2], ww[2], wT[2]);
+        load(k + 2, raw);
+        Pu[tid] = wu[1];
+        Pv[tid] = wv[1];
+        Pw[tid] = ww[1];
+        PT[tid] = wT[1];
+        __syncthreads();
+        // ---- node fluxes at (column, plane k): each computed once ----
+        double Gk[4] = {0, 0, 0, 0};
+        if (needE || needF) {
+            double um2 = 0.0, vm2 = 0.0, wm2 = 0.0, Tm2 = 0.0, up2 = 0.0, vp2 = 0.0, wp2 = 0.0, Tp2 = 0.0;
+            if (k == 0) prim(raw, up2, vp2, wp2, Tp2);
+            if (k == A.nz - 1) {
+                double q2[5];
+                load(k - 2, q2);
+                prim(q2, um2, vm2, wm2, Tm2);
+            }
+            const double u = wu[1], v = wv[1], w = ww[1], T = wT[1];
+            const double m = mu_of(c, T), bb = beta_of(c, T);
+            const double Aa = (4.0 / 3.0) * m + bb, Bb = bb - (2.0 / 3.0) * m;
+            // the stress tensor first (bv1-bv3), so that the nine velocity
+            // gradients die early; each entry is formed exactly as the oracle does
+            double txx, tyy, tzz;
+            {
+                const double ux = dplane<WALL>(Pu, tid, 1, gi, A.nx, A.ihx);
+                const double vy = dplane<WALL>(Pv, tid, CX, gj, A.ny, A.ihy);
+                const double wz = dz(ww, wm2, wp2, k, A.nz, A.ihz);
+                txx = (Aa * ux + Bb * (vy + wz)) * c.iRe;
+                tyy = (Aa * vy + Bb * (ux + wz)) * c.iRe;
+                tzz = (Aa * wz + Bb * (ux + vy)) * c.iRe;
+            }
+            const double txy =
+                m * (dplane<WALL>(Pu, tid, CX, gj, A.ny, A.ihy) + dplane<WALL>(Pv, tid, 1, gi, A.nx, A.ihx)) * c.iRe;
+            const double txz = m * (dz(wu, um2, up2, k, A.nz, A.ihz) + dplane<WALL>(Pw, tid, 1, gi, A.nx, A.ihx)) * c.iRe;
+            const double tyz = m * (dz(wv, vm2, vp2, k, A.nz, A.ihz) + dplane<WALL>(Pw, tid, CX, gj, A.ny, A.ihy)) * c.iRe;
+            if (needE) {
+                const double qx = -c.kappa * m * dplane<WALL>(PT, tid, 1, gi, A.nx, A.ihx);
+                S[4 * CNT + tid] = txx;
+                S[5 * CNT + tid] = txy;
+                S[6 * CNT + tid] = txz;
+                S[7 * CNT + tid] = u * txx + v * txy + w * txz - qx;
+            }
+            if (needF) {
+                const double qy = -c.kappa * m * dplane<WALL>(PT, tid, CX, gj, A.ny, A.ihy);
+                S[8 * CNT + tid] = txy;
+                S[9 * CNT + tid] = tyy;
+                S[10 * CNT + tid] = tyz;
+                S[11 * CNT + tid] = u * txy + v * tyy + w * tyz - qy;
+            }
+            if (center) {
+                const double qz = -c.kappa * m * dz(wT, Tm2, Tp2, k, A.nz, A.ihz);
+                Gk[0] = txz;
+                Gk[1] = tyz;
+                Gk[2] = tzz;
+                Gk[3] = u * txz + v * tyz + w * tzz - qz;
+            }
+        }
+        __syncthreads();
+        if (center) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                G[0][q] = G[1][q];
+                G[1][q] = G[2][q];
+                G[2][q] = Gk[q];
+            }
+            // dEv/dx + dFv/dy at plane k
+            double part[4] = {0, 0, 0, 0};
+            if (k >= k0 && k < k1) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    part[q] = dplane<WALL>(S + (4 + q) * CNT, tid, 1, gi, A.nx, A.ihx) +
+                              dplane<WALL>(S + (8 + q) * CNT, tid, CX, gj, A.ny, A.ihy);
+            }
+            // finish plane k-1 (inside): needs G(k) - G(k-2)
+            if (k - 1 >= k0 && k - 1 < k1 && k - 1 >= 1 && k - 1 <= A.nz - 2) {
+                double acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = partPrev[q] + d2c(G[0][q], G[2][q], A.ihz);
+                write_R(k - 1, acc);
+            }
+            // the bottom wall plane waits for G(0), G(1), G(2); its x-y part is
+            // parked in R, where only this thread reads it back
+            if (k == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) A.R[(q + 1) * N3 + col] = part[q];
+            }
+            if (k == 2 && k0 == 0) {
+                double acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[q] = A.R[(q + 1) * N3 + col] + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
+                write_R(0, acc);
+            }
+            // the top wall plane nz-1 is finished with G(nz-1), G(nz-2), G(nz-3)
+            if (k == A.nz - 1 && k < k1) {
+                double acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], A.ihz, true);
+                write_R(k, acc);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) partPrev[q] = part[q];
+        }
+    }
+}
+
+__global__ __launch_bounds__(CNT) void k_visc(VArgs A) {
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int tt = b % A.ntx, rest = b / A.ntx, ty = rest % A.nty, tz = rest / A.nty;
+    const int own_i = tt * CTX, own_j = ty * CTY;
+    const int i0 = min(own_i, max(0, A.nx - CTX));
+    const int j0 = min(own_j, max(0, A.ny - CTY));
+    const int k0 = tz * A.zc, k1 = min(A.nz, k0 + A.zc);
+    if (!A.c.viscous) {
+        const int ci = threadIdx.x % CX, cj = threadIdx.x / CX;
+        const int gi = i0 - 2 + ci, gj = j0 - 2 + cj;
+        if (ci < 2 || ci > CTX + 1 || cj < 2 || cj > CTY + 1 || gi < own_i || gj < own_j || gi >= A.nx ||
+            gj >= A.ny)
+            return;
+        const long long N3 = A.N3;
         for (int k = k0; k < k1; ++k) {
-            if (!valid) continue;
             const long long o = gi + (long long)A.nx * (gj + (long long)A.ny * k);
             A.R[o] = 0.0;
             A.R[N3 + o] = 0.0;
-            A.R[2 * N3 + o] = 0.0 - c.ghat * Q[o];
+            A.R[2 * N3 + o] = 0.0 - A.c.ghat * A.Q[o];
             A.R[3 * N3 + o] = 0.0;
-            A.R[4 * N3 + o] = 0.0 - c.ghat * Q[2 * N3 + o];
+            A.R[4 * N3 + o] = 0.0 - A.c.ghat * A.Q[2 * N3 + o];
         }
         return;
     }
-
-    __shared__ double S[VRING][4][VPL];
-    Ring r{S};
-    auto load_plane = [&](int p) {
-        for (int q = tid; q < VPL; q += VNT) {
-            const int li = q % VLX, lj = q / VLX;
-            const int x = i0 - 2 + li, y = j0 - 2 + lj;
-            if (x < 0 || x >= A.nx || y < 0 || y >= A.ny) continue;
-            const long long o = x + (long long)A.nx * (y + (long long)A.ny * p);
-            const Prim pr = prim_from(c, Q[o], Q[N3 + o], Q[2 * N3 + o], Q[3 * N3 + o], Q[4 * N3 + o]);
-            const int slot = p % VRING;
-            S[slot][0][q] = pr.u;
-            S[slot][1][q] = pr.v;
-            S[slot][2][q] = pr.w;
-            S[slot][3][q] = pr.T;
-        }
-    };
-    const int lo = max(0, min(k0 - 2, A.nz - 4));
-    int loaded = min(A.nz - 1, max(k0 + 2, 3));
-    for (int p = lo; p <= loaded; ++p) load_plane(p);
-    __syncthreads();
-    const int li = tid % VTX + 2, lj = tid / VTX + 2;
-    for (int k = k0; k < k1; ++k) {
-        const int target = min(A.nz - 1, max(k + 2, 3));
-        if (loaded < target) {
-            while (loaded < target) load_plane(++loaded);
-            __syncthreads();
-        }
-        if (valid) {
-            double ax[4], ay[4], az[4];
-            vdiv(r, A, 0, li, lj, k, gi, gj, k, ax);
-            vdiv(r, A, 1, li, lj, k, gi, gj, k, ay);
-            vdiv(r, A, 2, li, lj, k, gi, gj, k, az);
-            const long long o = gi + (long long)A.nx * (gj + (long long)A.ny * k);
-            double acc[4];
-            for (int q = 0; q < 4; ++q) acc[q] = ax[q] + ay[q] + az[q];
-            A.R[o] = 0.0;
-            A.R[N3 + o] = acc[0];
-            A.R[2 * N3 + o] = acc[1] - c.ghat * Q[o];
-            A.R[3 * N3 + o] = acc[2];
-            A.R[4 * N3 + o] = acc[3] - c.ghat * Q[2 * N3 + o];
-        }
-        __syncthreads();
-    }
+    __shared__ double S[12 * CNT];
+    // every column and every flux node of the tile off the x and y walls
+    const bool interior = i0 >= 2 && i0 + CTX + 2 <= A.nx && j0 >= 2 && j0 + CTY + 2 <= A.ny;
+    if (interior) visc_march<false>(A, S, i0, j0, own_i, own_j, k0, k1);
+    else visc_march<true>(A, S, i0, j0, own_i, own_j, k0, k1);
 }
 }  // namespace
 
@@ -195,9 +291,9 @@ hipError_t launch_visc(const double *Q, double *R, const int n[3], const double 
     A.nx = n[0];
     A.ny = n[1];
     A.nz = n[2];
-    A.ntx = (n[0] + VTX - 1) / VTX;
-    A.nty = (n[1] + VTY - 1) / VTY;
-    A.zc = n[2] <= 64 ? 16 : 32;
+    A.ntx = (n[0] + CTX - 1) / CTX;
+    A.nty = (n[1] + CTY - 1) / CTY;
+    A.zc = n[2] <= 64 ? 16 : 64;
     A.N3 = (long long)n[0] * n[1] * n[2];
     A.ihx = ih[0];
     A.ihy = ih[1];
@@ -205,7 +301,7 @@ hipError_t launch_visc(const double *Q, double *R, const int n[3], const double 
     A.c = c;
     const int ntz = (n[2] + A.zc - 1) / A.zc;
     const long long blocks = (long long)A.ntx * A.nty * ntz;
-    hipLaunchKernelGGL(k_visc, dim3((unsigned)blocks), dim3(VNT), 0, st, A);
+    hipLaunchKernelGGL(k_visc, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 //   driver deriv nx ny nz sx sy sz lx ly lz dir  in out        (in: N, out: d1 then d2)
 //   driver rhs   nx ny nz sx sy sz lx ly lz viscous gravity in out   (in/out: 5N)
 //   driver rk    nx ny nz sx sy sz lx ly lz viscous gravity dt nsteps in out
+// Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -36,6 +37,10 @@ static void write_raw(const char *path, const double *p, size_t n) {
 int main(int argc, char **argv) {
     if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
+    // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)
+    if (const char *pc = std::getenv("NOPCS_EMUL_PIECE"))
+        for (int d = 0; d < 3; ++d)
+            if (nopcs_set_piece_length(d, std::atoi(pc)) != NOPCS_OK) return 2;
     nopcs_grid g;
     for (int d = 0; d < 3; ++d) {
         g.n[d] = std::atoi(argv[2 + d]);
