@@ -27,12 +27,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 
-KERNEL_NAMES = ["viscous", "sweep_x", "sweep_y", "sweep_z", "wall", "derivative", "rk_update"]
+# timing ids of the library (NOPCS_K_* in include/nopcs.h), in order
+KERNEL_NAMES = ["viscous", "sweep_x", "sweep_y", "sweep_z", "wall", "derivative", "rk_update", "closure_y",
+                "closure_z"]
 KERNEL_SOURCES = {
     "viscous": ["visc.hip", "common.hpp", "kernels.hpp"],
     "sweep_x": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
-    "sweep_y": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
-    "sweep_z": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
+    "sweep_y": ["march.hip", "common.hpp", "plan.cpp"],
+    "sweep_z": ["march.hip", "common.hpp", "plan.cpp"],
+    "closure_y": ["march.hip", "common.hpp", "plan.cpp"],
+    "closure_z": ["march.hip", "common.hpp", "plan.cpp"],
     "rk_update": ["sweep.hip"],
     "wall": ["visc.hip", "common.hpp"],
 }
@@ -45,6 +49,8 @@ def kernel_bytes_per_point(name, precision):
         return 5 * w + 5 * w                       # read stage state, write R
     if name in ("sweep_x", "sweep_y", "sweep_z"):
         return 5 * w + 5 * w + 5 * w               # read state, read R, write R
+    if name in ("closure_y", "closure_z"):
+        return 5 * w                               # read state (closure rows written: ~1/16 of a field)
     if name == "rk_update":
         # stage 0: R, Qn -> K, Qs; stages 1, 2: R, Qn, K -> K, Qs; stage 3: R, Qn, K -> Qn
         return (4 * 5 * w + 2 * 5 * 5 * w + 4 * 5 * w) / 4.0

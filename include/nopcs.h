@@ -85,9 +85,12 @@ int nopcs_version(void);
  * concurrent calls). */
 int nopcs_release_plans(void);
 
-/* Workspace (device bytes) needed by nse_rhs (0) and rk_step (three 5-field
- * registers: the RK4 accumulator, the stage state and the right-hand side)
- * for this grid and precision.  Returns 0 on invalid input. */
+/* Workspace (device bytes) needed by nse_rhs and rk_step for this grid and
+ * precision: three 5-field FP64 registers (the RK4 accumulator, the stage state
+ * and the right-hand side; nse_rhs leaves them untouched) followed by the
+ * closure array of the sweeps along y and z (5 components x closure rows x
+ * lines, the larger direction).  Depends on the piece length in force
+ * (nopcs_set_piece_length).  Host only; returns 0 on invalid input. */
 size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision);
 
 /*
@@ -140,7 +143,9 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
  * differences (Section 4), central inside and one-sided on wall nodes.
  *
  * Q: device state (5 fields, read only); R: device output (5 fields), must not
- * overlap Q.  ws/ws_bytes: unused for NOPCS_FP64 (may be NULL/0).
+ * overlap Q.  ws: device workspace of at least nopcs_workspace_bytes(grid,
+ * precision) bytes, 256-byte aligned, not overlapping Q or R (NOPCS_EINVAL
+ * otherwise); its contents on return are unspecified.
  */
 int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R, void *ws,
             size_t ws_bytes, void *hip_stream);
@@ -191,7 +196,9 @@ enum {
     NOPCS_K_WALL = 4,     /* wall conditions (one launch per face pair)          */
     NOPCS_K_DERIV = 5,    /* standalone derivative                                */
     NOPCS_K_RK = 6,       /* RK4 register update of one stage                     */
-    NOPCS_K_COUNT = 7
+    NOPCS_K_CLOSURE_Y = 7,/* closure rows of the y sweep (line-march pass)         */
+    NOPCS_K_CLOSURE_Z = 8,/* closure rows of the z sweep (line-march pass)         */
+    NOPCS_K_COUNT = 9
 };
 
 /* on != 0: from now on every kernel launched by this library is bracketed by a

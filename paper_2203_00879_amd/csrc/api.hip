@@ -1,4 +1,5 @@
 // api.hip -- C ABI entry points of libnopcs (declared in include/nopcs.h).
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <mutex>
@@ -133,6 +134,37 @@ static hipError_t timed(int id, hipStream_t st, F &&f) {
 
 using namespace nopcs;
 
+// one 5-field FP64 state, 256-byte aligned
+static size_t state_bytes(const nopcs_grid *grid) {
+    return ((5 * field_elems(grid) * sizeof(double)) + 255) & ~(size_t)255;
+}
+
+// closure array of the line-march sweeps along y and z (one is live at a time)
+static size_t closure_bytes(const nopcs_grid *grid) {
+    size_t most = 0;
+    for (int d = 1; d <= 2; ++d) {
+        const std::vector<uint8_t> kind = row_kinds(grid->n[d], grid->nseg[d], piece_length(d, grid->n[d]));
+        int ncl = 0;
+        for (uint8_t k : kind) ncl += k == ROW_CLOSURE;
+        most = std::max(most, march_closure_elems(grid->n, d, ncl));
+    }
+    return ((most * sizeof(double)) + 255) & ~(size_t)255;
+}
+
+// convective sweep along d: line march (y, z) when the plan allows, LDS pencils otherwise
+static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, const LinePlanDev &pl, double *clo,
+                      hipStream_t st) {
+    if (clo && march_usable(d, pl)) {
+        NOPCS_HIP_CHECK(timed(NOPCS_K_CLOSURE_Y + (d - 1), st,
+                              [&] { return launch_march_closures(d, a.Qin, clo, grid->n, pl, a.c, st); }));
+        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
+                              [&] { return launch_march_runs(d, a.Qin, a.R, clo, grid->n, pl, a.c, st); }));
+        return NOPCS_OK;
+    }
+    NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl, st); }));
+    return NOPCS_OK;
+}
+
 extern "C" {
 
 const char *nopcs_last_error(void) { return get_error(); }
@@ -146,9 +178,7 @@ int nopcs_release_plans(void) {
 
 size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision) {
     if (!check_grid(grid) || (precision != NOPCS_FP64 && precision != NOPCS_MIXED)) return 0;
-    const size_t N = field_elems(grid);
-    const size_t reg = ((5 * N * sizeof(double)) + 255) & ~(size_t)255;
-    return 3 * reg;
+    return 3 * state_bytes(grid) + closure_bytes(grid);
 }
 
 int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int32_t *nrun, int32_t *runs,
@@ -194,7 +224,7 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
 }
 
 static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev pl[3], const double *Q, double *R,
-                    hipStream_t st) {
+                    double *clo, hipStream_t st) {
     double ih[3];
     for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
     NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, grid->n, ih, c, st); }));
@@ -203,23 +233,38 @@ static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev 
     a.R = R;
     a.N3 = (long long)field_elems(grid);
     a.c = c;
-    for (int d = 0; d < 3; ++d)
-        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
-                              [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl[d], st); }));
+    for (int d = 0; d < 3; ++d) {
+        const int rc = conv_sweep(d, a, grid, pl[d], clo, st);
+        if (rc != NOPCS_OK) return rc;
+    }
     return NOPCS_OK;
+}
+
+// checks of a caller-provided workspace
+static bool check_ws(const nopcs_grid *grid, int precision, const void *ws, size_t ws_bytes) {
+    const size_t need = nopcs_workspace_bytes(grid, precision);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return false;
+    }
+    if (((uintptr_t)ws & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return false;
+    }
+    return true;
 }
 
 int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R, void *ws,
             size_t ws_bytes, void *hip_stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
     if (precision != NOPCS_FP64) { set_error("nse_rhs: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
     if (!Q || !R) { set_error("Q and R must be non-NULL"); return NOPCS_EINVAL; }
+    if (!check_ws(grid, precision, ws, ws_bytes)) return NOPCS_EINVAL;
     LinePlanDev pl[3];
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
-    return rhs_into(make_nd(*params), grid, pl, Q, R, (hipStream_t)hip_stream);
+    double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * state_bytes(grid));
+    return rhs_into(make_nd(*params), grid, pl, Q, R, clo, (hipStream_t)hip_stream);
 }
 
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
@@ -229,22 +274,18 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
     if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
     if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
-    const size_t need = nopcs_workspace_bytes(grid, precision);
-    if (!ws || ws_bytes < need) {
-        set_error("workspace too small: need " + std::to_string(need) + " bytes");
-        return NOPCS_EINVAL;
-    }
-    if (((uintptr_t)ws & 255) != 0) { set_error("workspace must be 256-byte aligned"); return NOPCS_EINVAL; }
+    if (!check_ws(grid, precision, ws, ws_bytes)) return NOPCS_EINVAL;
     LinePlanDev pl[3];
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
     const NdConst c = make_nd(*params);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t N = field_elems(grid);
-    const size_t reg = need / 3;
+    const size_t reg = state_bytes(grid);
     double *K = reinterpret_cast<double *>(ws);
     double *Qs = reinterpret_cast<double *>(static_cast<char *>(ws) + reg);
     double *R = reinterpret_cast<double *>(static_cast<char *>(ws) + 2 * reg);
+    double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * reg);
     double ih[3];
     for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
     NseSweepArgs a{};
@@ -263,9 +304,10 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
             a.Qin = Qin;
             a.stage = stage;
             NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, grid->n, ih, c, st); }));
-            for (int d = 0; d < 3; ++d)
-                NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
-                                      [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl[d], st); }));
+            for (int d = 0; d < 3; ++d) {
+                const int rc2 = conv_sweep(d, a, grid, pl[d], clo, st);
+                if (rc2 != NOPCS_OK) return rc2;
+            }
             NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
             double *Qout = stage < 3 ? Qs : Q;
             for (int d = 0; d < 3; ++d)

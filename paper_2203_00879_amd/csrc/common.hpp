@@ -30,6 +30,24 @@
     } while (0)
 #endif
 
+// A value known to be the same in every lane of a wavefront, moved to a scalar
+// register (the host build of the kernels runs lanes as threads: no-op).
+#ifdef NOPCS_CPU_EMUL
+#define NOPCS_UNIFORM(x) (x)
+#else
+#define NOPCS_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
+#endif
+
+// Read-only table the kernels index with wave-uniform indices: through the
+// constant address space the compiler uses scalar loads (scalar cache, no wait
+// on the vector memory counter).  The tables are written before the launch and
+// never during it.
+#ifdef NOPCS_CPU_EMUL
+#define NOPCS_SCALAR_PTR(T, p) ((const T *)(p))
+#else
+#define NOPCS_SCALAR_PTR(T, p) ((const T __attribute__((address_space(4))) *)(p))
+#endif
+
 namespace nopcs {
 
 // OUCS3 scheme with eta = 0 (Section 3, entries of A and B after Eq. CS:AfpBf):

@@ -33,6 +33,23 @@ hipError_t launch_nse_sweep(int dir, const NseSweepArgs &a, const SweepGeom &g, 
 // RK4 register update of stage a.stage from R (point-wise over 5 fields)
 hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st);
 
+// Line-march sweeps along y (dir 1) and z (dir 2): geometry of the lines.
+struct MarchGeom {
+    int nx, no, n, nxc;     // lines along x, lines along the other axis, points per line, x chunks
+    long long sD, sO, N3;   // strides of the line direction and of the other axis; points per field
+};
+// true if the plan's runs and closure slots fit the march kernels
+bool march_usable(int dir, const LinePlanDev &pl);
+// doubles of the closure array of one march sweep
+size_t march_closure_elems(const int n[3], int dir, int ncl);
+// closure rows of the 5 convective flux components along dir into clo
+// (march_closure_elems doubles); nothing to do without closure rows
+hipError_t launch_march_closures(int dir, const double *Q, double *clo, const int n[3], const LinePlanDev &pl,
+                                 const NdConst &c, hipStream_t st);
+// R <- R - D_dir(convective flux) for the 5 components, closures from clo
+hipError_t launch_march_runs(int dir, const double *Q, double *R, const double *clo, const int n[3],
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st);
+
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, double *R, const int n[3], const double ih[3], const NdConst &c,
                        hipStream_t st);

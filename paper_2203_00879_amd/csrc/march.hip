@@ -1,0 +1,368 @@
+// march.hip -- convective sweeps along y and z that stream along the line.
+//
+// Lines along y and z are strided in memory.  Staging whole lines in LDS gives
+// narrow pencils (a few consecutive x per row, scattered over many DRAM pages);
+// here a block owns 64 neighbouring lines (consecutive x, so every load and
+// store is one 512-byte row) and walks along the line direction, one wavefront
+// per flux component:
+//
+//   k_closure_march  one pass over the rows that carry taps accumulates every
+//       closure row of the NOHAP split (Eqs. CS:fpCf, CS:fpCf_i) in a few
+//       register slots,
+//         f'_e = [sum_j C_ej (f_j - f_r) - (f_e - f_r) sum_j C_ej] / h,
+//       with f_r the flux at the first tap.  In exact arithmetic this is
+//       sum_j C_ej (f_j - f_e) (the form the LDS sweeps use); both vanish
+//       exactly for a constant field.  Results go to a small array
+//       [component][closure][line].
+//   k_march_sweep  walks a group of consecutive Thomas runs of a line: (B f)_i
+//       from a five-value register window, forward elimination with the
+//       tabulated pivots (Section 3) into registers (runs of <= 32 unknowns),
+//       back substitution fused with R -= f'.  The known rows bounding the runs
+//       come from the closure pass or from the explicit wall rows.
+//
+// Rows of the state reach the block through a two-chunk LDS ring: wavefront w
+// fetches field w of the next CH rows into registers while the block works on
+// the current chunk, and publishes them at the chunk boundary (one barrier per
+// chunk).  Every wavefront forms its own flux component from the staged row.
+// Arithmetic of the walls, the runs and the R update is operation for
+// operation that of the LDS sweeps.
+#include "kernels.hpp"
+
+namespace nopcs {
+
+namespace {
+
+constexpr int MW = 64;      // lines per block (consecutive x)
+constexpr int MRL = 32;     // longest run a thread keeps in registers
+constexpr int NCOMP = 5;    // flux components (one wavefront each) = state fields
+constexpr int CH = 8;       // rows per LDS chunk
+
+// Convective flux component comp along DIR (ge3-ge5) from the staged row of
+// one line, formed as in the LDS sweeps.
+template <int DIR>
+__device__ inline double flux_row(const double (*L)[MW], int lane, int comp, const NdConst &c) {
+    if (comp == 0) return L[DIR + 1][lane];
+    const double rho = L[0][lane], md = L[DIR + 1][lane];
+    if (comp == 4 || comp == DIR + 1) {
+        const Prim pr = prim_from(c, rho, L[1][lane], L[2][lane], L[3][lane], L[4][lane]);
+        const double ud = DIR == 1 ? pr.v : pr.w;
+        if (comp == 4) return ((L[4][lane] + pr.pp) + c.H) * ud;
+        return md * ud + pr.pp;
+    }
+    const double ri = 1.0 / rho;
+    const double ud = md * ri;
+    return L[comp][lane] * ud;
+}
+
+// Rows [row0, rowN] of the block's 64 lines pass through a two-chunk LDS ring.
+struct RowPipe {
+    double (*L)[CH][NCOMP][MW];   // [2][CH][field][lane]
+    const double *src;            // this wavefront's field at row 0 of its line (a valid
+                                  // address also for lanes past the last line)
+    long long sD;
+    int row0, rowN, lane, field;
+    double pre[CH];               // next chunk, in flight
+    // unconditional loads (no branches: the compiler's memory waits stay
+    // precise); rows past rowN repeat row rowN and are never used
+    __device__ void fetch(int rb) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) pre[u] = src[sD * min(rb + u, rowN)];
+    }
+    __device__ void publish(int buf) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u) L[buf][u][field][lane] = pre[u];
+    }
+    // before the first read: chunk 0 in LDS, chunk 1 in flight
+    __device__ void start() {
+        fetch(row0);
+        publish(0);
+        fetch(row0 + CH);
+        __syncthreads();
+    }
+    // staged fields of row r (rows are read in increasing order; the first
+    // read of a chunk k >= 1 publishes it and starts fetching chunk k + 1)
+    __device__ const double (*row(int r))[MW] {
+        const int rel = r - row0, k = rel / CH, u = rel - k * CH;
+        if (u == 0 && k > 0) {
+            publish(k & 1);
+            __syncthreads();
+            fetch(row0 + (k + 1) * CH);
+        }
+        NOPCS_LDS_BOUND(rel, rowN - row0 + 1 + CH);
+        NOPCS_LDS_BOUND(u, CH);
+        return L[k & 1][u];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Closure pass
+// ---------------------------------------------------------------------------
+template <int DIR, int S>
+__global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__restrict__ Q, double *__restrict__ clo,
+                                                              MarchGeom g, LinePlanDev pl, NdConst c) {
+    __shared__ double L[2][CH][NCOMP][MW];
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int xc = b % g.nxc, o = b / g.nxc;
+    const int lane = threadIdx.x;
+    const int x = xc * MW + lane;
+    const int comp = NOPCS_UNIFORM((int)threadIdx.y);
+    const bool ok = x < g.nx;
+    const long long base = x + g.sO * o;
+    const long long nlines = (long long)g.nx * g.no;
+    const long long line = x + (long long)g.nx * o;
+    const auto cl_j0 = NOPCS_SCALAR_PTR(int, pl.cl_j0);
+    const auto cl_len = NOPCS_SCALAR_PTR(int, pl.cl_len);
+    const auto k1_rec = NOPCS_SCALAR_PTR(int, pl.k1_rec);
+    const auto k1_w = NOPCS_SCALAR_PTR(double, pl.k1_w);
+    const auto cl_wsum = NOPCS_SCALAR_PTR(double, pl.cl_wsum);
+    const int jlo = cl_j0[0];
+    const int jhi = cl_j0[pl.ncl - 1] + cl_len[pl.ncl - 1] - 1;
+    RowPipe P;
+    P.L = L;
+    P.src = Q + comp * g.N3 + (ok ? base : 0);
+    P.sD = g.sD;
+    P.row0 = jlo;
+    P.rowN = jhi;
+    P.lane = lane;
+    P.field = comp;
+    P.start();
+    const auto k1_ev = NOPCS_SCALAR_PTR(int, pl.k1_ev);
+    double acc[S], fr[S], fe[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        acc[s] = 0.0;
+        fr[s] = 0.0;
+        fe[s] = 0.0;
+    }
+    // every slot accumulates every row (inactive slots carry a zero tap, which
+    // leaves the sum unchanged); the rare slot events take one uniform branch
+    for (int j = jlo; j <= jhi; ++j) {
+        const double f = flux_row<DIR>(P.row(j), lane, comp, c);
+        const auto wj = k1_w + (size_t)j * S;
+        const int ev = k1_ev[2 * j];
+        if (ev) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (ev & (1 << s)) {
+                    fr[s] = f;
+                    acc[s] = 0.0;
+                }
+                if (ev & (1 << (16 + s))) fe[s] = f;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += wj[s] * (f - fr[s]);
+        const int evc = k1_ev[2 * j + 1];
+        if (evc) {
+            const auto rec = k1_rec + (size_t)j * S;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (evc & (1 << s)) {
+                    const int qi = rec[s] & 0xfff;
+                    const double v = (acc[s] - (fe[s] - fr[s]) * cl_wsum[qi]) * pl.ih;
+                    if (ok) clo[((long long)comp * pl.ncl + qi) * nlines + line] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Run march
+// ---------------------------------------------------------------------------
+template <int DIR, bool FULL>
+__global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, double *R,
+                                                            const double *__restrict__ clo, MarchGeom g,
+                                                            LinePlanDev pl, NdConst c) {
+    __shared__ double L[2][CH][NCOMP][MW];
+    __shared__ double KV[2 * kGroupRuns][NCOMP][MW];   // closure values bounding the group's runs
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int xc = b % g.nxc, rest = b / g.nxc, o = rest % g.no, grp = rest / g.no;
+    const int lane = threadIdx.x;
+    const int x = xc * MW + lane;
+    const int comp = NOPCS_UNIFORM((int)threadIdx.y);
+    const bool ok = FULL || x < g.nx;   // FULL: nx is a multiple of MW
+    const int n = g.n;
+    const double ih = pl.ih;
+    const long long sD = g.sD;
+    const long long base = x + g.sO * o;
+    const long long nlines = (long long)g.nx * g.no;
+    const long long line = x + (long long)g.nx * o;
+    double *Rc = R + comp * g.N3 + (ok ? base : 0);   // this component's R at row 0 of the line
+    const double *clc = clo + (long long)comp * pl.ncl * nlines + (ok ? line : 0);
+    // int2 tables read as int pairs through the scalar path
+    const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
+    const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
+    const auto grp_i = NOPCS_SCALAR_PTR(int, pl.grp);
+    auto runs = [&](int r) { return make_int2(runs_i[2 * r], runs_i[2 * r + 1]); };
+    auto run_slot = [&](int r) { return make_int2(slot_i[2 * r], slot_i[2 * r + 1]); };
+    const auto run_own = NOPCS_SCALAR_PTR(int, pl.run_own);
+    const auto den = NOPCS_SCALAR_PTR(double, pl.den);
+    const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
+    const int2 gr = make_int2(grp_i[2 * grp], grp_i[2 * grp + 1]);
+    const int lo0 = runs(gr.x).x;
+
+    // closure values of the group's run bounds, read once into LDS (each
+    // thread reads back only what it wrote)
+    for (int r = gr.x; r < gr.y; ++r) {
+        const int2 slot = run_slot(r);
+        const int j = 2 * (r - gr.x);
+        NOPCS_LDS_BOUND(j + 1, 2 * kGroupRuns);
+        if (slot.x >= 4) KV[j][comp][lane] = ok ? clc[(long long)(slot.x - 4) * nlines] : 0.0;
+        if (slot.y >= 4) KV[j + 1][comp][lane] = ok ? clc[(long long)(slot.y - 4) * nlines] : 0.0;
+    }
+    RowPipe P;
+    P.L = L;
+    P.src = Q + comp * g.N3 + (ok ? base : 0);
+    P.sD = sD;
+    P.row0 = lo0 - 1;
+    P.rowN = runs(gr.y - 1).y + 1;
+    P.lane = lane;
+    P.field = comp;
+    P.start();
+
+    // window: w0..w4 = f(i-2) .. f(i+2) for the row i about to be solved
+    int i = lo0 + 1;
+    double w0 = flux_row<DIR>(P.row(i - 2), lane, comp, c);
+    double w1 = flux_row<DIR>(P.row(i - 1), lane, comp, c);
+    double w2 = flux_row<DIR>(P.row(i), lane, comp, c);
+    double w3 = flux_row<DIR>(P.row(i + 1), lane, comp, c);
+    double w4 = flux_row<DIR>(P.row(i + 2), lane, comp, c);
+    auto advance = [&]() {
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+        w3 = w4;
+        w4 = flux_row<DIR>(P.row(i + 3), lane, comp, c);   // a dummy past the group's last row
+        ++i;
+    };
+
+    for (int r = gr.x; r < gr.y; ++r) {
+        const int2 run = runs(r);
+        const int lo = run.x, hi = run.y, m = hi - lo - 1;
+        while (i < lo + 1) advance();
+        const int2 slot = run_slot(r);
+        const int own = run_own[r];
+        // known rows: closures from the closure pass, rows 1 and n-2 central,
+        // rows 0 and n-1 one-sided (the formulas of the LDS sweeps)
+        double xlo = 0.0, xhi = 0.0, v0 = 0.0, vn = 0.0;
+        if (slot.x >= 4) xlo = KV[2 * (r - gr.x)][comp][lane];
+        else xlo = 0.5 * ih * (w2 - w0);   // row 1 (i = 2)
+        if (slot.y >= 4) xhi = KV[2 * (r - gr.x) + 1][comp][lane];
+        if (own & 4) v0 = 0.5 * ih * (4.0 * (w1 - w0) - (w2 - w0));   // row 0 (i = 2)
+        double d[MRL];
+#pragma unroll
+        for (int t = 0; t < MRL; ++t) d[t] = 0.0;
+        double dprev = 0.0;
+#pragma unroll
+        for (int t = 0; t < MRL; ++t) {
+            if (t < m) {
+                const int k = t + 1;
+                double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+                if (k == 1) rr = rr - kAlpha * xlo;
+                if (k == m) {
+                    if (slot.y < 4) xhi = 0.5 * ih * (w4 - w2);   // row n-2 (i = n-3)
+                    if (own & 8) {
+                        const double fl = w4;                         // row n-1
+                        vn = -0.5 * ih * (4.0 * (w3 - fl) - (w2 - fl));
+                    }
+                    rr = rr - kAlpha * xhi;
+                }
+                const double dp = (rr - kAlpha * dprev) / den[k];
+                d[t] = dp;
+                dprev = dp;
+                advance();
+            }
+        }
+        // back substitution (x_m = d_m, x_k = d_k - c'_k x_{k+1}) fused with
+        // R -= f'.  The loop is straight-line over MRL steps so that memory
+        // waits stay precise: steps t >= m use x = 0 on the run's last row,
+        // which rewrites that row's original value before its real update.
+        // R rows are fetched RA steps ahead, each load issued before the store
+        // that follows it.
+        constexpr int RA = 8;
+        auto rrow = [&](int t) { return sD * (lo + 1 + (t < m ? t : m - 1)); };
+        double ring[RA];
+#pragma unroll
+        for (int t = MRL - RA; t < MRL; ++t) ring[t % RA] = Rc[rrow(t)];
+        // R of the known rows this run may update (rows outside lo+1 .. hi-1)
+        const double rlo = Rc[sD * lo], rhi = Rc[sD * hi], r0 = Rc[0], rn = Rc[sD * (n - 1)];
+        double xn = 0.0;
+#pragma unroll
+        for (int t = MRL - 1; t >= 0; --t) {
+            const int k = t + 1;
+            const double xs = k == m ? d[t] : d[t] - cp[k] * xn;
+            const double xk = t < m ? xs : 0.0;
+            xn = xk;
+            const double nv = ring[t % RA] - xk;
+            if (t - RA >= 0) ring[t % RA] = Rc[rrow(t - RA)];
+            if (ok) Rc[rrow(t)] = nv;
+        }
+        if (ok) {
+            if (own & 1) Rc[sD * lo] = rlo - xlo;
+            if (own & 2) Rc[sD * hi] = rhi - xhi;
+            if (own & 4) Rc[0] = r0 - v0;
+            if (own & 8) Rc[sD * (n - 1)] = rn - vn;
+        }
+    }
+}
+
+}  // namespace
+
+bool march_usable(int dir, const LinePlanDev &pl) {
+    if (dir != 1 && dir != 2) return false;
+    if (pl.nrun < 1 || pl.max_m > MRL || pl.max_m < 1) return false;
+    if (pl.ncl > 0 && pl.k1_S != 8 && pl.k1_S != kMaxSlots) return false;
+    return pl.ngrp >= 1;
+}
+
+size_t march_closure_elems(const int n[3], int dir, int ncl) {
+    const size_t lines = (size_t)n[0] * n[1] * n[2] / (size_t)n[dir];
+    return (size_t)NCOMP * (size_t)ncl * lines;
+}
+
+MarchGeom march_geom(const int n[3], int dir) {
+    MarchGeom g;
+    g.nx = n[0];
+    g.n = n[dir];
+    g.N3 = (long long)n[0] * n[1] * n[2];
+    if (dir == 1) {
+        g.no = n[2];
+        g.sD = n[0];
+        g.sO = (long long)n[0] * n[1];
+    } else {
+        g.no = n[1];
+        g.sD = (long long)n[0] * n[1];
+        g.sO = n[0];
+    }
+    g.nxc = (n[0] + MW - 1) / MW;
+    return g;
+}
+
+hipError_t launch_march_closures(int dir, const double *Q, double *clo, const int n[3], const LinePlanDev &pl,
+                                 const NdConst &c, hipStream_t st) {
+    if (pl.ncl == 0) return hipSuccess;
+    const MarchGeom g = march_geom(n, dir);
+    const dim3 blk(MW, NCOMP), grd((unsigned)(g.nxc * g.no));
+    if (dir == 1 && pl.k1_S == 8) hipLaunchKernelGGL((k_closure_march<1, 8>), grd, blk, 0, st, Q, clo, g, pl, c);
+    else if (dir == 1) hipLaunchKernelGGL((k_closure_march<1, kMaxSlots>), grd, blk, 0, st, Q, clo, g, pl, c);
+    else if (dir == 2 && pl.k1_S == 8) hipLaunchKernelGGL((k_closure_march<2, 8>), grd, blk, 0, st, Q, clo, g, pl, c);
+    else if (dir == 2) hipLaunchKernelGGL((k_closure_march<2, kMaxSlots>), grd, blk, 0, st, Q, clo, g, pl, c);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_march_runs(int dir, const double *Q, double *R, const double *clo, const int n[3],
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
+    const MarchGeom g = march_geom(n, dir);
+    const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
+    const bool full = g.nx % MW == 0;
+    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace nopcs

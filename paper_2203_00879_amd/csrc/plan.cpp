@@ -9,6 +9,7 @@
 // between known rows form independent constant-coefficient tridiagonal runs.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -77,6 +78,32 @@ static void global_column(int n, int j, std::vector<long double> &x, std::vector
     for (int k = m - 2; k >= 0; --k) x[2 + k] = dp[k] - cp[k] * x[2 + k + 1];
 }
 
+void build_march_tables(LinePlanHost &P);
+
+std::vector<uint8_t> row_kinds(int n, int nseg, int sub_len) {
+    const std::vector<int> seg_lo = even_segments(n, nseg);
+    // piece starts: user segment starts plus even cuts inside each segment
+    std::vector<int> starts;
+    for (int s = 0; s < nseg; ++s) {
+        const int a = seg_lo[s];
+        const int e = (s + 1 < nseg) ? seg_lo[s + 1] - 1 : n - 1;
+        const int len = e - a + 1;
+        int pieces = 1;
+        if (sub_len > 0) pieces = (len + sub_len - 1) / sub_len;
+        while (pieces > 1 && len / pieces < 4) --pieces;
+        const std::vector<int> sub = even_segments(len, pieces);
+        for (int v : sub) starts.push_back(a + v);
+    }
+    std::vector<uint8_t> kind(n, ROW_COMPACT);
+    for (int i : {0, 1, n - 2, n - 1}) kind[i] = ROW_WALL;
+    for (size_t q = 1; q < starts.size(); ++q) {
+        const int b = starts[q];
+        for (int e : {b - 1, b})
+            if (kind[e] == ROW_COMPACT) kind[e] = ROW_CLOSURE;
+    }
+    return kind;
+}
+
 bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string &err) {
     if (n < 8) {
         err = "line length must be >= 8 (got " + std::to_string(n) + ")";
@@ -92,25 +119,7 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
     P.nseg = nseg;
     P.sub_len = sub_len;
     P.seg_lo = even_segments(n, nseg);
-    // piece starts: user segment starts plus even cuts inside each segment
-    std::vector<int> starts;
-    for (int s = 0; s < nseg; ++s) {
-        const int a = P.seg_lo[s];
-        const int e = (s + 1 < nseg) ? P.seg_lo[s + 1] - 1 : n - 1;
-        const int len = e - a + 1;
-        int pieces = 1;
-        if (sub_len > 0) pieces = (len + sub_len - 1) / sub_len;
-        while (pieces > 1 && len / pieces < 4) --pieces;
-        const std::vector<int> sub = even_segments(len, pieces);
-        for (int v : sub) starts.push_back(a + v);
-    }
-    P.row_kind.assign(n, ROW_COMPACT);
-    for (int i : {0, 1, n - 2, n - 1}) P.row_kind[i] = ROW_WALL;
-    for (size_t q = 1; q < starts.size(); ++q) {
-        const int b = starts[q];
-        for (int e : {b - 1, b})
-            if (P.row_kind[e] == ROW_COMPACT) P.row_kind[e] = ROW_CLOSURE;
-    }
+    P.row_kind = row_kinds(n, nseg, sub_len);
     int lo = 1;
     for (int i = 2; i <= n - 2; ++i) {
         if (P.row_kind[i] != ROW_COMPACT) {
@@ -170,7 +179,80 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
         P.cp[k] = kAlpha / den;
         cprev = P.cp[k];
     }
+    build_march_tables(P);
     return true;
+}
+
+// Tables of the line-march sweeps: which run makes the R update of each known
+// row, a slot schedule for accumulating all closure sums in one pass along the
+// line, and groups of consecutive runs.
+void build_march_tables(LinePlanHost &P) {
+    const int n = P.n, nrun = (int)P.runs.size(), ncl = (int)P.cl_row.size();
+    P.max_m = 0;
+    for (const int2 &r : P.runs) P.max_m = std::max(P.max_m, r.y - r.x - 1);
+    // every known row is a bound of some run (segments and pieces have >= 4
+    // points); the first run that touches it updates it, rows 0 and n-1 go with
+    // the first and the last run
+    P.run_own.assign(nrun, 0);
+    std::vector<char> done(n, 0);
+    for (int r = 0; r < nrun; ++r) {
+        const int2 b = P.runs[r];
+        if (!done[b.x]) { P.run_own[r] |= 1; done[b.x] = 1; }
+        if (!done[b.y]) { P.run_own[r] |= 2; done[b.y] = 1; }
+    }
+    if (nrun > 0) {
+        P.run_own[0] |= 4;
+        P.run_own[nrun - 1] |= 8;
+    }
+    // closure slots: interval colouring of the tap windows in row order
+    std::vector<int> slot_of(ncl, -1), slot_end(kMaxSlots, -1);
+    int nslot = 0;
+    bool fits = true;
+    for (int q = 0; q < ncl && fits; ++q) {
+        int s = 0;
+        while (s < kMaxSlots && slot_end[s] >= P.cl_j0[q]) ++s;
+        if (s == kMaxSlots) { fits = false; break; }
+        slot_of[q] = s;
+        slot_end[s] = P.cl_j0[q] + P.cl_len[q] - 1;
+        nslot = std::max(nslot, s + 1);
+    }
+    P.k1_S = !fits ? 0 : (nslot <= 8 ? 8 : kMaxSlots);
+    P.k1_rec.assign((size_t)n * std::max(P.k1_S, 1), -1);
+    P.k1_w.assign((size_t)n * std::max(P.k1_S, 1), 0.0);
+    P.k1_ev.assign(2 * (size_t)n, 0);
+    if (P.k1_S > 0) {
+        for (int q = 0; q < ncl; ++q) {
+            for (int t = 0; t < P.cl_len[q]; ++t) {
+                const int j = P.cl_j0[q] + t;
+                int rec = q | (t << 12);
+                if (t == 0) rec |= kRecOpen;
+                if (j == P.cl_row[q]) rec |= kRecRow;
+                if (t == P.cl_len[q] - 1) rec |= kRecClose;
+                P.k1_rec[(size_t)j * P.k1_S + slot_of[q]] = rec;
+                if (rec & kRecOpen) P.k1_ev[2 * (size_t)j] |= 1 << slot_of[q];
+                if (rec & kRecRow) P.k1_ev[2 * (size_t)j] |= 1 << (16 + slot_of[q]);
+                if (rec & kRecClose) P.k1_ev[2 * (size_t)j + 1] |= 1 << slot_of[q];
+                P.k1_w[(size_t)j * P.k1_S + slot_of[q]] = P.cl_coef[(size_t)q * kTaps + t];
+            }
+        }
+    }
+    P.cl_wsum.assign(ncl, 0.0);
+    for (int q = 0; q < ncl; ++q) {
+        double w = 0.0;
+        for (int t = 0; t < P.cl_len[q]; ++t) w += P.cl_coef[(size_t)q * kTaps + t];
+        P.cl_wsum[q] = w;
+    }
+    // run groups of about kGroupRows rows and at most kGroupRuns runs
+    P.grp.clear();
+    int r0 = 0, rows = 0;
+    for (int r = 0; r < nrun; ++r) {
+        rows += P.runs[r].y - P.runs[r].x;
+        if (rows >= kGroupRows || r + 1 - r0 == kGroupRuns || r == nrun - 1) {
+            P.grp.push_back(make_int2(r0, r + 1));
+            r0 = r + 1;
+            rows = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -221,6 +303,13 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     const size_t o_cp = off;   off = align256(off + sizeof(double) * (n + 1));
     const size_t o_d32 = off;  off = align256(off + sizeof(float) * (n + 1));
     const size_t o_c32b = off; off = align256(off + sizeof(float) * (n + 1));
+    const int ngrp = (int)P.grp.size();
+    const size_t o_grp = off;  off = align256(off + sizeof(int2) * (ngrp + 1));
+    const size_t o_own = off;  off = align256(off + sizeof(int) * (nrun + 1));
+    const size_t o_rec = off;  off = align256(off + sizeof(int) * (P.k1_rec.size() + 1));
+    const size_t o_wsum = off; off = align256(off + sizeof(double) * (ncl + 1));
+    const size_t o_k1w = off;  off = align256(off + sizeof(double) * (P.k1_w.size() + 1));
+    const size_t o_k1ev = off; off = align256(off + sizeof(int) * (P.k1_ev.size() + 1));
     std::vector<unsigned char> host(off, 0);
     auto cpy = [&](size_t o, const void *src, size_t bytes) {
         if (bytes) std::memcpy(host.data() + o, src, bytes);
@@ -240,6 +329,12 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     std::vector<float> d32(P.den.begin(), P.den.end()), cp32(P.cp.begin(), P.cp.end());
     cpy(o_d32, d32.data(), sizeof(float) * (n + 1));
     cpy(o_c32b, cp32.data(), sizeof(float) * (n + 1));
+    cpy(o_grp, P.grp.data(), sizeof(int2) * ngrp);
+    cpy(o_own, P.run_own.data(), sizeof(int) * nrun);
+    cpy(o_rec, P.k1_rec.data(), sizeof(int) * P.k1_rec.size());
+    cpy(o_wsum, P.cl_wsum.data(), sizeof(double) * ncl);
+    cpy(o_k1w, P.k1_w.data(), sizeof(double) * P.k1_w.size());
+    cpy(o_k1ev, P.k1_ev.data(), sizeof(int) * P.k1_ev.size());
     void *buf = nullptr;
     if (hipMalloc(&buf, off) != hipSuccess) {
         set_error("hipMalloc of a line plan failed");
@@ -269,6 +364,15 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.cp = reinterpret_cast<const double *>(b + o_cp);
     d.den32 = reinterpret_cast<const float *>(b + o_d32);
     d.cp32 = reinterpret_cast<const float *>(b + o_c32b);
+    d.max_m = P.max_m;
+    d.ngrp = ngrp;
+    d.k1_S = P.k1_S;
+    d.grp = reinterpret_cast<const int2 *>(b + o_grp);
+    d.run_own = reinterpret_cast<const int *>(b + o_own);
+    d.k1_rec = reinterpret_cast<const int *>(b + o_rec);
+    d.cl_wsum = reinterpret_cast<const double *>(b + o_wsum);
+    d.k1_w = reinterpret_cast<const double *>(b + o_k1w);
+    d.k1_ev = reinterpret_cast<const int *>(b + o_k1ev);
     PlanEntry e;
     e.buf = buf;
     e.dev = d;

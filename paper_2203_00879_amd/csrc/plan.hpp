@@ -31,7 +31,25 @@ struct LinePlanDev {
     const double *cp;      // [n] c'_k = alpha / den_k
     const float *den32;    // FP32 copies
     const float *cp32;
+    // ---- line-march tables (sweeps that stream along the line) ----
+    int max_m;             // longest run (unknowns)
+    int ngrp;              // run groups (consecutive runs marched by one thread)
+    int k1_S;              // closure accumulator slots (0: more than kMaxSlots needed)
+    const int2 *grp;       // [ngrp] (first run, one past the last run)
+    const int *run_own;    // [nrun] known rows whose R update this run makes: bit 0 lo, 1 hi,
+                           // 2 row 0, 3 row n-1
+    const int *k1_rec;     // [n * k1_S] per row j and slot s: -1 or q | t << 12 | flags (kRec*)
+    const double *k1_w;    // [n * k1_S] the tap coefficient C_{e,j} * h of that record (0 if none)
+    const int *k1_ev;      // [2n] per row j: [2j] bit s = slot s opens, bit 16+s = row j is
+                           // slot s's closure row; [2j+1] bit s = slot s closes
+    const double *cl_wsum; // [ncl] sum of the closure's taps (ascending order)
 };
+
+// Closure-slot record flags (line-march closure pass).
+constexpr int kRecOpen = 1 << 20;   // first tap: the reference value is this row's flux
+constexpr int kRecRow = 1 << 21;    // this row is the closure row e itself
+constexpr int kRecClose = 1 << 22;  // last tap: the closure value is complete
+constexpr int kMaxSlots = 16;
 
 // Host description (kept for tests and for building the device copy).
 struct LinePlanHost {
@@ -43,12 +61,25 @@ struct LinePlanHost {
     std::vector<double> cl_coef;      // ncl * kTaps
     std::vector<uint8_t> row_kind;
     std::vector<double> den, cp;
+    int max_m = 0, k1_S = 0;
+    std::vector<int2> grp;
+    std::vector<int> run_own, k1_rec, k1_ev;
+    std::vector<double> k1_w, cl_wsum;
 };
+
+// Run groups of the line-march sweeps: about kGroupRows rows, at most
+// kGroupRuns runs each.
+constexpr int kGroupRows = 128;
+constexpr int kGroupRuns = 4;
 
 // Build the plan of a line of n points cut into nseg user segments; each user
 // segment is further cut into pieces of at most sub_len points (0 = no extra cuts).
 // Returns false with an error message on invalid input.
 bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &out, std::string &err);
+
+// Kind of every row of a line of n points cut into nseg user segments and
+// pieces of at most sub_len points (host only; valid n, nseg assumed).
+std::vector<uint8_t> row_kinds(int n, int nseg, int sub_len);
 
 // Segment starts of an even split (the first n % nseg segments one point longer).
 std::vector<int> even_segments(int n, int nseg);

@@ -140,7 +140,11 @@ def nopcs_derivative(grid, direction, f, d1=None, d2=None, precision=FP64, strea
 
 
 def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):
-    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    """R = right-hand side of ge17 at Q.  ws: device workspace of
+    workspace_bytes(grid, precision) bytes; allocated here when not given."""
+    if ws is None:
+        ws = alloc_workspace(grid, precision, device=Q.device)
+    nbytes = ws.numel() * ws.element_size()
     _check(lib().nse_rhs(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(R), _ptr(ws),
                          nbytes, _stream(stream)))
 

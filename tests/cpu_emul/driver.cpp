@@ -3,6 +3,7 @@
 //   driver deriv nx ny nz sx sy sz lx ly lz dir  in out        (in: N, out: d1 then d2)
 //   driver rhs   nx ny nz sx sy sz lx ly lz viscous gravity in out   (in/out: 5N)
 //   driver rk    nx ny nz sx sy sz lx ly lz viscous gravity dt nsteps in out
+//   driver plan  n nseg piece_len                            (prints the line-march tables)
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction.
 #include <cstdio>
 #include <cstdlib>
@@ -11,6 +12,7 @@
 #include <vector>
 
 #include "../../include/nopcs.h"
+#include "../../paper_2203_00879_amd/csrc/plan.hpp"
 #include "hip/hip_runtime.h"
 
 // device-like buffers: guarded on both sides
@@ -35,8 +37,17 @@ static void write_raw(const char *path, const double *p, size_t n) {
 }
 
 int main(int argc, char **argv) {
-    if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
+    if (argc < 2) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
+    if (mode == "plan" && argc >= 5) {  // driver plan n nseg piece: line-march tables of one line plan
+        nopcs::LinePlanHost P;
+        std::string err;
+        if (!nopcs::build_line_plan(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), P, err)) return 1;
+        std::printf("nrun %zu ncl %zu max_m %d k1_S %d ngrp %zu\n", P.runs.size(), P.cl_row.size(), P.max_m, P.k1_S,
+                    P.grp.size());
+        return 0;
+    }
+    if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
     // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)
     if (const char *pc = std::getenv("NOPCS_EMUL_PIECE"))
         for (int d = 0; d < 3; ++d)
@@ -70,7 +81,9 @@ int main(int argc, char **argv) {
         std::vector<double> Qh = read_raw(argv[13], 5 * N);
         Buf Q(5 * N), R(5 * N);
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
-        rc = nse_rhs(&p, &g, NOPCS_FP64, Q.p, R.p, nullptr, 0, nullptr);
+        const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
+        Buf ws((wsb + 7) / 8);
+        rc = nse_rhs(&p, &g, NOPCS_FP64, Q.p, R.p, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[14], R.p, 5 * N);
     } else if (mode == "rk") {
         p.viscous = std::atoi(argv[11]);

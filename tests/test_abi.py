@@ -62,3 +62,16 @@ def test_invalid_arguments_rejected():
     pb = nopcs.make_params(bad)
     assert lib.nse_rhs(ctypes.byref(pb), ctypes.byref(g), 0, ctypes.c_void_p(8), ctypes.c_void_p(16), None, 0,
                        None) == -1
+    # the right-hand side needs the workspace too (closure array of the line-march sweeps)
+    assert lib.nse_rhs(ctypes.byref(p), ctypes.byref(g), 0, ctypes.c_void_p(256), ctypes.c_void_p(512), None, 0,
+                       None) == -1
+    assert b"workspace" in lib.nopcs_last_error()
+
+
+def test_workspace_includes_closure_array():
+    """Three 5-field states plus, for y and z, 5 components x closure rows x lines
+    (the larger of the two), 256-byte aligned."""
+    g = nopcs.make_grid((16, 16, 16), nseg=(1, 2, 3))
+    # y: 2 segments -> closure rows 7, 8; z: 3 segments of 6, 5, 5 -> rows 5, 6, 10, 11
+    clo = max(5 * 2 * 16 * 16, 5 * 4 * 16 * 16) * 8
+    assert nopcs.workspace_bytes(g) == 3 * 5 * 16 ** 3 * 8 + (clo + 255) // 256 * 256

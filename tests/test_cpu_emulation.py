@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("api.hip", "sweep.hip", "visc.hip", "plan.cpp")]
+    return [os.path.join(CSRC, f) for f in ("api.hip", "sweep.hip", "march.hip", "visc.hip", "plan.cpp")]
 
 
 @pytest.fixture(scope="module")
@@ -99,3 +99,20 @@ def test_emulated_rhs_tiles_bitwise(driver, tmp_path, shape, v, g):
     _run(driver, ["rhs", *shape, 1, 1, 1, *L, v, g, qin, rout], tmp_path, piece=0)
     R = np.fromfile(rout).reshape(Q.shape)
     assert np.array_equal(R, oracle.rhs(p, Q, L))
+
+
+@pytest.mark.parametrize("shape, nseg, piece", [((20, 72, 150), (1, 2, 3), 16), ((12, 40, 200), (1, 1, 2), -1)])
+def test_emulated_rhs_line_march_with_closures(driver, tmp_path, shape, nseg, piece):
+    """Lines along y and z long enough to be cut into pieces: the line-march
+    sweeps (closure pass with 16 or 8 accumulator slots, run march with one or
+    several run groups per line) against the oracle's global solve."""
+    p = dict(inputs.AIR)
+    Q = inputs.smooth_state(shape, seed=21)
+    qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
+    Q.tofile(qin)
+    L = (0.7, 1.3, 1.0)
+    _run(driver, ["rhs", *shape, *nseg, *L, 1, 1, qin, rout], tmp_path, piece=piece)
+    R = np.fromfile(rout).reshape(Q.shape)
+    Ro = oracle.rhs(p, Q, L)
+    for c in range(5):
+        assert _rel(R[c], Ro[c]) <= 1e-13, c
