@@ -86,6 +86,15 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
     const int tid = threadIdx.x;
     const int n = pl.n;
     const double ih = pl.ih;
+    // plan tables through the scalar path where the index is wave-uniform
+    const auto cl_row = NOPCS_SCALAR_PTR(int, pl.cl_row);
+    const auto cl_j0 = NOPCS_SCALAR_PTR(int, pl.cl_j0);
+    const auto cl_len = NOPCS_SCALAR_PTR(int, pl.cl_len);
+    const auto cl_coef = NOPCS_SCALAR_PTR(double, pl.cl_coef);
+    const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
+    const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
+    const auto den = NOPCS_SCALAR_PTR(double, pl.den);
+    const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
     // ---- A: known rows (walls and closures) ----
     const int nk = 4 + pl.ncl;
     for (int q = tid; q < C::P * nk; q += C::NT) {
@@ -111,8 +120,8 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             }
         } else {
             const int e = s - 4;
-            const int row = pl.cl_row[e], j0 = pl.cl_j0[e], len = pl.cl_len[e];
-            const double *coef = pl.cl_coef + (size_t)e * kTaps;
+            const int row = cl_row[e], j0 = cl_j0[e], len = cl_len[e];
+            const auto coef = cl_coef + (size_t)e * kTaps;
             double fe[NC], acc[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -134,8 +143,8 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
     for (int q = tid; q < C::P * pl.nrun; q += C::NT) {
         const int l = q % C::P, r = q / C::P;
         if (l >= np) continue;
-        const int2 run = pl.runs[r];
-        const int2 slot = pl.run_slot[r];
+        const int2 run = make_int2(runs_i[2 * r], runs_i[2 * r + 1]);
+        const int2 slot = make_int2(slot_i[2 * r], slot_i[2 * r + 1]);
         const int lo = run.x, hi = run.y, m = hi - lo - 1;
         double xlo[NC], xhi[NC], w0[NC], w1[NC], w2[NC], w3[NC], w4[NC], dprev[NC];
 #pragma unroll
@@ -152,7 +161,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         }
         for (int k = 1; k <= m; ++k) {
             const int i = lo + k;
-            const double den = pl.den[k];
+            const double dk = den[k];
             const int inext = i + 3;
             const bool more = inext <= hi + 1;
             const int ixn = C::fidx(l, more ? inext : i);
@@ -161,7 +170,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
                 double rr = ih * (kB1 * (w3[c] - w1[c]) + kB2 * (w4[c] - w0[c]));
                 if (k == 1) rr = rr - kAlpha * xlo[c];
                 if (k == m) rr = rr - kAlpha * xhi[c];
-                const double dp = (rr - kAlpha * dprev[c]) / den;
+                const double dp = (rr - kAlpha * dprev[c]) / dk;
                 const double fn = more ? F(c)[ixn] : 0.0;
                 F(c)[C::fidx(l, i)] = dp;
                 dprev[c] = dp;
@@ -174,7 +183,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         }
         for (int k = m - 1; k >= 1; --k) {
             const int ix = C::fidx(l, lo + k);
-            const double cpk = pl.cp[k];
+            const double cpk = cp[k];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const double x = F(c)[ix] - cpk * dprev[c];
@@ -190,7 +199,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
 template <int DIR, int NMAX>
 __device__ inline double lds_result(const double *Fb, const double *KNb, int c, const LinePlanDev &pl, int l, int i) {
     using C = SweepCfg<DIR, NMAX>;
-    const int s = pl.kslot[i];
+    const int s = NOPCS_SCALAR_PTR(short, pl.kslot)[i];
     return s < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(s, l)];
 }
 

@@ -93,15 +93,16 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     const long long col = indom ? gi + (long long)A.nx * gj : 0;
     double *const Pu = S, *const Pv = S + CNT, *const Pw = S + 2 * CNT, *const PT = S + 3 * CNT;
 
-    // raw state of one plane of this column (a benign dummy outside the box)
+    // raw state of one plane of this column (a benign dummy outside the box);
+    // the loads are unconditional (clamped address, select afterwards) so that
+    // no branch makes the compiler drain the loads in flight
     auto load = [&](int p, double q[5]) {
-        if (indom && p >= 0 && p < A.nz) {
-            const long long o = col + plane * p;
+        const bool in = indom && p >= 0 && p < A.nz;
+        const long long o = col + plane * min(max(p, 0), A.nz - 1);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) q[f] = Q[f * N3 + o];
-        } else {
-            q[0] = 1.0;
-            q[1] = q[2] = q[3] = q[4] = 0.0;
+        for (int f = 0; f < 5; ++f) {
+            const double v = Q[f * N3 + o];
+            q[f] = in ? v : (f == 0 ? 1.0 : 0.0);
         }
     };
     auto prim = [&](const double q[5], double &u, double &v, double &w, double &T) {
@@ -111,23 +112,26 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
         w = pr.w;
         T = pr.T;
     };
-    auto write_R = [&](int k, const double acc[4]) {
+    // R of plane k: the divergence plus the gravity source (rho and rho v of that plane)
+    auto write_R = [&](int k, const double acc[4], double rho, double my) {
         const long long o = col + plane * k;
         A.R[o] = 0.0;
         A.R[N3 + o] = acc[0];
-        A.R[2 * N3 + o] = acc[1] - c.ghat * Q[o];
+        A.R[2 * N3 + o] = acc[1] - c.ghat * rho;
         A.R[3 * N3 + o] = acc[2];
-        A.R[4 * N3 + o] = acc[3] - c.ghat * Q[2 * N3 + o];
+        A.R[4 * N3 + o] = acc[3] - c.ghat * my;
     };
 
     // planes whose node fluxes are needed: k0-1 .. k1, and nz-3 for the top wall
     const int kb = max(0, min(k0 - 1, A.nz - 3)), ke = min(A.nz - 1, k1);
     // window before the first shift: planes kb-2, kb-1, kb; raw state of kb+1
-    double wu[3], wv[3], ww[3], wT[3], raw[5];
+    double wu[3], wv[3], ww[3], wT[3], wr[3], wy[3], raw[5];
 #pragma unroll
     for (int s = 1; s < 3; ++s) {
         load(kb - 2 + s, raw);
         prim(raw, wu[s], wv[s], ww[s], wT[s]);
+        wr[s] = raw[0];
+        wy[s] = raw[2];
     }
     load(kb + 1, raw);
     // G history (planes k-2, k-1, k) and the pending dEv/dx + dFv/dy of plane k-1
@@ -144,8 +148,12 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             wv[s] = wv[s + 1];
             ww[s] = ww[s + 1];
             wT[s] = wT[s + 1];
+            wr[s] = wr[s + 1];
+            wy[s] = wy[s + 1];
         }
         prim(raw, wu[2], wv[2], ww[2], wT[2]);
+        wr[2] = raw[0];
+        wy[2] = raw[2];
         load(k + 2, raw);
         Pu[tid] = wu[1];
         Pv[tid] = wv[1];
@@ -223,7 +231,7 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
                 double acc[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[q] = partPrev[q] + d2c(G[0][q], G[2][q], A.ihz);
-                write_R(k - 1, acc);
+                write_R(k - 1, acc, wr[0], wy[0]);
             }
             // the bottom wall plane waits for G(0), G(1), G(2); its x-y part is
             // parked in R, where only this thread reads it back
@@ -236,14 +244,14 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     acc[q] = A.R[(q + 1) * N3 + col] + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
-                write_R(0, acc);
+                write_R(0, acc, Q[col], Q[2 * N3 + col]);
             }
             // the top wall plane nz-1 is finished with G(nz-1), G(nz-2), G(nz-3)
             if (k == A.nz - 1 && k < k1) {
                 double acc[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], A.ihz, true);
-                write_R(k, acc);
+                write_R(k, acc, wr[1], wy[1]);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) partPrev[q] = part[q];
