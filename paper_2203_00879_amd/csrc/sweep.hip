@@ -37,6 +37,8 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
     long long base;
     pencil_of<C>(g, np, base);
     const int n = g.n;
+    int ks[C::PTS];
+    owned_slots<DIR, NMAX>(pl, ks);
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, pl, l, i);
+            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, ks[s], l, i);
         }
     }
     if (d2) {
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, pl, l, i);
+            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, ks[s], l, i);
         }
     }
 }
@@ -81,8 +83,8 @@ namespace {
 
 template <int DIR, int NMAX, int C0, int NC>
 __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, int np,
-                                 long long base, double (&flux)[5][SweepCfg<DIR, NMAX>::PTS], double *F,
-                                 double *KN) {
+                                 long long base, double (&flux)[5][SweepCfg<DIR, NMAX>::PTS],
+                                 const int (&ks)[SweepCfg<DIR, NMAX>::PTS], double *F, double *KN) {
     using C = SweepCfg<DIR, NMAX>;
     const int n = g.n;
     const long long N3 = a.N3;
@@ -97,14 +99,16 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
     }
     __syncthreads();
     lds_line_solve<DIR, NMAX, NC>(F, KN, pl, np);
+    // R of the owned points; unconditional loads at clamped indices (no branch
+    // makes the compiler drain the loads in flight), unused values dropped
     double rv[NC][C::PTS];
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
         C::owned(threadIdx.x + s * C::NT, l, i);
-        const long long o = base + l * g.sA + i * g.sD;
+        const long long o = base + min(l, np - 1) * g.sA + min(i, n - 1) * g.sD;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) rv[c][s] = (l < np && i < n) ? a.R[(C0 + c) * N3 + o] : 0.0;
+        for (int c = 0; c < NC; ++c) rv[c][s] = a.R[(C0 + c) * N3 + o];
     }
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
@@ -114,7 +118,7 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
         const long long o = base + l * g.sA + i * g.sD;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            a.R[(C0 + c) * N3 + o] = rv[c][s] - lds_result<DIR, NMAX>(F, KN, c, pl, l, i);
+            a.R[(C0 + c) * N3 + o] = rv[c][s] - lds_result<DIR, NMAX>(F, KN, c, ks[s], l, i);
     }
 }
 
@@ -132,31 +136,30 @@ __global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, 
     const long long N3 = a.N3;
     const NdConst &c = a.c;
     // convective fluxes of the owned points (ge3-ge5), kept in registers
+    // (loads at clamped indices, unconditional: see nse_group; points outside
+    // the pencil are never stored)
     double flux[5][C::PTS];
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
         C::owned(threadIdx.x + s * C::NT, l, i);
-        if (l < np && i < n) {
-            const long long o = base + l * g.sA + i * g.sD;
-            const double rho = a.Qin[o], mx = a.Qin[N3 + o], my = a.Qin[2 * N3 + o], mz = a.Qin[3 * N3 + o],
-                         Ep = a.Qin[4 * N3 + o];
-            const Prim pr = prim_from(c, rho, mx, my, mz, Ep);
-            const double ud = DIR == 0 ? pr.u : DIR == 1 ? pr.v : pr.w;
-            flux[0][s] = DIR == 0 ? mx : DIR == 1 ? my : mz;
-            flux[1][s] = DIR == 0 ? mx * ud + pr.pp : mx * ud;
-            flux[2][s] = DIR == 1 ? my * ud + pr.pp : my * ud;
-            flux[3][s] = DIR == 2 ? mz * ud + pr.pp : mz * ud;
-            flux[4][s] = ((Ep + pr.pp) + c.H) * ud;
-        } else {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) flux[k][s] = 0.0;
-        }
+        const long long o = base + min(l, np - 1) * g.sA + min(i, n - 1) * g.sD;
+        const double rho = a.Qin[o], mx = a.Qin[N3 + o], my = a.Qin[2 * N3 + o], mz = a.Qin[3 * N3 + o],
+                     Ep = a.Qin[4 * N3 + o];
+        const Prim pr = prim_from(c, rho, mx, my, mz, Ep);
+        const double ud = DIR == 0 ? pr.u : DIR == 1 ? pr.v : pr.w;
+        flux[0][s] = DIR == 0 ? mx : DIR == 1 ? my : mz;
+        flux[1][s] = DIR == 0 ? mx * ud + pr.pp : mx * ud;
+        flux[2][s] = DIR == 1 ? my * ud + pr.pp : my * ud;
+        flux[3][s] = DIR == 2 ? mz * ud + pr.pp : mz * ud;
+        flux[4][s] = ((Ep + pr.pp) + c.H) * ud;
     }
+    int ks[C::PTS];
+    owned_slots<DIR, NMAX>(pl, ks);
     static_assert(C::G == 3, "component grouping below assumes groups {0,1,2} and {3,4}");
-    nse_group<DIR, NMAX, 0, 3>(a, g, pl, np, base, flux, F, KN);
+    nse_group<DIR, NMAX, 0, 3>(a, g, pl, np, base, flux, ks, F, KN);
     __syncthreads();
-    nse_group<DIR, NMAX, 3, 2>(a, g, pl, np, base, flux, F, KN);
+    nse_group<DIR, NMAX, 3, 2>(a, g, pl, np, base, flux, ks, F, KN);
 }
 
 // ---------------------------------------------------------------------------

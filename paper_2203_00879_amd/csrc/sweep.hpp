@@ -139,68 +139,71 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         }
     }
     __syncthreads();
-    // ---- C: B f and Thomas on every run ----
-    for (int q = tid; q < C::P * pl.nrun; q += C::NT) {
-        const int l = q % C::P, r = q / C::P;
+    // ---- C: B f and Thomas on every run, one thread per (component, line, run) ----
+    for (int q = tid; q < NC * C::P * pl.nrun; q += C::NT) {
+        const int c = q / (C::P * pl.nrun), rest = q - c * (C::P * pl.nrun);
+        const int l = rest % C::P, r = rest / C::P;
         if (l >= np) continue;
+        double *f = F(c);
+        const double *kn = KN(c);
         const int2 run = make_int2(runs_i[2 * r], runs_i[2 * r + 1]);
         const int2 slot = make_int2(slot_i[2 * r], slot_i[2 * r + 1]);
         const int lo = run.x, hi = run.y, m = hi - lo - 1;
-        double xlo[NC], xhi[NC], w0[NC], w1[NC], w2[NC], w3[NC], w4[NC], dprev[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            xlo[c] = KN(c)[C::kidx(slot.x, l)];
-            xhi[c] = KN(c)[C::kidx(slot.y, l)];
-            // window f_{i-2} .. f_{i+2} at i = lo + 1; rows past hi + 1 are never used
-            w0[c] = F(c)[C::fidx(l, lo - 1)];
-            w1[c] = F(c)[C::fidx(l, lo)];
-            w2[c] = F(c)[C::fidx(l, lo + 1)];
-            w3[c] = F(c)[C::fidx(l, lo + 2)];
-            w4[c] = lo + 3 <= hi + 1 ? F(c)[C::fidx(l, lo + 3)] : 0.0;
-            dprev[c] = 0.0;
-        }
+        const double xlo = kn[C::kidx(slot.x, l)];
+        const double xhi = kn[C::kidx(slot.y, l)];
+        // window f_{i-2} .. f_{i+2} at i = lo + 1; rows past hi + 1 are never used
+        double w0 = f[C::fidx(l, lo - 1)];
+        double w1 = f[C::fidx(l, lo)];
+        double w2 = f[C::fidx(l, lo + 1)];
+        double w3 = f[C::fidx(l, lo + 2)];
+        double w4 = lo + 3 <= hi + 1 ? f[C::fidx(l, lo + 3)] : 0.0;
+        double dprev = 0.0;
         for (int k = 1; k <= m; ++k) {
             const int i = lo + k;
             const double dk = den[k];
             const int inext = i + 3;
             const bool more = inext <= hi + 1;
-            const int ixn = C::fidx(l, more ? inext : i);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                double rr = ih * (kB1 * (w3[c] - w1[c]) + kB2 * (w4[c] - w0[c]));
-                if (k == 1) rr = rr - kAlpha * xlo[c];
-                if (k == m) rr = rr - kAlpha * xhi[c];
-                const double dp = (rr - kAlpha * dprev[c]) / dk;
-                const double fn = more ? F(c)[ixn] : 0.0;
-                F(c)[C::fidx(l, i)] = dp;
-                dprev[c] = dp;
-                w0[c] = w1[c];
-                w1[c] = w2[c];
-                w2[c] = w3[c];
-                w3[c] = w4[c];
-                w4[c] = fn;
-            }
+            double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+            if (k == 1) rr = rr - kAlpha * xlo;
+            if (k == m) rr = rr - kAlpha * xhi;
+            const double dp = (rr - kAlpha * dprev) / dk;
+            const double fn = more ? f[C::fidx(l, inext)] : 0.0;
+            f[C::fidx(l, i)] = dp;
+            dprev = dp;
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            w3 = w4;
+            w4 = fn;
         }
         for (int k = m - 1; k >= 1; --k) {
             const int ix = C::fidx(l, lo + k);
-            const double cpk = cp[k];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double x = F(c)[ix] - cpk * dprev[c];
-                F(c)[ix] = x;
-                dprev[c] = x;
-            }
+            const double x = f[ix] - cp[k] * dprev;
+            f[ix] = x;
+            dprev = x;
         }
     }
     __syncthreads();
 }
 
-// f' of component c at (l, i) after lds_line_solve
+// f' of component c at (l, i) after lds_line_solve; ks = pl.kslot[i] (the
+// known-row slot of row i, -1 for a compact row), read once by the caller
 template <int DIR, int NMAX>
-__device__ inline double lds_result(const double *Fb, const double *KNb, int c, const LinePlanDev &pl, int l, int i) {
+__device__ inline double lds_result(const double *Fb, const double *KNb, int c, int ks, int l, int i) {
     using C = SweepCfg<DIR, NMAX>;
-    const int s = NOPCS_SCALAR_PTR(short, pl.kslot)[i];
-    return s < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(s, l)];
+    return ks < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(ks, l)];
+}
+
+// known-row slots of a thread's owned points (clamped index: always a valid read)
+template <int DIR, int NMAX>
+__device__ inline void owned_slots(const LinePlanDev &pl, int ks[SweepCfg<DIR, NMAX>::PTS]) {
+    using C = SweepCfg<DIR, NMAX>;
+#pragma unroll
+    for (int s = 0; s < C::PTS; ++s) {
+        int l, i;
+        C::owned(threadIdx.x + s * C::NT, l, i);
+        ks[s] = pl.kslot[min(i, pl.n - 1)];
+    }
 }
 
 }  // namespace nopcs
