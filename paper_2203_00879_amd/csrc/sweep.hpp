@@ -95,48 +95,34 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
     const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
     const auto den = NOPCS_SCALAR_PTR(double, pl.den);
     const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
-    // ---- A: known rows (walls and closures) ----
+    // ---- A: known rows (walls and closures), one thread per (component, line, row) ----
     const int nk = 4 + pl.ncl;
-    for (int q = tid; q < C::P * nk; q += C::NT) {
-        const int l = q % C::P, s = q / C::P;
+    for (int q = tid; q < NC * C::P * nk; q += C::NT) {
+        const int c = q / (C::P * nk), rest = q - c * (C::P * nk);
+        const int l = rest % C::P, s = rest / C::P;
         if (l >= np) continue;
-        if (s < 4) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double *f = F(c);
-                double v;
-                if (s == 0) {
-                    const double f0 = f[C::fidx(l, 0)];
-                    v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
-                } else if (s == 1) {
-                    v = 0.5 * ih * (f[C::fidx(l, 2)] - f[C::fidx(l, 0)]);
-                } else if (s == 2) {
-                    v = 0.5 * ih * (f[C::fidx(l, n - 1)] - f[C::fidx(l, n - 3)]);
-                } else {
-                    const double fl = f[C::fidx(l, n - 1)];
-                    v = -0.5 * ih * (4.0 * (f[C::fidx(l, n - 2)] - fl) - (f[C::fidx(l, n - 3)] - fl));
-                }
-                KN(c)[C::kidx(s, l)] = v;
-            }
+        const double *f = F(c);
+        double v;
+        if (s == 0) {
+            const double f0 = f[C::fidx(l, 0)];
+            v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
+        } else if (s == 1) {
+            v = 0.5 * ih * (f[C::fidx(l, 2)] - f[C::fidx(l, 0)]);
+        } else if (s == 2) {
+            v = 0.5 * ih * (f[C::fidx(l, n - 1)] - f[C::fidx(l, n - 3)]);
+        } else if (s == 3) {
+            const double fl = f[C::fidx(l, n - 1)];
+            v = -0.5 * ih * (4.0 * (f[C::fidx(l, n - 2)] - fl) - (f[C::fidx(l, n - 3)] - fl));
         } else {
             const int e = s - 4;
             const int row = cl_row[e], j0 = cl_j0[e], len = cl_len[e];
             const auto coef = cl_coef + (size_t)e * kTaps;
-            double fe[NC], acc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                fe[c] = F(c)[C::fidx(l, row)];
-                acc[c] = 0.0;
-            }
-            for (int t = 0; t < len; ++t) {
-                const double w = coef[t];
-                const int ix = C::fidx(l, j0 + t);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] += w * (F(c)[ix] - fe[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) KN(c)[C::kidx(s, l)] = acc[c] * ih;
+            const double fe = f[C::fidx(l, row)];
+            double acc = 0.0;
+            for (int t = 0; t < len; ++t) acc += coef[t] * (f[C::fidx(l, j0 + t)] - fe);
+            v = acc * ih;
         }
+        KN(c)[C::kidx(s, l)] = v;
     }
     __syncthreads();
     // ---- C: B f and Thomas on every run, one thread per (component, line, run) ----

@@ -79,6 +79,19 @@ inline dim3 gridDim, blockDim;
 inline thread_local std::barrier<> *emu_bar = nullptr;
 inline void __syncthreads() { emu_bar->arrive_and_wait(); }
 
+// Lane exchange inside a 64-wide wavefront: every thread of the block must call
+// it the same number of times (as every lane of a wavefront does on the GPU).
+inline double emu_shfl_buf[1024];
+inline double __shfl_xor(double v, int mask, int width = 64) {
+    const unsigned t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    emu_shfl_buf[t] = v;
+    emu_bar->arrive_and_wait();
+    const unsigned lane = t % (unsigned)width, src = t - lane + ((lane ^ (unsigned)mask) % (unsigned)width);
+    const double r = emu_shfl_buf[src];
+    emu_bar->arrive_and_wait();
+    return r;
+}
+
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
 typedef void *hipStream_t;
