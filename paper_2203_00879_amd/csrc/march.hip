@@ -54,43 +54,49 @@ __device__ inline double flux_row(const double (*L)[MW], int lane, int comp, con
     return L[comp][lane] * ud;
 }
 
-// Rows [row0, rowN] of the block's 64 lines pass through a two-chunk LDS ring.
+// Rows [row0, rowN] of the block's 64 lines pass through a two-chunk LDS ring
+// and are read strictly in order through next().
 struct RowPipe {
     double (*L)[CH][NCOMP][MW];   // [2][CH][field][lane]
     const double *src;            // this wavefront's field at row 0 of its line (a valid
                                   // address also for lanes past the last line)
     long long sD;
     int row0, rowN, lane, field;
+    int u, k;                     // next row to read: slot u of chunk k
     double pre[CH];               // next chunk, in flight
     // unconditional loads (no branches: the compiler's memory waits stay
     // precise); rows past rowN repeat row rowN and are never used
     __device__ void fetch(int rb) {
 #pragma unroll
-        for (int u = 0; u < CH; ++u) pre[u] = src[sD * min(rb + u, rowN)];
+        for (int v = 0; v < CH; ++v) pre[v] = src[sD * min(rb + v, rowN)];
     }
     __device__ void publish(int buf) {
 #pragma unroll
-        for (int u = 0; u < CH; ++u) L[buf][u][field][lane] = pre[u];
+        for (int v = 0; v < CH; ++v) L[buf][v][field][lane] = pre[v];
     }
     // before the first read: chunk 0 in LDS, chunk 1 in flight
     __device__ void start() {
         fetch(row0);
         publish(0);
         fetch(row0 + CH);
+        u = 0;
+        k = 0;
         __syncthreads();
     }
-    // staged fields of row r (rows are read in increasing order; the first
-    // read of a chunk k >= 1 publishes it and starts fetching chunk k + 1)
-    __device__ const double (*row(int r))[MW] {
-        const int rel = r - row0, k = rel / CH, u = rel - k * CH;
-        if (u == 0 && k > 0) {
+    // staged fields of the next row; the first read of chunk k >= 1 publishes
+    // it and starts fetching chunk k + 1 (uniform: every wavefront of the
+    // block reads the same rows)
+    __device__ const double (*next())[MW] {
+        if (u == CH) {
+            u = 0;
+            ++k;
             publish(k & 1);
             __syncthreads();
             fetch(row0 + (k + 1) * CH);
         }
-        NOPCS_LDS_BOUND(rel, rowN - row0 + 1 + CH);
         NOPCS_LDS_BOUND(u, CH);
-        return L[k & 1][u];
+        NOPCS_LDS_BOUND(k * CH + u, rowN - row0 + 1 + CH);
+        return L[k & 1][u++];
     }
 };
 
@@ -126,7 +132,8 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
     P.lane = lane;
     P.field = comp;
     P.start();
-    const auto k1_ev = NOPCS_SCALAR_PTR(int, pl.k1_ev);
+    const auto ev_row = NOPCS_SCALAR_PTR(int, pl.k1_evrow);
+    const auto ev_msk = NOPCS_SCALAR_PTR(int, pl.k1_evmask);
     double acc[S], fr[S], fe[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -134,36 +141,41 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
         fr[s] = 0.0;
         fe[s] = 0.0;
     }
-    // every slot accumulates every row (inactive slots carry a zero tap, which
-    // leaves the sum unchanged); the rare slot events take one uniform branch
-    for (int j = jlo; j <= jhi; ++j) {
-        const double f = flux_row<DIR>(P.row(j), lane, comp, c);
+    // every slot accumulates every row (an idle slot carries a zero tap, which
+    // leaves its sum unchanged); slots open, meet their closure row and close
+    // only on the listed event rows, handled outside the plain row loop
+    auto accumulate = [&](int j, double f) {
         const auto wj = k1_w + (size_t)j * S;
-        const int ev = k1_ev[2 * j];
-        if (ev) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (ev & (1 << s)) {
-                    fr[s] = f;
-                    acc[s] = 0.0;
-                }
-                if (ev & (1 << (16 + s))) fe[s] = f;
-            }
-        }
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] += wj[s] * (f - fr[s]);
-        const int evc = k1_ev[2 * j + 1];
-        if (evc) {
+    };
+    int j = jlo;
+    for (int e = 0; e < pl.k1_nev; ++e) {
+        const int je = ev_row[e];
+        for (; j < je; ++j) accumulate(j, flux_row<DIR>(P.next(), lane, comp, c));
+        const double f = flux_row<DIR>(P.next(), lane, comp, c);
+        const int open = ev_msk[3 * e], erow = ev_msk[3 * e + 1], close = ev_msk[3 * e + 2];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (open & (1 << s)) {
+                fr[s] = f;
+                acc[s] = 0.0;
+            }
+            if (erow & (1 << s)) fe[s] = f;
+        }
+        accumulate(j, f);
+        if (close) {
             const auto rec = k1_rec + (size_t)j * S;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (evc & (1 << s)) {
+                if (close & (1 << s)) {
                     const int qi = rec[s] & 0xfff;
                     const double v = (acc[s] - (fe[s] - fr[s]) * cl_wsum[qi]) * pl.ih;
                     if (ok) clo[((long long)comp * pl.ncl + qi) * nlines + line] = v;
                 }
             }
         }
+        ++j;
     }
 }
 
@@ -223,17 +235,17 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
 
     // window: w0..w4 = f(i-2) .. f(i+2) for the row i about to be solved
     int i = lo0 + 1;
-    double w0 = flux_row<DIR>(P.row(i - 2), lane, comp, c);
-    double w1 = flux_row<DIR>(P.row(i - 1), lane, comp, c);
-    double w2 = flux_row<DIR>(P.row(i), lane, comp, c);
-    double w3 = flux_row<DIR>(P.row(i + 1), lane, comp, c);
-    double w4 = flux_row<DIR>(P.row(i + 2), lane, comp, c);
+    double w0 = flux_row<DIR>(P.next(), lane, comp, c);
+    double w1 = flux_row<DIR>(P.next(), lane, comp, c);
+    double w2 = flux_row<DIR>(P.next(), lane, comp, c);
+    double w3 = flux_row<DIR>(P.next(), lane, comp, c);
+    double w4 = flux_row<DIR>(P.next(), lane, comp, c);
     auto advance = [&]() {
         w0 = w1;
         w1 = w2;
         w2 = w3;
         w3 = w4;
-        w4 = flux_row<DIR>(P.row(i + 3), lane, comp, c);   // a dummy past the group's last row
+        w4 = flux_row<DIR>(P.next(), lane, comp, c);   // row i + 3 (a dummy past the group's last row)
         ++i;
     };
 

@@ -219,7 +219,7 @@ void build_march_tables(LinePlanHost &P) {
     P.k1_S = !fits ? 0 : (nslot <= 8 ? 8 : kMaxSlots);
     P.k1_rec.assign((size_t)n * std::max(P.k1_S, 1), -1);
     P.k1_w.assign((size_t)n * std::max(P.k1_S, 1), 0.0);
-    P.k1_ev.assign(2 * (size_t)n, 0);
+    std::vector<int> ev(3 * (size_t)n, 0);
     if (P.k1_S > 0) {
         for (int q = 0; q < ncl; ++q) {
             for (int t = 0; t < P.cl_len[q]; ++t) {
@@ -229,13 +229,20 @@ void build_march_tables(LinePlanHost &P) {
                 if (j == P.cl_row[q]) rec |= kRecRow;
                 if (t == P.cl_len[q] - 1) rec |= kRecClose;
                 P.k1_rec[(size_t)j * P.k1_S + slot_of[q]] = rec;
-                if (rec & kRecOpen) P.k1_ev[2 * (size_t)j] |= 1 << slot_of[q];
-                if (rec & kRecRow) P.k1_ev[2 * (size_t)j] |= 1 << (16 + slot_of[q]);
-                if (rec & kRecClose) P.k1_ev[2 * (size_t)j + 1] |= 1 << slot_of[q];
+                const int m3[3] = {rec & kRecOpen, rec & kRecRow, rec & kRecClose};
+                for (int x = 0; x < 3; ++x)
+                    if (m3[x]) ev[3 * (size_t)j + x] |= 1 << slot_of[q];
                 P.k1_w[(size_t)j * P.k1_S + slot_of[q]] = P.cl_coef[(size_t)q * kTaps + t];
             }
         }
     }
+    P.k1_evrow.clear();
+    P.k1_evmask.clear();
+    for (int j = 0; j < n; ++j)
+        if (ev[3 * (size_t)j] | ev[3 * (size_t)j + 1] | ev[3 * (size_t)j + 2]) {
+            P.k1_evrow.push_back(j);
+            for (int x = 0; x < 3; ++x) P.k1_evmask.push_back(ev[3 * (size_t)j + x]);
+        }
     P.cl_wsum.assign(ncl, 0.0);
     for (int q = 0; q < ncl; ++q) {
         double w = 0.0;
@@ -309,7 +316,8 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     const size_t o_rec = off;  off = align256(off + sizeof(int) * (P.k1_rec.size() + 1));
     const size_t o_wsum = off; off = align256(off + sizeof(double) * (ncl + 1));
     const size_t o_k1w = off;  off = align256(off + sizeof(double) * (P.k1_w.size() + 1));
-    const size_t o_k1ev = off; off = align256(off + sizeof(int) * (P.k1_ev.size() + 1));
+    const size_t o_evr = off;  off = align256(off + sizeof(int) * (P.k1_evrow.size() + 1));
+    const size_t o_evm = off;  off = align256(off + sizeof(int) * (P.k1_evmask.size() + 1));
     std::vector<unsigned char> host(off, 0);
     auto cpy = [&](size_t o, const void *src, size_t bytes) {
         if (bytes) std::memcpy(host.data() + o, src, bytes);
@@ -334,7 +342,8 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     cpy(o_rec, P.k1_rec.data(), sizeof(int) * P.k1_rec.size());
     cpy(o_wsum, P.cl_wsum.data(), sizeof(double) * ncl);
     cpy(o_k1w, P.k1_w.data(), sizeof(double) * P.k1_w.size());
-    cpy(o_k1ev, P.k1_ev.data(), sizeof(int) * P.k1_ev.size());
+    cpy(o_evr, P.k1_evrow.data(), sizeof(int) * P.k1_evrow.size());
+    cpy(o_evm, P.k1_evmask.data(), sizeof(int) * P.k1_evmask.size());
     void *buf = nullptr;
     if (hipMalloc(&buf, off) != hipSuccess) {
         set_error("hipMalloc of a line plan failed");
@@ -372,7 +381,9 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.k1_rec = reinterpret_cast<const int *>(b + o_rec);
     d.cl_wsum = reinterpret_cast<const double *>(b + o_wsum);
     d.k1_w = reinterpret_cast<const double *>(b + o_k1w);
-    d.k1_ev = reinterpret_cast<const int *>(b + o_k1ev);
+    d.k1_nev = (int)P.k1_evrow.size();
+    d.k1_evrow = reinterpret_cast<const int *>(b + o_evr);
+    d.k1_evmask = reinterpret_cast<const int *>(b + o_evm);
     PlanEntry e;
     e.buf = buf;
     e.dev = d;

@@ -40,8 +40,9 @@ struct LinePlanDev {
                            // 2 row 0, 3 row n-1
     const int *k1_rec;     // [n * k1_S] per row j and slot s: -1 or q | t << 12 | flags (kRec*)
     const double *k1_w;    // [n * k1_S] the tap coefficient C_{e,j} * h of that record (0 if none)
-    const int *k1_ev;      // [2n] per row j: [2j] bit s = slot s opens, bit 16+s = row j is
-                           // slot s's closure row; [2j+1] bit s = slot s closes
+    int k1_nev;            // rows with slot events (in order)
+    const int *k1_evrow;   // [k1_nev] those rows
+    const int *k1_evmask;  // [3 k1_nev] bit s: slot s opens / meets its closure row / closes there
     const double *cl_wsum; // [ncl] sum of the closure's taps (ascending order)
 };
 
@@ -63,7 +64,7 @@ struct LinePlanHost {
     std::vector<double> den, cp;
     int max_m = 0, k1_S = 0;
     std::vector<int2> grp;
-    std::vector<int> run_own, k1_rec, k1_ev;
+    std::vector<int> run_own, k1_rec, k1_evrow, k1_evmask;
     std::vector<double> k1_w, cl_wsum;
 };
 
