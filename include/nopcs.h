@@ -161,7 +161,7 @@ int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, con
  * density evolved by continuity; E' from the equation of state.  Faces are
  * treated in the order x, y, z.
  *
- * Q: device state, in/out.  ws: device workspace of at least
+ * Q: device state, in/out, 16-byte aligned.  ws: device workspace of at least
  * nopcs_workspace_bytes(grid, precision) bytes, 256-byte aligned.
  */
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,

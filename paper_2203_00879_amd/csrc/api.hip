@@ -272,6 +272,7 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
     if (precision != NOPCS_FP64) { set_error("rk_step: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
     if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
+    if (((uintptr_t)Q & 15) != 0) { set_error("Q must be 16-byte aligned"); return NOPCS_EINVAL; }
     if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
     if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
     if (!check_ws(grid, precision, ws, ws_bytes)) return NOPCS_EINVAL;

@@ -163,35 +163,83 @@ __global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, 
 }
 
 // ---------------------------------------------------------------------------
+// RK4 register update
+// ---------------------------------------------------------------------------
+namespace {
+// one element: the stage's register updates, k = R
+template <int STAGE>
+__device__ inline void rk_elem(double kv, double &K, double &Qs, double &Qn, const NseSweepArgs &a) {
+    if (STAGE == 0) {
+        K = kv;
+        Qs = Qn + a.half_dt * kv;
+    } else if (STAGE == 1) {
+        K = K + 2.0 * kv;
+        Qs = Qn + a.half_dt * kv;
+    } else if (STAGE == 2) {
+        K = K + 2.0 * kv;
+        Qs = Qn + a.dt * kv;
+    } else {
+        Qn = Qn + a.sixth_dt * (K + kv);
+    }
+}
+
+// two neighbouring elements per thread and iteration (16-byte accesses); the
+// registers must be 16-byte aligned, an odd tail element is done separately
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long total) {
+    const long long npair = total >> 1;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const double2 *R2 = reinterpret_cast<const double2 *>(a.R);
+    double2 *K2 = reinterpret_cast<double2 *>(a.K);
+    double2 *S2 = reinterpret_cast<double2 *>(a.Qs);
+    double2 *N2 = reinterpret_cast<double2 *>(a.Qn);
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += stride) {
+        const double2 kv = R2[p];
+        double2 kk = STAGE == 0 ? make_double2(0.0, 0.0) : K2[p];
+        double2 qn = N2[p];
+        double2 qs;
+        rk_elem<STAGE>(kv.x, kk.x, qs.x, qn.x, a);
+        rk_elem<STAGE>(kv.y, kk.y, qs.y, qn.y, a);
+        if (STAGE < 3) {
+            K2[p] = kk;
+            S2[p] = qs;
+        } else {
+            N2[p] = qn;
+        }
+    }
+    if ((total & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const long long o = total - 1;
+        double kk = STAGE == 0 ? 0.0 : a.K[o], qs = 0.0, qn = a.Qn[o];
+        rk_elem<STAGE>(a.R[o], kk, qs, qn, a);
+        if (STAGE < 3) {
+            a.K[o] = kk;
+            a.Qs[o] = qs;
+        } else {
+            a.Qn[o] = qn;
+        }
+    }
+}
+}  // namespace
+
 // Classical RK4 register update of one stage (Section 4), point-wise over the
 // 5 fields:  k = R;  stage 0: K = k, Qs = Qn + dt/2 k;  stage 1: K += 2k,
 // Qs = Qn + dt/2 k;  stage 2: K += 2k, Qs = Qn + dt k;  stage 3:
 // Qn = Qn + dt/6 (K + k).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long total) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += stride) {
-        const double kv = a.R[o];
-        if (a.stage == 0) {
-            a.K[o] = kv;
-            a.Qs[o] = a.Qn[o] + a.half_dt * kv;
-        } else if (a.stage == 1) {
-            a.K[o] = a.K[o] + 2.0 * kv;
-            a.Qs[o] = a.Qn[o] + a.half_dt * kv;
-        } else if (a.stage == 2) {
-            a.K[o] = a.K[o] + 2.0 * kv;
-            a.Qs[o] = a.Qn[o] + a.dt * kv;
-        } else {
-            a.Qn[o] = a.Qn[o] + a.sixth_dt * (a.K[o] + kv);
-        }
-    }
-}
-
 hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st) {
     const long long total = 5 * a.N3;
-    long long blocks = (total + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    hipLaunchKernelGGL(k_rk_update, dim3((unsigned)blocks), dim3(256), 0, st, a, total);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(a.R) | reinterpret_cast<uintptr_t>(a.K) |
+                           reinterpret_cast<uintptr_t>(a.Qs) | reinterpret_cast<uintptr_t>(a.Qn)) & 15) == 0;
+    if (!aligned) return hipErrorInvalidValue;   // the library's own buffers are 256-byte aligned
+    long long blocks = ((total >> 1) + 255) / 256;
+    if (blocks > 256 * 32) blocks = 256 * 32;
+    if (blocks < 1) blocks = 1;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (a.stage) {
+        case 0: hipLaunchKernelGGL(k_rk_update<0>, g, b, 0, st, a, total); break;
+        case 1: hipLaunchKernelGGL(k_rk_update<1>, g, b, 0, st, a, total); break;
+        case 2: hipLaunchKernelGGL(k_rk_update<2>, g, b, 0, st, a, total); break;
+        default: hipLaunchKernelGGL(k_rk_update<3>, g, b, 0, st, a, total); break;
+    }
     return hipGetLastError();
 }
 

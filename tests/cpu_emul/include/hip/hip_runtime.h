@@ -73,6 +73,10 @@ struct int2 {
     int x, y;
 };
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
+struct alignas(16) double2 {
+    double x, y;
+};
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
 
 inline thread_local dim3 threadIdx, blockIdx;
 inline dim3 gridDim, blockDim;

@@ -58,6 +58,10 @@ def test_invalid_arguments_rejected():
     assert lib.rk_step(ctypes.byref(p), ctypes.byref(g), 0, ctypes.c_void_p(256), 1e-5, 1, ctypes.c_void_p(256),
                        ws - 8, None) == -1
     assert lib.rk_step(ctypes.byref(p), ctypes.byref(g), 0, None, 1e-5, 1, ctypes.c_void_p(256), ws, None) == -1
+    # misaligned state (the RK register update moves 16 bytes at a time)
+    assert lib.rk_step(ctypes.byref(p), ctypes.byref(g), 0, ctypes.c_void_p(264), 1e-5, 1, ctypes.c_void_p(256), ws,
+                       None) == -1
+    assert b"aligned" in lib.nopcs_last_error()
     bad = dict(inputs.AIR, gamma=0.9)
     pb = nopcs.make_params(bad)
     assert lib.nse_rhs(ctypes.byref(pb), ctypes.byref(g), 0, ctypes.c_void_p(8), ctypes.c_void_p(16), None, 0,

@@ -31,7 +31,7 @@ def driver():
     deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
     if not os.path.exists(BIN) or os.path.getmtime(BIN) < max(os.path.getmtime(d) for d in deps):
         cmd = ["g++", "-std=c++20", "-O1", "-g", "-DNOPCS_CPU_EMUL", "-fsanitize=address,undefined",
-               "-fno-omit-frame-pointer", "-ffp-contract=off", "-pthread", "-I", os.path.join(EMU, "include"),
+               "-fno-omit-frame-pointer", "-fno-strict-aliasing", "-ffp-contract=off", "-pthread", "-I", os.path.join(EMU, "include"),
                "-x", "c++"] + _sources() + [os.path.join(EMU, "driver.cpp"), "-o", BIN + ".tmp"]
         subprocess.check_call(cmd)
         os.replace(BIN + ".tmp", BIN)
