@@ -186,6 +186,56 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
 int nopcs_set_piece_length(int32_t dir, int32_t piece_len);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of many boxes on one GPU.                    */
+/* ------------------------------------------------------------------------ */
+typedef struct nopcs_solver nopcs_solver;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* device bytes the solver may hold for resident requests */
+    int32_t max_slots;       /* maximum requests resident on the device at once */
+    int32_t max_queue;       /* maximum requests waiting for admission */
+    int32_t device;          /* HIP device ordinal */
+} solver_config;
+
+typedef struct {
+    nse_params params;
+    nopcs_grid grid;
+    int32_t nsteps;          /* RK4 steps to run, >= 1 */
+    int32_t precision;       /* NOPCS_FP64 or NOPCS_MIXED */
+    double dt;               /* fixed non-dimensional step, > 0 */
+    const double *Q0_host;   /* initial state, host, 5*n0*n1*n2 doubles; copied at submit */
+} solve_request;
+
+typedef struct {
+    int32_t status;          /* NOPCS_OK, NOPCS_EAGAIN or an error */
+    int32_t steps_done;
+    double t_submit, t_admit, t_done; /* seconds on the solver's monotonic clock */
+} solve_result;
+
+/* Create a solver: one stream per slot (default priority) and a worker thread that
+ * admits queued requests in arrival order while a slot is free and their device
+ * footprint (state + nopcs_workspace_bytes) fits hbm_budget_bytes, and keeps every
+ * resident request advancing in chunks of RK4 steps on its own stream (continuous
+ * batching; a request's arithmetic is that of rk_step on its box alone).  Serves the
+ * FP64 path.  *out is owned by the caller until solver_destroy. */
+int solver_create(const solver_config *cfg, nopcs_solver **out);
+
+/* Queue a request (non-blocking; the initial state is copied).  NOPCS_EBUSY if the
+ * queue is full; NOPCS_ENOMEM if the request alone exceeds the HBM budget. */
+int solver_submit(nopcs_solver *s, const solve_request *req, uint64_t *id_out);
+
+/* NOPCS_EAGAIN while pending; once finished, copies the final state into Q_out_host
+ * (5*n0*n1*n2 doubles, may be NULL), fills *out, releases the request and returns
+ * its status (NOPCS_OK or NOPCS_ENONFINITE).  Unknown / released id: NOPCS_ENOTFOUND. */
+int solver_poll(nopcs_solver *s, uint64_t id, double *Q_out_host, solve_result *out);
+
+/* Seconds on the solver's monotonic clock (the clock of solve_result). */
+double solver_now(nopcs_solver *s);
+
+/* Stop the admission thread, drop pending requests and free device memory. */
+int solver_destroy(nopcs_solver *s);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (instrumentation).                                           */
 /* ------------------------------------------------------------------------ */
 enum {

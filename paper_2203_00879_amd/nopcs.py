@@ -85,6 +85,10 @@ def lib():
             L.solver_create.argtypes = [ctypes.POINTER(SolverConfig), ctypes.POINTER(_V)]
             L.solver_submit.argtypes = [_V, ctypes.POINTER(SolveRequest), ctypes.POINTER(ctypes.c_uint64)]
             L.solver_poll.argtypes = [_V, ctypes.c_uint64, _V, ctypes.POINTER(SolveResult)]
+            L.solver_create.restype = _I
+            L.solver_submit.restype = _I
+            L.solver_poll.restype = _I
+            L.solver_destroy.restype = _I
             L.solver_destroy.argtypes = [_V]
             L.solver_now.argtypes = [_V]
             L.solver_now.restype = ctypes.c_double
@@ -161,3 +165,58 @@ def alloc_workspace(grid, precision=FP64, device="cuda"):
     if nb == 0:
         raise NopcsError(NOPCS_EINVAL, last_error())
     return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+class Solver:
+    """Serving runtime (solver_create / submit / poll / destroy of include/nopcs.h).
+
+    submit() copies the host initial state; poll() returns (status, result, Q)
+    where status is NOPCS_EAGAIN while the request is pending.  Q is a new
+    numpy array holding the final state once done."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=4, max_queue=1024, device=0):
+        cfg = SolverConfig(int(hbm_budget_bytes), int(max_slots), int(max_queue), int(device))
+        h = ctypes.c_void_p()
+        _check(lib().solver_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, params, grid, Q0, nsteps, dt, precision=FP64):
+        import numpy as np
+        q = np.ascontiguousarray(Q0, dtype=np.float64)
+        n = grid.n[0] * grid.n[1] * grid.n[2]
+        if q.size != 5 * n:
+            raise ValueError("Q0 must hold 5*n0*n1*n2 doubles")
+        req = SolveRequest(params, grid, int(nsteps), int(precision), float(dt), q.ctypes.data_as(ctypes.c_void_p))
+        rid = ctypes.c_uint64()
+        _check(lib().solver_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._shapes[rid.value] = q.shape
+        return rid.value
+
+    def poll(self, rid):
+        import numpy as np
+        res = SolveResult()
+        shape = self._shapes.get(rid)
+        out = np.empty(shape, dtype=np.float64) if shape is not None else None
+        ptr = out.ctypes.data_as(ctypes.c_void_p) if out is not None else None
+        rc = lib().solver_poll(self._h, ctypes.c_uint64(rid), ptr, ctypes.byref(res))
+        if rc == NOPCS_EAGAIN:
+            return rc, res, None
+        if rc == NOPCS_ENOTFOUND:
+            raise NopcsError(rc, last_error())
+        self._shapes.pop(rid, None)
+        return rc, res, out
+
+    def now(self):
+        return lib().solver_now(self._h)
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().solver_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,122 @@
+"""Serving benchmark: a Poisson stream of Rayleigh-Taylor boxes through the
+library's serving runtime (solver_create / submit / poll) on one GPU.
+
+Workload (seeded, synthetic): request sizes N in {32, 48, 64, 96, 128, 192},
+a hot lower half 50-300 K above the 300 K upper half, 50-500 RK4 steps, the
+fixed step of inputs.stable_dt, max(1, N // 64) segments per direction;
+exponential inter-arrival times (mean 50 ms, 20 requests/s).  Every draw comes
+from numpy.random.default_rng(4), in the order (gap, N, dT, steps) per request.
+
+Prints one JSON line: aggregate Mpoint-stage/s, p50 / p99 latency (submit to
+done), admission delay percentiles, the number of requests, and (with --check)
+whether each checked request equals the same box run alone, bit for bit.
+
+    python -m paper_2203_00879_amd.serve_bench [--requests 256] [--step-scale 1.0]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    __package__ = "paper_2203_00879_amd"
+
+from . import inputs, nopcs  # noqa: E402
+
+SIZES = (32, 48, 64, 96, 128, 192)
+
+
+def workload(n_req, seed=4, mean_gap_s=0.05, step_scale=1.0):
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    for _ in range(n_req):
+        t += rng.exponential(mean_gap_s)
+        n = int(rng.choice(SIZES))
+        dT = float(rng.uniform(50.0, 300.0))
+        steps = int(rng.integers(50, 501))
+        steps = max(1, int(round(steps * step_scale)))
+        out.append({"t": t, "n": n, "dT": dT, "steps": steps, "nseg": max(1, n // 64)})
+    return out
+
+
+def request_state(w, seed):
+    return inputs.rti_state(w["n"], T_upper=300.0, T_lower=300.0 + w["dT"], seed=seed)
+
+
+def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False):
+    import torch
+    params = nopcs.make_params(inputs.AIR)
+    W = workload(n_req, step_scale=step_scale)
+    states = [request_state(w, i) for i, w in enumerate(W)]
+    grids = [nopcs.make_grid(w["n"], w["nseg"]) for w in W]
+    dts = [inputs.stable_dt(w["n"], 300.0 + w["dT"]) for w in W]
+    ids, t_sub = {}, {}
+    results = {}
+    with nopcs.Solver(int(budget_gb * 1e9), max_slots=slots, max_queue=max(1, n_req)) as S:
+        t0 = time.perf_counter()
+        k = 0
+        pending = set()
+        while k < n_req or pending:
+            now = time.perf_counter() - t0
+            while k < n_req and W[k]["t"] <= now:
+                rid = S.submit(params, grids[k], states[k], W[k]["steps"], dts[k])
+                ids[rid] = k
+                pending.add(rid)
+                k += 1
+            for rid in list(pending):
+                rc, res, Q = S.poll(rid)
+                if rc == nopcs.NOPCS_EAGAIN:
+                    continue
+                pending.discard(rid)
+                results[ids[rid]] = (rc, res.t_submit, res.t_admit, res.t_done, Q if ids[rid] < check else None)
+                if verbose:
+                    print("done", ids[rid], rc, res.t_done - res.t_submit, flush=True)
+            time.sleep(0.001)
+        wall = time.perf_counter() - t0
+    ok = all(r[0] == nopcs.NOPCS_OK for r in results.values())
+    lat = np.array([results[i][3] - results[i][1] for i in range(n_req)])
+    adm = np.array([results[i][2] - results[i][1] for i in range(n_req)])
+    pst = sum(w["n"] ** 3 * 4 * w["steps"] for w in W)
+    first = min(r[1] for r in results.values())
+    last = max(r[3] for r in results.values())
+    out = {
+        "metric": "serving: Mpoint-stage/s and request latency (RTI boxes 32^3..192^3, FP64)",
+        "requests": n_req, "all_ok": ok, "slots": slots,
+        "Mpoint_stage_per_s": pst / (last - first) / 1e6,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_admission_s": float(np.percentile(adm, 50)), "p99_admission_s": float(np.percentile(adm, 99)),
+        "wall_s": wall, "offered_point_stages": pst, "step_scale": step_scale,
+        "arrival_span_s": W[-1]["t"],
+    }
+    if check:
+        # the first `check` requests again, each alone through rk_step: bitwise equal?
+        same = []
+        for i in range(check):
+            Qd = torch.from_numpy(states[i]).to("cuda")
+            ws = nopcs.alloc_workspace(grids[i])
+            nopcs.rk_step(params, grids[i], Qd, dts[i], W[i]["steps"], ws)
+            torch.cuda.synchronize()
+            same.append(bool(np.array_equal(Qd.cpu().numpy(), results[i][4])))
+        out["mix_equals_alone"] = all(same)
+        out["checked"] = check
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--step-scale", type=float, default=1.0)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--check", type=int, default=0)
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args()
+    print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,9 +4,13 @@
 //   driver rhs   nx ny nz sx sy sz lx ly lz viscous gravity in out   (in/out: 5N)
 //   driver rk    nx ny nz sx sy sz lx ly lz viscous gravity dt nsteps in out
 //   driver plan  n nseg piece_len                            (prints the line-march tables)
+//   driver serve                                              (scripted checks of the serving runtime)
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction.
+#include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <thread>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,6 +40,132 @@ static void write_raw(const char *path, const double *p, size_t n) {
     std::fclose(f);
 }
 
+static nse_params air_params() {
+    nse_params p;
+    p.gamma = 1.4; p.R_gas = 287.0; p.g = 9.81; p.L = 0.15; p.T_s = 300.0; p.rho_s = 101325.0 / (287.0 * 300.0);
+    p.Pr = 0.712; p.mu_ref = 1.716e-5; p.T_ref = 273.15; p.S_suth = 110.4; p.mub_a = 3.381e-4; p.mub_b = 7.383e-4;
+    p.viscous = 1; p.gravity = 1;
+    return p;
+}
+
+// a smooth non-dimensional state on an n^3 box (rho ~ 1, small velocities, E' ~ 0)
+static std::vector<double> test_state(int n, int seed) {
+    const size_t N = (size_t)n * n * n;
+    std::vector<double> q(5 * N);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const size_t o = i + (size_t)n * (j + (size_t)n * k);
+                const double a = 0.3 * (seed + 1), x = (double)i / (n - 1), y = (double)j / (n - 1), z = (double)k / (n - 1);
+                q[o] = 1.0 + 0.05 * std::sin(6.0 * x + a) * std::cos(5.0 * y - a) * std::sin(4.0 * z + 1.0);
+                q[N + o] = 0.01 * std::sin(3.0 * y + a) * x * (1 - x);
+                q[2 * N + o] = 0.01 * std::cos(2.0 * z - a) * y * (1 - y);
+                q[3 * N + o] = 0.01 * std::sin(4.0 * x + 2 * a) * z * (1 - z);
+                q[4 * N + o] = 50.0 * std::cos(3.0 * x - a) * std::sin(2.0 * y + z);
+            }
+    return q;
+}
+
+#define SERVE_CHECK(cond, what)                                          \
+    do {                                                                 \
+        if (!(cond)) {                                                   \
+            std::fprintf(stderr, "serve check failed: %s\n", what);     \
+            return 1;                                                    \
+        }                                                                \
+        std::printf("ok %s\n", what);                                   \
+    } while (0)
+
+// Scripted checks of the serving runtime on 8^3 boxes.
+static int serve_checks() {
+    const int n = 8, nsteps = 2;
+    const double dt = 1e-5;
+    nse_params p = air_params();
+    nopcs_grid g;
+    for (int d = 0; d < 3; ++d) { g.n[d] = n; g.nseg[d] = 1; g.len[d] = 1.0; }
+    const size_t N5 = 5 * (size_t)n * n * n;
+    const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
+    const size_t fp = ((N5 * sizeof(double) + 255) & ~(size_t)255) + wsb;
+    // references: rk_step on each state alone (before any solver thread runs kernels)
+    std::vector<std::vector<double>> q0(3), ref(3);
+    for (int r = 0; r < 3; ++r) {
+        q0[r] = test_state(n, r);
+        Buf Q(N5), ws((wsb + 7) / 8);
+        std::memcpy(Q.p, q0[r].data(), N5 * sizeof(double));
+        if (rk_step(&p, &g, NOPCS_FP64, Q.p, dt, nsteps, ws.p, wsb, nullptr) != NOPCS_OK) return 1;
+        ref[r].assign(Q.p, Q.p + N5);
+    }
+    solve_request rq{};
+    rq.params = p; rq.grid = g; rq.nsteps = nsteps; rq.precision = NOPCS_FP64; rq.dt = dt;
+    // 1. three requests on two slots: every result equals its box run alone, bit for bit
+    {
+        solver_config cfg{2 * fp, 2, 16, 0};
+        nopcs_solver *s = nullptr;
+        SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create");
+        uint64_t id[3];
+        for (int r = 0; r < 3; ++r) {
+            rq.Q0_host = q0[r].data();
+            SERVE_CHECK(solver_submit(s, &rq, &id[r]) == NOPCS_OK, "submit");
+        }
+        std::vector<double> out(N5);
+        solve_result res{};
+        for (int r = 0; r < 3; ++r) {
+            int rc;
+            while ((rc = solver_poll(s, id[r], out.data(), &res)) == NOPCS_EAGAIN) std::this_thread::sleep_for(std::chrono::milliseconds(5));
+            SERVE_CHECK(rc == NOPCS_OK && res.steps_done == nsteps, "request done");
+            SERVE_CHECK(std::memcmp(out.data(), ref[r].data(), N5 * sizeof(double)) == 0, "mix equals alone bit for bit");
+            SERVE_CHECK(res.t_submit <= res.t_admit && res.t_admit <= res.t_done, "timestamps ordered");
+        }
+        SERVE_CHECK(solver_poll(s, id[0], nullptr, &res) == NOPCS_ENOTFOUND, "released id not found");
+        SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy");
+    }
+    // 2. budget for one box: admission strictly in arrival order; a non-finite box is flagged
+    {
+        solver_config cfg{fp, 4, 16, 0};
+        nopcs_solver *s = nullptr;
+        SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (one box budget)");
+        std::vector<double> bad = q0[1];
+        bad[7] = std::nan("");
+        uint64_t id[3];
+        const double *src[3] = {q0[0].data(), bad.data(), q0[2].data()};
+        for (int r = 0; r < 3; ++r) {
+            rq.Q0_host = src[r];
+            SERVE_CHECK(solver_submit(s, &rq, &id[r]) == NOPCS_OK, "submit (one box budget)");
+        }
+        solve_result res[3];
+        int rc[3];
+        for (int r = 0; r < 3; ++r)
+            while ((rc[r] = solver_poll(s, id[r], nullptr, &res[r])) == NOPCS_EAGAIN) std::this_thread::sleep_for(std::chrono::milliseconds(5));
+        SERVE_CHECK(rc[0] == NOPCS_OK && rc[2] == NOPCS_OK, "finite boxes ok");
+        SERVE_CHECK(rc[1] == NOPCS_ENONFINITE, "non-finite box flagged");
+        SERVE_CHECK(res[0].t_done <= res[1].t_admit && res[1].t_done <= res[2].t_admit, "admitted in arrival order, one at a time");
+        SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy (one box budget)");
+    }
+    // 3. argument and capacity errors; destroy with work pending
+    {
+        solver_config cfg{fp, 1, 1, 0};
+        nopcs_solver *s = nullptr;
+        SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (queue of one)");
+        uint64_t id = 0;
+        rq.Q0_host = q0[0].data();
+        rq.nsteps = 0;
+        SERVE_CHECK(solver_submit(s, &rq, &id) == NOPCS_EINVAL, "nsteps 0 rejected");
+        rq.nsteps = 400;   // long enough to keep the slot busy while the queue fills
+        nopcs_grid big = g;
+        big.n[0] = 16;
+        solve_request rb = rq;
+        rb.grid = big;
+        SERVE_CHECK(solver_submit(s, &rb, &id) == NOPCS_ENOMEM, "over-budget box rejected");
+        int busy = 0;
+        for (int k = 0; k < 8 && !busy; ++k) busy = solver_submit(s, &rq, &id) == NOPCS_EBUSY;
+        SERVE_CHECK(busy, "full queue answers EBUSY");
+        SERVE_CHECK(solver_poll(s, 987654321ULL, nullptr, nullptr) == NOPCS_ENOTFOUND, "unknown id");
+        SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy with pending work");
+        solver_config badcfg{fp, 0, 1, 0};
+        SERVE_CHECK(solver_create(&badcfg, &s) == NOPCS_EINVAL, "zero slots rejected");
+    }
+    return 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
@@ -47,6 +177,7 @@ int main(int argc, char **argv) {
                     P.grp.size());
         return 0;
     }
+    if (mode == "serve") return serve_checks();
     if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
     // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)
     if (const char *pc = std::getenv("NOPCS_EMUL_PIECE"))

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("api.hip", "sweep.hip", "march.hip", "visc.hip", "plan.cpp")]
+    return [os.path.join(CSRC, f) for f in ("api.hip", "sweep.hip", "march.hip", "visc.hip", "plan.cpp", "solver.cpp")]
 
 
 @pytest.fixture(scope="module")
@@ -116,3 +116,12 @@ def test_emulated_rhs_line_march_with_closures(driver, tmp_path, shape, nseg, pi
     Ro = oracle.rhs(p, Q, L)
     for c in range(5):
         assert _rel(R[c], Ro[c]) <= 1e-13, c
+
+
+def test_emulated_serving_runtime(driver, tmp_path):
+    """Serving runtime on 8^3 boxes: results in a mix equal each box run alone
+    bit for bit, arrival-order admission under a one-box budget, a non-finite
+    box flagged, EBUSY / ENOMEM / ENOTFOUND / EINVAL, destroy with pending work."""
+    r = subprocess.run([driver, "serve"], capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "ok mix equals alone bit for bit" in r.stdout
