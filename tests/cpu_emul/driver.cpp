@@ -77,7 +77,7 @@ static std::vector<double> test_state(int n, int seed) {
 
 // Scripted checks of the serving runtime on 8^3 boxes.
 static int serve_checks() {
-    const int n = 8, nsteps = 2;
+    const int n = 8, nsteps = 1;
     const double dt = 1e-5;
     nse_params p = air_params();
     nopcs_grid g;
@@ -149,7 +149,7 @@ static int serve_checks() {
         rq.Q0_host = q0[0].data();
         rq.nsteps = 0;
         SERVE_CHECK(solver_submit(s, &rq, &id) == NOPCS_EINVAL, "nsteps 0 rejected");
-        rq.nsteps = 400;   // long enough to keep the slot busy while the queue fills
+        rq.nsteps = 8;   // one chunk: keeps the slot busy while the queue fills
         nopcs_grid big = g;
         big.n[0] = 16;
         solve_request rb = rq;

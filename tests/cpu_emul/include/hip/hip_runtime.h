@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <barrier>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -79,7 +80,7 @@ struct alignas(16) double2 {
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
 
 inline thread_local dim3 threadIdx, blockIdx;
-inline dim3 gridDim, blockDim;
+inline dim3 gridDim, blockDim;   // written by every pool thread of a launch with the same value
 inline thread_local std::barrier<> *emu_bar = nullptr;
 inline void __syncthreads() { emu_bar->arrive_and_wait(); }
 
@@ -130,27 +131,70 @@ inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
     return hipSuccess;
 }
 
+// A pool of host threads that play the device threads of one block at a time;
+// created once and reused by every launch (launches from several host threads
+// are serialised).
+struct EmuPool {
+    std::mutex mu, launch_mu;
+    std::condition_variable cv, cv_done;
+    std::vector<std::thread> th;
+    std::function<void(unsigned)> job;
+    unsigned job_nt = 0, active = 0;
+    unsigned long long gen = 0;
+    void loop(unsigned id) {
+        unsigned long long seen = 0;
+        for (;;) {
+            std::function<void(unsigned)> f;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return gen != seen; });
+                seen = gen;
+                if (id >= job_nt) continue;
+                f = job;
+            }
+            f(id);
+            std::lock_guard<std::mutex> lk(mu);
+            if (--active == 0) cv_done.notify_all();
+        }
+    }
+    void run(unsigned nt, std::function<void(unsigned)> f) {
+        std::lock_guard<std::mutex> serial(launch_mu);
+        std::unique_lock<std::mutex> lk(mu);
+        while (th.size() < nt) {
+            const unsigned id = (unsigned)th.size();
+            th.emplace_back([this, id] { loop(id); });
+            th.back().detach();
+        }
+        job = std::move(f);
+        job_nt = nt;
+        active = nt;
+        ++gen;
+        cv.notify_all();
+        cv_done.wait(lk, [&] { return active == 0; });
+    }
+};
+inline EmuPool &emu_pool() {
+    static EmuPool *p = new EmuPool();   // never destroyed: detached threads outlive main
+    return *p;
+}
+
 template <class K, class... A>
 void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
-    gridDim = grid;
-    blockDim = block;
     const unsigned nt = block.x * block.y * block.z;
     const unsigned nb = grid.x * grid.y * grid.z;
-    // one host thread per device thread; blocks run one after the other, separated
-    // by a barrier so that block-shared (static) arrays are reused safely
+    // blocks run one after the other, separated by a barrier so that
+    // block-shared (static) arrays are reused safely
     std::barrier<> bar((std::ptrdiff_t)nt);
-    std::vector<std::thread> th;
-    th.reserve(nt);
-    for (unsigned t = 0; t < nt; ++t)
-        th.emplace_back([&, t]() {
-            threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-            emu_bar = &bar;
-            for (unsigned b = 0; b < nb; ++b) {
-                blockIdx = dim3(b % grid.x, (b / grid.x) % grid.y, b / (grid.x * grid.y));
-                kernel(args...);
-                bar.arrive_and_wait();
-            }
-        });
-    for (auto &x : th) x.join();
+    emu_pool().run(nt, [&](unsigned t) {
+        gridDim = grid;
+        blockDim = block;
+        threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+        emu_bar = &bar;
+        for (unsigned b = 0; b < nb; ++b) {
+            blockIdx = dim3(b % grid.x, (b / grid.x) % grid.y, b / (grid.x * grid.y));
+            kernel(args...);
+            bar.arrive_and_wait();
+        }
+    });
 }
 #define hipLaunchKernelGGL(K, G, B, SHM, ST, ...) emu_launch(K, G, B, __VA_ARGS__)

@@ -86,7 +86,7 @@ def test_emulated_rk_step_matches_oracle_bitwise(driver, tmp_path):
     assert np.array_equal(G, oracle.rk4(p, Q, 2e-5, 2))
 
 
-@pytest.mark.parametrize("shape, v, g", [((90, 40, 20), 1, 1), ((30, 14, 131), 1, 0)])
+@pytest.mark.parametrize("shape, v, g", [((60, 30, 20), 1, 1), ((30, 14, 131), 1, 0)])
 def test_emulated_rhs_tiles_bitwise(driver, tmp_path, shape, v, g):
     """No extra cuts and one segment per direction: interior tiles (no wall
     inside the halo), wall tiles, shifted edge tiles and several z chunks of
@@ -101,7 +101,7 @@ def test_emulated_rhs_tiles_bitwise(driver, tmp_path, shape, v, g):
     assert np.array_equal(R, oracle.rhs(p, Q, L))
 
 
-@pytest.mark.parametrize("shape, nseg, piece", [((20, 72, 150), (1, 2, 3), 16), ((12, 40, 200), (1, 1, 2), -1)])
+@pytest.mark.parametrize("shape, nseg, piece", [((8, 36, 100), (1, 2, 3), 16), ((8, 20, 200), (1, 1, 2), -1)])
 def test_emulated_rhs_line_march_with_closures(driver, tmp_path, shape, nseg, piece):
     """Lines along y and z long enough to be cut into pieces: the line-march
     sweeps (closure pass with 16 or 8 accumulator slots, run march with one or
