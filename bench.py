@@ -43,17 +43,20 @@ KERNEL_SOURCES = {
 
 
 def kernel_bytes_per_point(name, precision):
-    """Compulsory HBM bytes per grid point of one launch (each operand read or written once)."""
-    w = 8  # FP64
+    """Compulsory HBM bytes per grid point of one launch (each operand read or written once).
+    Mixed precision stores the RHS register R in FP32 (4 bytes); everything else is FP64."""
+    w = 8                                          # state, K, Qn, Qs
+    r = 4 if precision == "mixed" else 8           # R
     if name == "viscous":
-        return 5 * w + 5 * w                       # read stage state, write R
+        return 5 * w + 5 * r                       # read stage state, write R
     if name in ("sweep_x", "sweep_y", "sweep_z"):
-        return 5 * w + 5 * w + 5 * w               # read state, read R, write R
+        return 5 * w + 5 * r + 5 * r               # read state, read R, write R
     if name in ("closure_y", "closure_z"):
         return 5 * w                               # read state (closure rows written: ~1/16 of a field)
     if name == "rk_update":
-        # stage 0: R, Qn -> K, Qs; stages 1, 2: R, Qn, K -> K, Qs; stage 3: R, Qn, K -> Qn
-        return (4 * 5 * w + 2 * 5 * 5 * w + 4 * 5 * w) / 4.0
+        # stage 0: R, Qn -> K, Qs; stages 1, 2: R, Qn, K -> K, Qs; stage 3: R, Qn, K -> Qn;
+        # over the 4 stages: R read 4 times, FP64 fields read 7 and written 7 times
+        return (4 * 5 * r + 14 * 5 * w) / 4.0
     return 0.0
 
 
@@ -105,7 +108,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--nseg", type=int, default=4)
     ap.add_argument("--dt", type=float, default=1e-6)
-    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=192)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -138,11 +141,12 @@ def main():
     Q0 = inputs.rti_state(n, seed=0)
     Q = torch.from_numpy(Q0).to(dev)
     del Q0
-    ws = nopcs.alloc_workspace(grid)
+    prec = nopcs.MIXED if args.precision == "mixed" else nopcs.FP64
+    ws = nopcs.alloc_workspace(grid, prec)
     stream = torch.cuda.current_stream()
     lib = nopcs.lib()
 
-    nopcs.rk_step(params, grid, Q, args.dt, args.warmup, ws)
+    nopcs.rk_step(params, grid, Q, args.dt, args.warmup, ws, precision=prec)
     torch.cuda.synchronize()
 
     import ctypes
@@ -154,7 +158,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    nopcs.rk_step(params, grid, Q, args.dt, args.steps, ws)
+    nopcs.rk_step(params, grid, Q, args.dt, args.steps, ws, precision=prec)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -173,19 +177,21 @@ def main():
     N3 = n ** 3
     pstage = N3 * 4 * args.steps
     value = pstage / sec / 1e6
-    dom = max((k for k in per if k in KERNEL_SOURCES and kernel_bytes_per_point(k, "fp64") > 0),
+    pr = args.precision
+    dom = max((k for k in per if k in KERNEL_SOURCES and kernel_bytes_per_point(k, pr) > 0),
               key=lambda k: per[k][0])
     tot_ms, cnt = per[dom]
     avg_s = tot_ms / cnt / 1e3
-    bpl = kernel_bytes_per_point(dom, "fp64") * N3
+    bpl = kernel_bytes_per_point(dom, pr) * N3
     achieved = bpl / avg_s / 1e9
     workload_key = "rti_%d_fp64_seg%d" % (n, args.nseg)
     traffic = load_traffic(dom, workload_key)
     kernels = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
-                   "alg_GBps": (kernel_bytes_per_point(k, "fp64") * N3 / (v[0] / v[1] / 1e3) / 1e9)
-                   if kernel_bytes_per_point(k, "fp64") else None} for k, v in per.items()}
+                   "alg_GBps": (kernel_bytes_per_point(k, pr) * N3 / (v[0] / v[1] / 1e3) / 1e9)
+                   if kernel_bytes_per_point(k, pr) else None} for k, v in per.items()}
     out = {
-        "metric": "Mpoint-stage updates/s (512^3 FP64 RK4 stepping)",
+        "metric": "Mpoint-stage updates/s (512^3 FP64 RK4 stepping)" if pr == "fp64" else
+                  "Mpoint-stage updates/s (512^3 mixed-precision RK4 stepping)",
         "value": value,
         "unit": "Mpoint-stage/s",
         "n_gpus": 1,
@@ -195,11 +201,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if pr == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "Rayleigh-Taylor box %d^3, FP64, %d segments/direction, RK4 dt=%g, seeded "
-                               "interface noise" % (n, args.nseg, args.dt),
-                   "points": N3, "segments_per_direction": args.nseg, "precision": "fp64"},
+        "config": {"workload": "Rayleigh-Taylor box %d^3, %s, %d segments/direction, RK4 dt=%g, seeded "
+                               "interface noise" % (n, "FP64" if pr == "fp64" else "mixed precision", args.nseg, args.dt),
+                   "points": N3, "segments_per_direction": args.nseg, "precision": pr},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": bpl, "mean_launch_ms": avg_s * 1e3},

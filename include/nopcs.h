@@ -50,8 +50,12 @@ enum {
 
 enum {
     NOPCS_FP64 = 0,   /* every step in FP64 */
-    NOPCS_MIXED = 1   /* FP32 interior sweeps and fluxes; FP64 closure rows, wall rows,
-                         RHS accumulation and RK registers */
+    NOPCS_MIXED = 1   /* nse_rhs, rk_step: the Thomas eliminations of the y and z sweeps
+                         run in FP32 on (B f)_i rounded once from FP64; the RHS
+                         register of rk_step is stored in FP32; fluxes, closure rows,
+                         wall rows, viscous terms and the RK registers (state,
+                         accumulator, stage state) stay FP64.  The x sweep (and any
+                         line that falls back to the LDS pencil) computes in FP64. */
 };
 
 /* Uniform box.  n[d] >= 8 points along x, y, z; len[d] > 0 non-dimensional edge
@@ -126,7 +130,7 @@ int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int
  * applied twice.  The library may cut segments further into shorter
  * independent pieces with the same closure; results change by round-off only.
  *
- * dir: 0 = x, 1 = y, 2 = z.  precision: NOPCS_FP64 or NOPCS_MIXED.
+ * dir: 0 = x, 1 = y, 2 = z.  precision: NOPCS_FP64 (NOPCS_MIXED is rejected here).
  * f: device, n0*n1*n2 doubles (read only).  d1, d2: device outputs of the same
  * size, either may be NULL but not both; they must not overlap f.
  */

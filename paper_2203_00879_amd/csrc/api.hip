@@ -151,14 +151,16 @@ static size_t closure_bytes(const nopcs_grid *grid) {
     return ((most * sizeof(double)) + 255) & ~(size_t)255;
 }
 
-// convective sweep along d: line march (y, z) when the plan allows, LDS pencils otherwise
+// convective sweep along d: line march (y, z) when the plan allows, LDS pencils
+// otherwise.  c32: the march eliminates in FP32 (mixed precision).
 static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, const LinePlanDev &pl, double *clo,
-                      hipStream_t st) {
+                      bool c32, hipStream_t st) {
     if (clo && march_usable(d, pl)) {
         NOPCS_HIP_CHECK(timed(NOPCS_K_CLOSURE_Y + (d - 1), st,
                               [&] { return launch_march_closures(d, a.Qin, clo, grid->n, pl, a.c, st); }));
-        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st,
-                              [&] { return launch_march_runs(d, a.Qin, a.R, clo, grid->n, pl, a.c, st); }));
+        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] {
+            return launch_march_runs(d, a.Qin, a.R, a.r32, c32, clo, grid->n, pl, a.c, st);
+        }));
         return NOPCS_OK;
     }
     NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl, st); }));
@@ -224,17 +226,18 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
 }
 
 static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev pl[3], const double *Q, double *R,
-                    double *clo, hipStream_t st) {
+                    double *clo, bool c32, hipStream_t st) {
     double ih[3];
     for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
-    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, grid->n, ih, c, st); }));
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, false, grid->n, ih, c, st); }));
     NseSweepArgs a{};
     a.Qin = Q;
     a.R = R;
+    a.r32 = false;
     a.N3 = (long long)field_elems(grid);
     a.c = c;
     for (int d = 0; d < 3; ++d) {
-        const int rc = conv_sweep(d, a, grid, pl[d], clo, st);
+        const int rc = conv_sweep(d, a, grid, pl[d], clo, c32, st);
         if (rc != NOPCS_OK) return rc;
     }
     return NOPCS_OK;
@@ -257,20 +260,20 @@ static bool check_ws(const nopcs_grid *grid, int precision, const void *ws, size
 int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R, void *ws,
             size_t ws_bytes, void *hip_stream) {
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
-    if (precision != NOPCS_FP64) { set_error("nse_rhs: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
+    if (precision != NOPCS_FP64 && precision != NOPCS_MIXED) { set_error("unknown precision"); return NOPCS_EINVAL; }
     if (!Q || !R) { set_error("Q and R must be non-NULL"); return NOPCS_EINVAL; }
     if (!check_ws(grid, precision, ws, ws_bytes)) return NOPCS_EINVAL;
     LinePlanDev pl[3];
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
     double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * state_bytes(grid));
-    return rhs_into(make_nd(*params), grid, pl, Q, R, clo, (hipStream_t)hip_stream);
+    return rhs_into(make_nd(*params), grid, pl, Q, R, clo, precision == NOPCS_MIXED, (hipStream_t)hip_stream);
 }
 
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
             void *ws, size_t ws_bytes, void *hip_stream) {
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
-    if (precision != NOPCS_FP64) { set_error("rk_step: only NOPCS_FP64 is implemented"); return NOPCS_EINVAL; }
+    if (precision != NOPCS_FP64 && precision != NOPCS_MIXED) { set_error("unknown precision"); return NOPCS_EINVAL; }
     if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
     if (((uintptr_t)Q & 15) != 0) { set_error("Q must be 16-byte aligned"); return NOPCS_EINVAL; }
     if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
@@ -285,12 +288,14 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     const size_t reg = state_bytes(grid);
     double *K = reinterpret_cast<double *>(ws);
     double *Qs = reinterpret_cast<double *>(static_cast<char *>(ws) + reg);
-    double *R = reinterpret_cast<double *>(static_cast<char *>(ws) + 2 * reg);
+    void *R = static_cast<char *>(ws) + 2 * reg;   // FP64, or FP32 in mixed precision
     double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * reg);
+    const bool mixed = precision == NOPCS_MIXED;
     double ih[3];
     for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
     NseSweepArgs a{};
     a.R = R;
+    a.r32 = mixed;
     a.Qn = Q;
     a.K = K;
     a.Qs = Qs;
@@ -304,9 +309,9 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
             const double *Qin = stage == 0 ? Q : Qs;
             a.Qin = Qin;
             a.stage = stage;
-            NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, grid->n, ih, c, st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, mixed, grid->n, ih, c, st); }));
             for (int d = 0; d < 3; ++d) {
-                const int rc2 = conv_sweep(d, a, grid, pl[d], clo, st);
+                const int rc2 = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
                 if (rc2 != NOPCS_OK) return rc2;
             }
             NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));

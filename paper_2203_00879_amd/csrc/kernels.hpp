@@ -9,7 +9,8 @@ namespace nopcs {
 
 struct NseSweepArgs {
     const double *Qin;  // stage input state (5 fields)
-    double *R;          // right-hand side accumulator (5 fields)
+    void *R;            // right-hand side accumulator (5 fields; FP64, or FP32 when r32)
+    bool r32;           // R stored in FP32 (mixed precision)
     double *Qn;         // RK: state at the start of the step (in/out at the last stage)
     double *K;          // RK: k1 + 2 k2 + 2 k3 accumulator
     double *Qs;         // RK: next stage state
@@ -46,12 +47,13 @@ size_t march_closure_elems(const int n[3], int dir, int ncl);
 // (march_closure_elems doubles); nothing to do without closure rows
 hipError_t launch_march_closures(int dir, const double *Q, double *clo, const int n[3], const LinePlanDev &pl,
                                  const NdConst &c, hipStream_t st);
-// R <- R - D_dir(convective flux) for the 5 components, closures from clo
-hipError_t launch_march_runs(int dir, const double *Q, double *R, const double *clo, const int n[3],
+// R <- R - D_dir(convective flux) for the 5 components, closures from clo;
+// r32: R is stored in FP32; c32: the elimination runs in FP32
+hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
                              const LinePlanDev &pl, const NdConst &c, hipStream_t st);
 
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
-hipError_t launch_visc(const double *Q, double *R, const int n[3], const double ih[3], const NdConst &c,
+hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
                        hipStream_t st);
 
 // Wall conditions on one face pair (dir 0, 1, 2) of state Q.

@@ -182,8 +182,10 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
 // ---------------------------------------------------------------------------
 // Run march
 // ---------------------------------------------------------------------------
-template <int DIR, bool FULL>
-__global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, double *R,
+// TR: storage type of R; TC: arithmetic of the elimination (B f is formed in
+// FP64 from the FP64 window and rounded once; known rows stay FP64)
+template <int DIR, bool FULL, class TR, class TC>
+__global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, TR *R,
                                                             const double *__restrict__ clo, MarchGeom g,
                                                             LinePlanDev pl, NdConst c) {
     __shared__ double L[2][CH][NCOMP][MW];
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
     const long long base = x + g.sO * o;
     const long long nlines = (long long)g.nx * g.no;
     const long long line = x + (long long)g.nx * o;
-    double *Rc = R + comp * g.N3 + (ok ? base : 0);   // this component's R at row 0 of the line
+    TR *Rc = R + comp * g.N3 + (ok ? base : 0);   // this component's R at row 0 of the line
     const double *clc = clo + (long long)comp * pl.ncl * nlines + (ok ? line : 0);
     // int2 tables read as int pairs through the scalar path
     const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
@@ -209,8 +211,8 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
     auto runs = [&](int r) { return make_int2(runs_i[2 * r], runs_i[2 * r + 1]); };
     auto run_slot = [&](int r) { return make_int2(slot_i[2 * r], slot_i[2 * r + 1]); };
     const auto run_own = NOPCS_SCALAR_PTR(int, pl.run_own);
-    const auto den = NOPCS_SCALAR_PTR(double, pl.den);
-    const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
+    const auto den = NOPCS_SCALAR_PTR(TC, (sizeof(TC) == 8 ? (const void *)pl.den : (const void *)pl.den32));
+    const auto cp = NOPCS_SCALAR_PTR(TC, (sizeof(TC) == 8 ? (const void *)pl.cp : (const void *)pl.cp32));
     const int2 gr = make_int2(grp_i[2 * grp], grp_i[2 * grp + 1]);
     const int lo0 = runs(gr.x).x;
 
@@ -262,25 +264,27 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
         else xlo = 0.5 * ih * (w2 - w0);   // row 1 (i = 2)
         if (slot.y >= 4) xhi = KV[2 * (r - gr.x) + 1][comp][lane];
         if (own & 4) v0 = 0.5 * ih * (4.0 * (w1 - w0) - (w2 - w0));   // row 0 (i = 2)
-        double d[MRL];
+        TC d[MRL];
 #pragma unroll
-        for (int t = 0; t < MRL; ++t) d[t] = 0.0;
-        double dprev = 0.0;
+        for (int t = 0; t < MRL; ++t) d[t] = TC(0);
+        TC dprev = TC(0);
+        const TC alpha = TC(kAlpha);
 #pragma unroll
         for (int t = 0; t < MRL; ++t) {
             if (t < m) {
                 const int k = t + 1;
-                double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
-                if (k == 1) rr = rr - kAlpha * xlo;
+                const double rr64 = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+                TC rr = TC(rr64);
+                if (k == 1) rr = rr - alpha * TC(xlo);
                 if (k == m) {
                     if (slot.y < 4) xhi = 0.5 * ih * (w4 - w2);   // row n-2 (i = n-3)
                     if (own & 8) {
                         const double fl = w4;                         // row n-1
                         vn = -0.5 * ih * (4.0 * (w3 - fl) - (w2 - fl));
                     }
-                    rr = rr - kAlpha * xhi;
+                    rr = rr - alpha * TC(xhi);
                 }
-                const double dp = (rr - kAlpha * dprev) / den[k];
+                const TC dp = (rr - alpha * dprev) / den[k];
                 d[t] = dp;
                 dprev = dp;
                 advance();
@@ -294,27 +298,27 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
         // that follows it.
         constexpr int RA = 8;
         auto rrow = [&](int t) { return sD * (lo + 1 + (t < m ? t : m - 1)); };
-        double ring[RA];
+        TR ring[RA];
 #pragma unroll
         for (int t = MRL - RA; t < MRL; ++t) ring[t % RA] = Rc[rrow(t)];
         // R of the known rows this run may update (rows outside lo+1 .. hi-1)
-        const double rlo = Rc[sD * lo], rhi = Rc[sD * hi], r0 = Rc[0], rn = Rc[sD * (n - 1)];
-        double xn = 0.0;
+        const TR rlo = Rc[sD * lo], rhi = Rc[sD * hi], r0 = Rc[0], rn = Rc[sD * (n - 1)];
+        TC xn = TC(0);
 #pragma unroll
         for (int t = MRL - 1; t >= 0; --t) {
             const int k = t + 1;
-            const double xs = k == m ? d[t] : d[t] - cp[k] * xn;
-            const double xk = t < m ? xs : 0.0;
+            const TC xs = k == m ? d[t] : d[t] - cp[k] * xn;
+            const TC xk = t < m ? xs : TC(0);
             xn = xk;
-            const double nv = ring[t % RA] - xk;
+            const TR nv = ring[t % RA] - TR(xk);
             if (t - RA >= 0) ring[t % RA] = Rc[rrow(t - RA)];
             if (ok) Rc[rrow(t)] = nv;
         }
         if (ok) {
-            if (own & 1) Rc[sD * lo] = rlo - xlo;
-            if (own & 2) Rc[sD * hi] = rhi - xhi;
-            if (own & 4) Rc[0] = r0 - v0;
-            if (own & 8) Rc[sD * (n - 1)] = rn - vn;
+            if (own & 1) Rc[sD * lo] = rlo - TR(xlo);
+            if (own & 2) Rc[sD * hi] = rhi - TR(xhi);
+            if (own & 4) Rc[0] = r0 - TR(v0);
+            if (own & 8) Rc[sD * (n - 1)] = rn - TR(vn);
         }
     }
 }
@@ -364,17 +368,25 @@ hipError_t launch_march_closures(int dir, const double *Q, double *clo, const in
     return hipGetLastError();
 }
 
-hipError_t launch_march_runs(int dir, const double *Q, double *R, const double *clo, const int n[3],
-                             const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
-    const MarchGeom g = march_geom(n, dir);
+template <class TR, class TC>
+static hipError_t launch_runs_t(int dir, const double *Q, TR *R, const double *clo, const MarchGeom &g,
+                                const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
     const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
     const bool full = g.nx % MW == 0;
-    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
+    const MarchGeom g = march_geom(n, dir);
+    if (!c32) return launch_runs_t<double, double>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
+    if (!r32) return launch_runs_t<double, float>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
+    return launch_runs_t<float, float>(dir, Q, static_cast<float *>(R), clo, g, pl, c, st);
 }
 
 }  // namespace nopcs

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int DIR, int NMAX, int C0, int NC>
+template <int DIR, int NMAX, int C0, int NC, class TR>
 __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, int np,
                                  long long base, double (&flux)[5][SweepCfg<DIR, NMAX>::PTS],
                                  const int (&ks)[SweepCfg<DIR, NMAX>::PTS], double *F, double *KN) {
@@ -101,14 +101,15 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
     lds_line_solve<DIR, NMAX, NC>(F, KN, pl, np);
     // R of the owned points; unconditional loads at clamped indices (no branch
     // makes the compiler drain the loads in flight), unused values dropped
-    double rv[NC][C::PTS];
+    TR *const R = static_cast<TR *>(a.R);
+    TR rv[NC][C::PTS];
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
         C::owned(threadIdx.x + s * C::NT, l, i);
         const long long o = base + min(l, np - 1) * g.sA + min(i, n - 1) * g.sD;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) rv[c][s] = a.R[(C0 + c) * N3 + o];
+        for (int c = 0; c < NC; ++c) rv[c][s] = R[(C0 + c) * N3 + o];
     }
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
@@ -118,13 +119,13 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
         const long long o = base + l * g.sA + i * g.sD;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            a.R[(C0 + c) * N3 + o] = rv[c][s] - lds_result<DIR, NMAX>(F, KN, c, ks[s], l, i);
+            R[(C0 + c) * N3 + o] = rv[c][s] - TR(lds_result<DIR, NMAX>(F, KN, c, ks[s], l, i));
     }
 }
 
 }  // namespace
 
-template <int DIR, int NMAX>
+template <int DIR, int NMAX, class TR>
 __global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, LinePlanDev pl) {
     using C = SweepCfg<DIR, NMAX>;
     __shared__ double F[C::G * C::FSZ];
@@ -157,9 +158,9 @@ __global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, 
     int ks[C::PTS];
     owned_slots<DIR, NMAX>(pl, ks);
     static_assert(C::G == 3, "component grouping below assumes groups {0,1,2} and {3,4}");
-    nse_group<DIR, NMAX, 0, 3>(a, g, pl, np, base, flux, ks, F, KN);
+    nse_group<DIR, NMAX, 0, 3, TR>(a, g, pl, np, base, flux, ks, F, KN);
     __syncthreads();
-    nse_group<DIR, NMAX, 3, 2>(a, g, pl, np, base, flux, ks, F, KN);
+    nse_group<DIR, NMAX, 3, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,16 +186,22 @@ __device__ inline void rk_elem(double kv, double &K, double &Qs, double &Qn, con
 
 // two neighbouring elements per thread and iteration (16-byte accesses); the
 // registers must be 16-byte aligned, an odd tail element is done separately
-template <int STAGE>
+template <class TR> struct Pair;
+template <> struct Pair<double> { using T = double2; };
+template <> struct Pair<float> { using T = float2; };
+
+template <int STAGE, class TR>
 __global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long total) {
     const long long npair = total >> 1;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const double2 *R2 = reinterpret_cast<const double2 *>(a.R);
+    const TR *const R = static_cast<const TR *>(a.R);
+    const auto *R2 = reinterpret_cast<const typename Pair<TR>::T *>(R);
     double2 *K2 = reinterpret_cast<double2 *>(a.K);
     double2 *S2 = reinterpret_cast<double2 *>(a.Qs);
     double2 *N2 = reinterpret_cast<double2 *>(a.Qn);
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += stride) {
-        const double2 kv = R2[p];
+        const auto kr = R2[p];
+        const double2 kv = make_double2(double(kr.x), double(kr.y));
         double2 kk = STAGE == 0 ? make_double2(0.0, 0.0) : K2[p];
         double2 qn = N2[p];
         double2 qs;
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long tot
     if ((total & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const long long o = total - 1;
         double kk = STAGE == 0 ? 0.0 : a.K[o], qs = 0.0, qn = a.Qn[o];
-        rk_elem<STAGE>(a.R[o], kk, qs, qn, a);
+        rk_elem<STAGE>(double(R[o]), kk, qs, qn, a);
         if (STAGE < 3) {
             a.K[o] = kk;
             a.Qs[o] = qs;
@@ -234,11 +241,20 @@ hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st) {
     if (blocks > 256 * 32) blocks = 256 * 32;
     if (blocks < 1) blocks = 1;
     const dim3 g((unsigned)blocks), b(256);
-    switch (a.stage) {
-        case 0: hipLaunchKernelGGL(k_rk_update<0>, g, b, 0, st, a, total); break;
-        case 1: hipLaunchKernelGGL(k_rk_update<1>, g, b, 0, st, a, total); break;
-        case 2: hipLaunchKernelGGL(k_rk_update<2>, g, b, 0, st, a, total); break;
-        default: hipLaunchKernelGGL(k_rk_update<3>, g, b, 0, st, a, total); break;
+    if (a.r32) {
+        switch (a.stage) {
+            case 0: hipLaunchKernelGGL((k_rk_update<0, float>), g, b, 0, st, a, total); break;
+            case 1: hipLaunchKernelGGL((k_rk_update<1, float>), g, b, 0, st, a, total); break;
+            case 2: hipLaunchKernelGGL((k_rk_update<2, float>), g, b, 0, st, a, total); break;
+            default: hipLaunchKernelGGL((k_rk_update<3, float>), g, b, 0, st, a, total); break;
+        }
+    } else {
+        switch (a.stage) {
+            case 0: hipLaunchKernelGGL((k_rk_update<0, double>), g, b, 0, st, a, total); break;
+            case 1: hipLaunchKernelGGL((k_rk_update<1, double>), g, b, 0, st, a, total); break;
+            case 2: hipLaunchKernelGGL((k_rk_update<2, double>), g, b, 0, st, a, total); break;
+            default: hipLaunchKernelGGL((k_rk_update<3, double>), g, b, 0, st, a, total); break;
+        }
     }
     return hipGetLastError();
 }
@@ -261,7 +277,10 @@ static hipError_t launch_sweep_t(const NseSweepArgs &a, const SweepGeom &g, cons
     using C = SweepCfg<DIR, NMAX>;
     const int npa = (g.nA + C::P - 1) / C::P;
     const long long blocks = (long long)npa * g.nB;
-    hipLaunchKernelGGL((k_nse_sweep<DIR, NMAX>), dim3((unsigned)blocks), dim3(C::NT), 0, st, a, g, pl);
+    if (a.r32)
+        hipLaunchKernelGGL((k_nse_sweep<DIR, NMAX, float>), dim3((unsigned)blocks), dim3(C::NT), 0, st, a, g, pl);
+    else
+        hipLaunchKernelGGL((k_nse_sweep<DIR, NMAX, double>), dim3((unsigned)blocks), dim3(C::NT), 0, st, a, g, pl);
     return hipGetLastError();
 }
 

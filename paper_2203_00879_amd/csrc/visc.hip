@@ -29,7 +29,7 @@ constexpr int CTX = 28, CTY = 12, CX = CTX + 4, CY = CTY + 4, CNT = CX * CY;
 
 struct VArgs {
     const double *Q;
-    double *R;
+    void *R;        // TR[5 N3]
     int nx, ny, nz, ntx, nty, zc;
     long long N3;
     double ihx, ihy, ihz;
@@ -75,9 +75,10 @@ __device__ inline double dz(const double w[3], double fm2, double fp2, int k, in
 // One block's march over planes k0..k1-1 (see the file header).  S holds, per
 // column slot: u, v, w, T of plane k (fields 0-3), Ev (4-7) and Fv (8-11).
 // Output columns with gi < own_i or gj < own_j belong to the neighbouring tile.
-template <bool WALL>
+template <bool WALL, class TR>
 __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int own_i, int own_j, int k0,
                                   int k1) {
+    TR *const R = static_cast<TR *>(A.R);
     const NdConst &c = A.c;
     const double *Q = A.Q;
     const long long N3 = A.N3;
@@ -115,11 +116,11 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     // R of plane k: the divergence plus the gravity source (rho and rho v of that plane)
     auto write_R = [&](int k, const double acc[4], double rho, double my) {
         const long long o = col + plane * k;
-        A.R[o] = 0.0;
-        A.R[N3 + o] = acc[0];
-        A.R[2 * N3 + o] = acc[1] - c.ghat * rho;
-        A.R[3 * N3 + o] = acc[2];
-        A.R[4 * N3 + o] = acc[3] - c.ghat * my;
+        R[o] = TR(0.0);
+        R[N3 + o] = TR(acc[0]);
+        R[2 * N3 + o] = TR(acc[1] - c.ghat * rho);
+        R[3 * N3 + o] = TR(acc[2]);
+        R[4 * N3 + o] = TR(acc[3] - c.ghat * my);
     };
 
     // planes whose node fluxes are needed: k0-1 .. k1, and nz-3 for the top wall
@@ -237,13 +238,13 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             // parked in R, where only this thread reads it back
             if (k == 0) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) A.R[(q + 1) * N3 + col] = part[q];
+                for (int q = 0; q < 4; ++q) R[(q + 1) * N3 + col] = TR(part[q]);
             }
             if (k == 2 && k0 == 0) {
                 double acc[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    acc[q] = A.R[(q + 1) * N3 + col] + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
+                    acc[q] = double(R[(q + 1) * N3 + col]) + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
                 write_R(0, acc, Q[col], Q[2 * N3 + col]);
             }
             // the top wall plane nz-1 is finished with G(nz-1), G(nz-2), G(nz-3)
@@ -259,6 +260,7 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     }
 }
 
+template <class TR>
 __global__ __launch_bounds__(CNT) void k_visc(VArgs A) {
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int tt = b % A.ntx, rest = b / A.ntx, ty = rest % A.nty, tz = rest / A.nty;
@@ -273,25 +275,26 @@ __global__ __launch_bounds__(CNT) void k_visc(VArgs A) {
             gj >= A.ny)
             return;
         const long long N3 = A.N3;
+        TR *const R = static_cast<TR *>(A.R);
         for (int k = k0; k < k1; ++k) {
             const long long o = gi + (long long)A.nx * (gj + (long long)A.ny * k);
-            A.R[o] = 0.0;
-            A.R[N3 + o] = 0.0;
-            A.R[2 * N3 + o] = 0.0 - A.c.ghat * A.Q[o];
-            A.R[3 * N3 + o] = 0.0;
-            A.R[4 * N3 + o] = 0.0 - A.c.ghat * A.Q[2 * N3 + o];
+            R[o] = TR(0.0);
+            R[N3 + o] = TR(0.0);
+            R[2 * N3 + o] = TR(0.0 - A.c.ghat * A.Q[o]);
+            R[3 * N3 + o] = TR(0.0);
+            R[4 * N3 + o] = TR(0.0 - A.c.ghat * A.Q[2 * N3 + o]);
         }
         return;
     }
     __shared__ double S[12 * CNT];
     // every column and every flux node of the tile off the x and y walls
     const bool interior = i0 >= 2 && i0 + CTX + 2 <= A.nx && j0 >= 2 && j0 + CTY + 2 <= A.ny;
-    if (interior) visc_march<false>(A, S, i0, j0, own_i, own_j, k0, k1);
-    else visc_march<true>(A, S, i0, j0, own_i, own_j, k0, k1);
+    if (interior) visc_march<false, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
+    else visc_march<true, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
 }
 }  // namespace
 
-hipError_t launch_visc(const double *Q, double *R, const int n[3], const double ih[3], const NdConst &c,
+hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
                        hipStream_t st) {
     VArgs A;
     A.Q = Q;
@@ -309,7 +312,8 @@ hipError_t launch_visc(const double *Q, double *R, const int n[3], const double 
     A.c = c;
     const int ntz = (n[2] + A.zc - 1) / A.zc;
     const long long blocks = (long long)A.ntx * A.nty * ntz;
-    hipLaunchKernelGGL(k_visc, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
+    if (r32) hipLaunchKernelGGL(k_visc<float>, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
+    else hipLaunchKernelGGL(k_visc<double>, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
     return hipGetLastError();
 }
 

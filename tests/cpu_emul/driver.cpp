@@ -5,7 +5,8 @@
 //   driver rk    nx ny nz sx sy sz lx ly lz viscous gravity dt nsteps in out
 //   driver plan  n nseg piece_len                            (prints the line-march tables)
 //   driver serve                                              (scripted checks of the serving runtime)
-// Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction.
+// Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction;
+// NOPCS_EMUL_PRECISION=1 runs rhs and rk in mixed precision.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -190,6 +191,9 @@ int main(int argc, char **argv) {
         g.len[d] = std::atof(argv[8 + d]);
     }
     const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    // NOPCS_EMUL_PRECISION=1: mixed precision for rhs and rk
+    const char *pe = std::getenv("NOPCS_EMUL_PRECISION");
+    const int prec = pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64;
     nse_params p;
     p.gamma = 1.4; p.R_gas = 287.0; p.g = 9.81; p.L = 0.15; p.T_s = 300.0; p.rho_s = 101325.0 / (287.0 * 300.0);
     p.Pr = 0.712; p.mu_ref = 1.716e-5; p.T_ref = 273.15; p.S_suth = 110.4; p.mub_a = 3.381e-4; p.mub_b = 7.383e-4;
@@ -214,7 +218,7 @@ int main(int argc, char **argv) {
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
         const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
         Buf ws((wsb + 7) / 8);
-        rc = nse_rhs(&p, &g, NOPCS_FP64, Q.p, R.p, ws.p, wsb, nullptr);
+        rc = nse_rhs(&p, &g, prec, Q.p, R.p, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[14], R.p, 5 * N);
     } else if (mode == "rk") {
         p.viscous = std::atoi(argv[11]);
@@ -226,7 +230,7 @@ int main(int argc, char **argv) {
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
         const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
         Buf ws((wsb + 7) / 8);
-        rc = rk_step(&p, &g, NOPCS_FP64, Q.p, dt, nsteps, ws.p, wsb, nullptr);
+        rc = rk_step(&p, &g, prec, Q.p, dt, nsteps, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[16], Q.p, 5 * N);
     } else {
         return 2;

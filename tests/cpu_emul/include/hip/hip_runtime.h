@@ -78,6 +78,9 @@ struct alignas(16) double2 {
     double x, y;
 };
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
+struct alignas(8) float2 {
+    float x, y;
+};
 
 inline thread_local dim3 threadIdx, blockIdx;
 inline dim3 gridDim, blockDim;   // written by every pool thread of a launch with the same value

@@ -38,10 +38,12 @@ def driver():
     return BIN
 
 
-def _run(driver, args, tmp_path, piece=None):
+def _run(driver, args, tmp_path, piece=None, mixed=False):
     env = dict(os.environ)
     if piece is not None:
         env["NOPCS_EMUL_PIECE"] = str(piece)
+    if mixed:
+        env["NOPCS_EMUL_PRECISION"] = "1"
     r = subprocess.run([driver] + [str(a) for a in args], capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, r.stderr[-4000:]
 
@@ -125,3 +127,23 @@ def test_emulated_serving_runtime(driver, tmp_path):
     r = subprocess.run([driver, "serve"], capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "ok mix equals alone bit for bit" in r.stdout
+
+
+def test_emulated_rhs_mixed_precision(driver, tmp_path):
+    """Mixed precision (FP32 elimination along y and z, FP64 everything else)
+    against the oracle's FP64 right-hand side.  Error budget: the FP32 runs see
+    (B f)_i rounded once (relative 6e-8) and amplify it by at most the row sum
+    of |A^-1| (< 4.4); with the viscous and x parts exact to FP64 the RHS error
+    stays below 1e-6 of each component's maximum."""
+    p = dict(inputs.AIR)
+    shape = (12, 40, 70)
+    Q = inputs.smooth_state(shape, seed=31)
+    qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
+    Q.tofile(qin)
+    _run(driver, ["rhs", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, qin, rout], tmp_path, mixed=True)
+    R = np.fromfile(rout).reshape(Q.shape)
+    Ro = oracle.rhs(p, Q)
+    errs = [_rel(R[c], Ro[c]) for c in range(5)]
+    print("mixed rhs rel errors", errs)
+    assert max(errs) <= 1e-6
+    assert max(errs) > 0.0     # the FP32 path really ran
