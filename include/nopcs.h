@@ -189,6 +189,18 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
  */
 int nopcs_set_piece_length(int32_t dir, int32_t piece_len);
 
+/*
+ * nopcs_set_graphs -- on != 0: rk_step captures one RK4 step (all its kernel
+ * launches) into a HIP graph on a private stream, the first time it sees a given
+ * (device, state pointer, workspace pointer, box, parameters, precision, dt,
+ * piece lengths), and replays that graph nsteps times on the caller's stream;
+ * results are bit for bit those of the launches themselves.  Graphs are cached
+ * (at most 64) and freed by nopcs_release_plans.  Kernel timing
+ * (nopcs_timing_*) does not see launches inside graphs.  on == 0 (the default)
+ * launches every kernel directly.  Process-wide; returns NOPCS_OK.
+ */
+int nopcs_set_graphs(int32_t on);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of many boxes on one GPU.                    */
 /* ------------------------------------------------------------------------ */

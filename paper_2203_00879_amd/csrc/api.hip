@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -109,8 +110,19 @@ int drain_timing() {
 }  // namespace
 
 // Launch through f() bracketed by events when timing is on.
+static thread_local bool t_capturing = false;   // inside a graph capture: no event records
+
+template <class F>
+static hipError_t timed_impl(int id, hipStream_t st, F &&f);
+
 template <class F>
 static hipError_t timed(int id, hipStream_t st, F &&f) {
+    if (t_capturing) return f();
+    return timed_impl(id, st, std::forward<F>(f));
+}
+
+template <class F>
+static hipError_t timed_impl(int id, hipStream_t st, F &&f) {
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
@@ -167,6 +179,129 @@ static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, cons
     return NOPCS_OK;
 }
 
+// One classical RK4 step (Section 4): per stage the viscous terms and source,
+// the three convective sweeps, the register update and the wall conditions.
+static int launch_step(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
+                       const LinePlanDev pl[3], hipStream_t st) {
+    const NdConst c = make_nd(params);
+    const size_t N = field_elems(grid);
+    const size_t reg = state_bytes(grid);
+    double *K = reinterpret_cast<double *>(ws);
+    double *Qs = reinterpret_cast<double *>(static_cast<char *>(ws) + reg);
+    void *R = static_cast<char *>(ws) + 2 * reg;   // FP64, or FP32 in mixed precision
+    double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * reg);
+    const bool mixed = precision == NOPCS_MIXED;
+    double ih[3];
+    for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
+    NseSweepArgs a{};
+    a.R = R;
+    a.r32 = mixed;
+    a.Qn = Q;
+    a.K = K;
+    a.Qs = Qs;
+    a.N3 = (long long)N;
+    a.c = c;
+    a.dt = dt;
+    a.half_dt = 0.5 * dt;
+    a.sixth_dt = dt / 6.0;
+    for (int stage = 0; stage < 4; ++stage) {
+        const double *Qin = stage == 0 ? Q : Qs;
+        a.Qin = Qin;
+        a.stage = stage;
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, mixed, grid->n, ih, c, st); }));
+        for (int d = 0; d < 3; ++d) {
+            const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
+            if (rc != NOPCS_OK) return rc;
+        }
+        NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
+        double *Qout = stage < 3 ? Qs : Q;
+        for (int d = 0; d < 3; ++d)
+            NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
+    }
+    return NOPCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs of one RK4 step: captured once per (device, state, workspace, box,
+// parameters, precision, dt, piece lengths) on a private stream and replayed on
+// the caller's stream.  Kernel timing is not recorded inside graphs.
+// ---------------------------------------------------------------------------
+static std::atomic<int> g_graphs{0};
+namespace {
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_gmu;
+std::map<std::string, GraphEntry> g_graph_cache;
+std::map<int, hipStream_t> g_capture_stream;
+constexpr size_t kMaxGraphs = 64;
+
+template <class T>
+void put_bytes(std::string &k, const T &v) {
+    k.append(reinterpret_cast<const char *>(&v), sizeof v);
+}
+
+void drop_graph(GraphEntry &e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+}
+}  // namespace
+
+static void release_graphs() {
+    std::lock_guard<std::mutex> lk(g_gmu);
+    for (auto &kv : g_graph_cache) drop_graph(kv.second);
+    g_graph_cache.clear();
+}
+
+static int step_graph(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
+                      const LinePlanDev pl[3], hipGraphExec_t *out) {
+    int dev = 0;
+    NOPCS_HIP_CHECK(hipGetDevice(&dev));
+    std::string key;
+    put_bytes(key, dev);
+    put_bytes(key, Q);
+    put_bytes(key, ws);
+    put_bytes(key, *grid);
+    put_bytes(key, params);
+    put_bytes(key, precision);
+    put_bytes(key, dt);
+    for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, grid->n[d]));
+    std::lock_guard<std::mutex> lk(g_gmu);
+    auto it = g_graph_cache.find(key);
+    if (it != g_graph_cache.end()) {
+        *out = it->second.exec;
+        return NOPCS_OK;
+    }
+    if (g_graph_cache.size() >= kMaxGraphs) {
+        drop_graph(g_graph_cache.begin()->second);
+        g_graph_cache.erase(g_graph_cache.begin());
+    }
+    hipStream_t &cs = g_capture_stream[dev];
+    if (!cs) NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    GraphEntry e;
+    NOPCS_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    t_capturing = true;
+    const int rc = launch_step(params, grid, precision, Q, dt, ws, pl, cs);
+    t_capturing = false;
+    const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
+    if (rc != NOPCS_OK) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        return rc;
+    }
+    NOPCS_HIP_CHECK(ec);
+    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(e.graph);
+        set_error("hipGraphInstantiate failed");
+        return NOPCS_EDEVICE;
+    }
+    g_graph_cache[key] = e;
+    *out = e.exec;
+    return NOPCS_OK;
+}
+
 extern "C" {
 
 const char *nopcs_last_error(void) { return get_error(); }
@@ -174,6 +309,7 @@ const char *nopcs_last_error(void) { return get_error(); }
 int nopcs_version(void) { return 100; }
 
 int nopcs_release_plans(void) {
+    release_graphs();   // graphs reference plan memory
     release_line_plans();
     return NOPCS_OK;
 }
@@ -282,44 +418,24 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     LinePlanDev pl[3];
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
-    const NdConst c = make_nd(*params);
     hipStream_t st = (hipStream_t)hip_stream;
-    const size_t N = field_elems(grid);
-    const size_t reg = state_bytes(grid);
-    double *K = reinterpret_cast<double *>(ws);
-    double *Qs = reinterpret_cast<double *>(static_cast<char *>(ws) + reg);
-    void *R = static_cast<char *>(ws) + 2 * reg;   // FP64, or FP32 in mixed precision
-    double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * reg);
-    const bool mixed = precision == NOPCS_MIXED;
-    double ih[3];
-    for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
-    NseSweepArgs a{};
-    a.R = R;
-    a.r32 = mixed;
-    a.Qn = Q;
-    a.K = K;
-    a.Qs = Qs;
-    a.N3 = (long long)N;
-    a.c = c;
-    a.dt = dt;
-    a.half_dt = 0.5 * dt;
-    a.sixth_dt = dt / 6.0;
-    for (int step = 0; step < nsteps; ++step) {
-        for (int stage = 0; stage < 4; ++stage) {
-            const double *Qin = stage == 0 ? Q : Qs;
-            a.Qin = Qin;
-            a.stage = stage;
-            NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, mixed, grid->n, ih, c, st); }));
-            for (int d = 0; d < 3; ++d) {
-                const int rc2 = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
-                if (rc2 != NOPCS_OK) return rc2;
-            }
-            NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
-            double *Qout = stage < 3 ? Qs : Q;
-            for (int d = 0; d < 3; ++d)
-                NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
+    if (nsteps == 0) return NOPCS_OK;
+    if (!g_graphs.load()) {
+        for (int step = 0; step < nsteps; ++step) {
+            rc = launch_step(*params, grid, precision, Q, dt, ws, pl, st);
+            if (rc != NOPCS_OK) return rc;
         }
+        return NOPCS_OK;
     }
+    hipGraphExec_t exec = nullptr;
+    rc = step_graph(*params, grid, precision, Q, dt, ws, pl, &exec);
+    if (rc != NOPCS_OK) return rc;
+    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(exec, st));
+    return NOPCS_OK;
+}
+
+int nopcs_set_graphs(int32_t on) {
+    g_graphs.store(on ? 1 : 0);
     return NOPCS_OK;
 }
 

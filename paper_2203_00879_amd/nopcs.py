@@ -81,6 +81,8 @@ def lib():
         L.nse_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V, ctypes.c_size_t, _V]
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
+        L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
+        L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
         if hasattr(L, "solver_create"):
             L.solver_create.argtypes = [ctypes.POINTER(SolverConfig), ctypes.POINTER(_V)]
             L.solver_submit.argtypes = [_V, ctypes.POINTER(SolveRequest), ctypes.POINTER(ctypes.c_uint64)]
