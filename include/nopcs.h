@@ -190,6 +190,20 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
 int nopcs_set_piece_length(int32_t dir, int32_t piece_len);
 
 /*
+ * nopcs_autotune -- choose the piece length of each direction for this box by
+ * timing rk_step (one untimed step, then two timed with HIP events on
+ * hip_stream) on a scratch copy of Q for each candidate (n <= 64: 0, 16, 32;
+ * longer lines: 16, 24, 32 points), one direction after the other, and leave
+ * the fastest set with nopcs_set_piece_length (process-wide).  Candidates whose
+ * closure array would not fit ws_bytes are skipped.  Q is not modified; the
+ * call allocates and frees a 5-field scratch state and synchronises hip_stream.
+ * piece_out[3]: the lengths in force on return.  Results of later calls change
+ * by round-off only.
+ */
+int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,
+                   size_t ws_bytes, void *hip_stream, int32_t piece_out[3]);
+
+/*
  * nopcs_set_graphs -- on != 0: rk_step captures one RK4 step (all its kernel
  * launches) into a HIP graph on a private stream, the first time it sees a given
  * (device, state pointer, workspace pointer, box, parameters, precision, dt,

@@ -434,6 +434,71 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     return NOPCS_OK;
 }
 
+int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,
+                   size_t ws_bytes, void *hip_stream, int32_t piece_out[3]) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (precision != NOPCS_FP64 && precision != NOPCS_MIXED) { set_error("unknown precision"); return NOPCS_EINVAL; }
+    if (!Q || !piece_out) { set_error("Q and piece_out must be non-NULL"); return NOPCS_EINVAL; }
+    if (!check_ws(grid, precision, ws, ws_bytes)) return NOPCS_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t bytes = 5 * field_elems(grid) * sizeof(double);
+    double *scratch = nullptr;
+    NOPCS_HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&scratch), bytes));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = NOPCS_OK;
+    const double dt = 1e-9;   // any admissible step: only the time of the launches matters
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipMemcpyAsync(scratch, Q, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        set_error("autotune: device setup failed");
+        rc = NOPCS_EDEVICE;
+    }
+    // one step untimed (plans, caches), two timed; the copy keeps Q untouched
+    auto time_it = [&](float *ms) -> int {
+        int r = rk_step(params, grid, precision, scratch, dt, 1, ws, ws_bytes, hip_stream);
+        if (r != NOPCS_OK) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return NOPCS_EDEVICE;
+        r = rk_step(params, grid, precision, scratch, dt, 2, ws, ws_bytes, hip_stream);
+        if (r != NOPCS_OK) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return NOPCS_EDEVICE;
+        return NOPCS_OK;
+    };
+    int best[3];
+    for (int d = 0; d < 3; ++d) best[d] = g_piece_len[d].load();
+    for (int d = 0; d < 3 && rc == NOPCS_OK; ++d) {
+        const int n = grid->n[d];
+        const std::vector<int> cand = n <= 64 ? std::vector<int>{0, 16, 32} : std::vector<int>{16, 24, 32};
+        float best_ms = 0.0f;
+        int best_len = best[d];
+        bool any = false;
+        for (int len : cand) {
+            g_piece_len[d].store(len);
+            if (nopcs_workspace_bytes(grid, precision) > ws_bytes) continue;   // closure array would not fit
+            LinePlanDev pl[3];
+            if (get_plans(grid, pl) != NOPCS_OK) continue;                    // too many known rows per line
+            float ms = 0.0f;
+            rc = time_it(&ms);
+            if (rc != NOPCS_OK) break;
+            if (!any || ms < best_ms) {
+                best_ms = ms;
+                best_len = len;
+                any = true;
+            }
+        }
+        g_piece_len[d].store(best_len);
+        best[d] = best_len;
+    }
+    if (rc != NOPCS_OK)
+        for (int d = 0; d < 3; ++d) g_piece_len[d].store(best[d]);
+    for (int d = 0; d < 3; ++d) piece_out[d] = piece_length(d, grid->n[d]);
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    return rc;
+}
+
 int nopcs_set_graphs(int32_t on) {
     g_graphs.store(on ? 1 : 0);
     return NOPCS_OK;

@@ -82,6 +82,8 @@ def lib():
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
         L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
+        L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
+                                     ctypes.POINTER(ctypes.c_int32 * 3)]
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
         if hasattr(L, "solver_create"):
             L.solver_create.argtypes = [ctypes.POINTER(SolverConfig), ctypes.POINTER(_V)]
@@ -159,6 +161,19 @@ def rk_step(params, grid, Q, dt, nsteps, ws, precision=FP64, stream=None):
     nbytes = ws.numel() * ws.element_size()
     _check(lib().rk_step(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), float(dt), int(nsteps),
                          _ptr(ws), nbytes, _stream(stream)))
+
+
+def autotune(params, grid, Q, ws, precision=FP64, stream=None):
+    """Time rk_step for the candidate piece lengths on a copy of Q; returns the
+    chosen (x, y, z) lengths, which stay in force (process-wide)."""
+    out = (ctypes.c_int32 * 3)()
+    _check(lib().nopcs_autotune(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(out)))
+    return tuple(out)
+
+
+def set_piece_length(direction, length):
+    _check(lib().nopcs_set_piece_length(int(direction), int(length)))
 
 
 def alloc_workspace(grid, precision=FP64, device="cuda"):
