@@ -157,10 +157,12 @@ __global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, 
     }
     int ks[C::PTS];
     owned_slots<DIR, NMAX>(pl, ks);
-    static_assert(C::G == 3, "component grouping below assumes groups {0,1,2} and {3,4}");
-    nse_group<DIR, NMAX, 0, 3, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    static_assert(C::G == 2, "component grouping below assumes groups {0,1}, {2,3} and {4}");
+    nse_group<DIR, NMAX, 0, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
     __syncthreads();
-    nse_group<DIR, NMAX, 3, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    nse_group<DIR, NMAX, 2, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    __syncthreads();
+    nse_group<DIR, NMAX, 4, 1, TR>(a, g, pl, np, base, flux, ks, F, KN);
 }
 
 // ---------------------------------------------------------------------------

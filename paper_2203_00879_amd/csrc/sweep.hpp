@@ -30,7 +30,7 @@ struct SweepCfg {
     static constexpr int P = NMAX <= 128 ? 1024 / NMAX : 2048 / NMAX;
     static constexpr int NT = 256;                                   // threads per block
     static constexpr int PTS = (P * NMAX) / NT;                      // owned slots per thread
-    static constexpr int G = 3;                                      // components per LDS pass
+    static constexpr int G = 2;                                      // components per LDS pass
     static constexpr int KMAX = NMAX <= 128 ? NMAX / 2 + 4 : NMAX / 8 + 8;
     static constexpr int PAD = (NMAX >> 5) * 2 + 2;
     static constexpr int PITCH = NMAX + PAD + 1;                     // x layout line pitch
