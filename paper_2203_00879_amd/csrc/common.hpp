@@ -111,6 +111,11 @@ __host__ __device__ inline Prim prim_from(const NdConst &c, double rho, double m
     return q;
 }
 
+// a * b + c with one rounding (the build disables implicit contraction, so
+// every fused multiply-add of the kernels is written out with these)
+__host__ __device__ inline double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ inline float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Sutherland's law relative to T_s, mu/mu_s (Section 2).
 __host__ __device__ inline double mu_of(const NdConst &c, double T) {
     return T * sqrt(T) * (1.0 + c.St) / (T + c.St);

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
     auto runs = [&](int r) { return make_int2(runs_i[2 * r], runs_i[2 * r + 1]); };
     auto run_slot = [&](int r) { return make_int2(slot_i[2 * r], slot_i[2 * r + 1]); };
     const auto run_own = NOPCS_SCALAR_PTR(int, pl.run_own);
-    const auto den = NOPCS_SCALAR_PTR(TC, (sizeof(TC) == 8 ? (const void *)pl.den : (const void *)pl.den32));
+    const auto rden = NOPCS_SCALAR_PTR(TC, (sizeof(TC) == 8 ? (const void *)pl.rden : (const void *)pl.rden32));
     const auto cp = NOPCS_SCALAR_PTR(TC, (sizeof(TC) == 8 ? (const void *)pl.cp : (const void *)pl.cp32));
     const int2 gr = make_int2(grp_i[2 * grp], grp_i[2 * grp + 1]);
     const int lo0 = runs(gr.x).x;
@@ -284,7 +284,8 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
                     }
                     rr = rr - alpha * TC(xhi);
                 }
-                const TC dp = (rr - alpha * dprev) / den[k];
+                // (r_k - alpha d_{k-1}) / den_k as r_k / den_k - c'_k d_{k-1}
+                const TC dp = fma_(-cp[k], dprev, rr * rden[k]);
                 d[t] = dp;
                 dprev = dp;
                 advance();
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
 #pragma unroll
         for (int t = MRL - 1; t >= 0; --t) {
             const int k = t + 1;
-            const TC xs = k == m ? d[t] : d[t] - cp[k] * xn;
+            const TC xs = k == m ? d[t] : fma_(-cp[k], xn, d[t]);
             const TC xk = t < m ? xs : TC(0);
             xn = xk;
             const TR nv = ring[t % RA] - TR(xk);

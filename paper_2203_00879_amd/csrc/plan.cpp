@@ -170,12 +170,14 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
     // elimination tables of a constant-coefficient run, indexed by the position
     // k = 1, 2, ... inside the run (Thomas algorithm, Section 3)
     P.den.assign(n + 1, 0.0);
+    P.rden.assign(n + 1, 0.0);
     P.cp.assign(n + 1, 0.0);
     double cprev = 0.0;
     for (int k = 1; k <= n; ++k) {
         const double s = (k > 1) ? kAlpha : 0.0;
         const double den = 1.0 - s * cprev;
         P.den[k] = den;
+        P.rden[k] = 1.0 / den;
         P.cp[k] = kAlpha / den;
         cprev = P.cp[k];
     }
@@ -305,6 +307,7 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     const size_t o_len = off;  off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_coef = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
     const size_t o_c32 = off;  off = align256(off + sizeof(float) * ((size_t)ncl * kTaps + 1));
+    const size_t o_coefT = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
     const size_t o_kind = off; off = align256(off + (size_t)n);
     const size_t o_den = off;  off = align256(off + sizeof(double) * (n + 1));
     const size_t o_cp = off;   off = align256(off + sizeof(double) * (n + 1));
@@ -331,10 +334,14 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     cpy(o_coef, P.cl_coef.data(), sizeof(double) * (size_t)ncl * kTaps);
     std::vector<float> c32(P.cl_coef.begin(), P.cl_coef.end());
     cpy(o_c32, c32.data(), sizeof(float) * c32.size());
+    std::vector<double> coefT((size_t)ncl * kTaps, 0.0);
+    for (int q = 0; q < ncl; ++q)
+        for (int t = 0; t < kTaps; ++t) coefT[(size_t)t * ncl + q] = P.cl_coef[(size_t)q * kTaps + t];
+    cpy(o_coefT, coefT.data(), sizeof(double) * coefT.size());
     cpy(o_kind, P.row_kind.data(), (size_t)n);
-    cpy(o_den, P.den.data(), sizeof(double) * (n + 1));
+    cpy(o_den, P.rden.data(), sizeof(double) * (n + 1));
     cpy(o_cp, P.cp.data(), sizeof(double) * (n + 1));
-    std::vector<float> d32(P.den.begin(), P.den.end()), cp32(P.cp.begin(), P.cp.end());
+    std::vector<float> d32(P.rden.begin(), P.rden.end()), cp32(P.cp.begin(), P.cp.end());
     cpy(o_d32, d32.data(), sizeof(float) * (n + 1));
     cpy(o_c32b, cp32.data(), sizeof(float) * (n + 1));
     cpy(o_grp, P.grp.data(), sizeof(int2) * ngrp);
@@ -369,9 +376,10 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.cl_coef = reinterpret_cast<const double *>(b + o_coef);
     d.cl_coef32 = reinterpret_cast<const float *>(b + o_c32);
     d.row_kind = reinterpret_cast<const uint8_t *>(b + o_kind);
-    d.den = reinterpret_cast<const double *>(b + o_den);
+    d.rden = reinterpret_cast<const double *>(b + o_den);
     d.cp = reinterpret_cast<const double *>(b + o_cp);
-    d.den32 = reinterpret_cast<const float *>(b + o_d32);
+    d.rden32 = reinterpret_cast<const float *>(b + o_d32);
+    d.cl_coefT = reinterpret_cast<const double *>(b + o_coefT);
     d.cp32 = reinterpret_cast<const float *>(b + o_c32b);
     d.max_m = P.max_m;
     d.ngrp = ngrp;

@@ -27,10 +27,11 @@ struct LinePlanDev {
     const double *cl_coef; // [ncl][97] coefficients C_{e,j} * h, taps j0 .. j0+len-1
     const float *cl_coef32;// [ncl][97] the same rounded to FP32 (mixed precision)
     const uint8_t *row_kind;  // [n]
-    const double *den;     // [n] elimination pivots 1 - alpha c'_{k-1}, k = 1.. (index k)
+    const double *rden;    // [n] reciprocal elimination pivots 1 / (1 - alpha c'_{k-1}), k = 1..
     const double *cp;      // [n] c'_k = alpha / den_k
-    const float *den32;    // FP32 copies
+    const float *rden32;   // FP32 copies
     const float *cp32;
+    const double *cl_coefT;// [97][ncl] cl_coef transposed (tap-major), 0 past cl_len
     // ---- line-march tables (sweeps that stream along the line) ----
     int max_m;             // longest run (unknowns)
     int ngrp;              // run groups (consecutive runs marched by one thread)
@@ -61,7 +62,7 @@ struct LinePlanHost {
     std::vector<int> cl_row, cl_j0, cl_len;
     std::vector<double> cl_coef;      // ncl * kTaps
     std::vector<uint8_t> row_kind;
-    std::vector<double> den, cp;
+    std::vector<double> den, rden, cp;
     int max_m = 0, k1_S = 0;
     std::vector<int2> grp;
     std::vector<int> run_own, k1_rec, k1_evrow, k1_evmask;

@@ -87,86 +87,116 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
     const int n = pl.n;
     const double ih = pl.ih;
     // plan tables through the scalar path where the index is wave-uniform
-    const auto cl_row = NOPCS_SCALAR_PTR(int, pl.cl_row);
-    const auto cl_j0 = NOPCS_SCALAR_PTR(int, pl.cl_j0);
-    const auto cl_len = NOPCS_SCALAR_PTR(int, pl.cl_len);
-    const auto cl_coef = NOPCS_SCALAR_PTR(double, pl.cl_coef);
     const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
     const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
-    const auto den = NOPCS_SCALAR_PTR(double, pl.den);
+    const auto rden = NOPCS_SCALAR_PTR(double, pl.rden);
     const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
-    // ---- A: known rows (walls and closures), one thread per (component, line, row) ----
-    const int nk = 4 + pl.ncl;
-    for (int q = tid; q < NC * C::P * nk; q += C::NT) {
-        const int c = q / (C::P * nk), rest = q - c * (C::P * nk);
-        const int l = rest % C::P, s = rest / C::P;
+    // ---- A: known rows, one thread per (component, line, row); the closure
+    // items come first so that every thread has at most one of them ----
+    const int ncl = pl.ncl;
+    const int ncli = NC * C::P * ncl;
+    for (int q = tid; q < ncli + NC * C::P * 4; q += C::NT) {
+        const bool clo = q < ncli;
+        const int w = clo ? q : q - ncli;
+        const int l = w % C::P, rest = w / C::P;
+        const int c = rest % NC, s = rest / NC;     // s: closure index, or wall slot 0..3
         if (l >= np) continue;
         const double *f = F(c);
         double v;
-        if (s == 0) {
+        if (clo) {
+            // f'_e = sum_t C_{e,j0+t} (f_{j0+t} - f_e) / h over two interleaved
+            // partial sums, TB taps per batch: all coefficient loads of a batch are
+            // issued before the first is used.  Coefficients are tap-major and 0
+            // past the closure's length (the clamped row then adds 0), so the 8
+            // lanes sharing a closure and the closures of a wavefront read one row.
+            constexpr int TB = 8;
+            const int row = pl.cl_row[s], j0 = pl.cl_j0[s];
+            const double *coef = pl.cl_coefT + s;
+            const double fe = f[C::fidx(l, row)];
+            double a0 = 0.0, a1 = 0.0;
+            for (int t = 0; t < kTaps; t += TB, coef += TB * ncl) {
+                double cf[TB], fv[TB];
+#pragma unroll
+                for (int u = 0; u < TB; ++u) cf[u] = t + u < kTaps ? coef[u * ncl] : 0.0;
+#pragma unroll
+                for (int u = 0; u < TB; ++u) fv[u] = f[C::fidx(l, min(j0 + t + u, n - 1))] - fe;
+#pragma unroll
+                for (int u = 0; u < TB; u += 2) {
+                    a0 = fma_(cf[u], fv[u], a0);
+                    a1 = fma_(cf[u + 1], fv[u + 1], a1);
+                }
+            }
+            v = (a0 + a1) * ih;
+        } else if (s == 0) {
             const double f0 = f[C::fidx(l, 0)];
             v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
         } else if (s == 1) {
             v = 0.5 * ih * (f[C::fidx(l, 2)] - f[C::fidx(l, 0)]);
         } else if (s == 2) {
             v = 0.5 * ih * (f[C::fidx(l, n - 1)] - f[C::fidx(l, n - 3)]);
-        } else if (s == 3) {
+        } else {
             const double fl = f[C::fidx(l, n - 1)];
             v = -0.5 * ih * (4.0 * (f[C::fidx(l, n - 2)] - fl) - (f[C::fidx(l, n - 3)] - fl));
-        } else {
-            const int e = s - 4;
-            const int row = cl_row[e], j0 = cl_j0[e], len = cl_len[e];
-            const auto coef = cl_coef + (size_t)e * kTaps;
-            const double fe = f[C::fidx(l, row)];
-            double acc = 0.0;
-            for (int t = 0; t < len; ++t) acc += coef[t] * (f[C::fidx(l, j0 + t)] - fe);
-            v = acc * ih;
         }
-        KN(c)[C::kidx(s, l)] = v;
+        KN(c)[C::kidx(clo ? 4 + s : s, l)] = v;
     }
     __syncthreads();
     // ---- C: B f and Thomas on every run, one thread per (component, line, run) ----
+    // Forward: d_k = (r_k - alpha d_{k-1}) / den_k as r_k * (1/den_k) - c'_k d_{k-1}
+    // (c'_k = alpha / den_k), one fused multiply-add on the recurrence.  Both
+    // loops count k uniformly across the wavefront (table entries come through
+    // scalar loads issued one step ahead); LDS reads sit at clamped rows.
+    const int kmax = pl.max_m;
     for (int q = tid; q < NC * C::P * pl.nrun; q += C::NT) {
         const int c = q / (C::P * pl.nrun), rest = q - c * (C::P * pl.nrun);
         const int l = rest % C::P, r = rest / C::P;
         if (l >= np) continue;
         double *f = F(c);
         const double *kn = KN(c);
-        const int2 run = make_int2(runs_i[2 * r], runs_i[2 * r + 1]);
-        const int2 slot = make_int2(slot_i[2 * r], slot_i[2 * r + 1]);
-        const int lo = run.x, hi = run.y, m = hi - lo - 1;
-        const double xlo = kn[C::kidx(slot.x, l)];
-        const double xhi = kn[C::kidx(slot.y, l)];
-        // window f_{i-2} .. f_{i+2} at i = lo + 1; rows past hi + 1 are never used
+        const int lo = runs_i[2 * r], hi = runs_i[2 * r + 1], m = hi - lo - 1;
+        const double xlo = kn[C::kidx(slot_i[2 * r], l)];
+        const double xhi = kn[C::kidx(slot_i[2 * r + 1], l)];
+        // window f_{i-2} .. f_{i+2} at i = lo + 1; rows lo - 1 and hi + 1 are
+        // known rows (closures and walls come in adjacent pairs), whose F keeps f
         double w0 = f[C::fidx(l, lo - 1)];
         double w1 = f[C::fidx(l, lo)];
         double w2 = f[C::fidx(l, lo + 1)];
-        double w3 = f[C::fidx(l, lo + 2)];
-        double w4 = lo + 3 <= hi + 1 ? f[C::fidx(l, lo + 3)] : 0.0;
+        double w3 = f[C::fidx(l, min(lo + 2, hi + 1))];
+        double w4 = f[C::fidx(l, min(lo + 3, hi + 1))];
         double dprev = 0.0;
+        double cpk = cp[1], rdk = rden[1];
         for (int k = 1; k <= m; ++k) {
             const int i = lo + k;
-            const double dk = den[k];
-            const int inext = i + 3;
-            const bool more = inext <= hi + 1;
+            const double fn = f[C::fidx(l, min(i + 3, hi + 1))];
+            const double cpn = cp[k + 1], rdn = rden[k + 1];
             double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
             if (k == 1) rr = rr - kAlpha * xlo;
             if (k == m) rr = rr - kAlpha * xhi;
-            const double dp = (rr - kAlpha * dprev) / dk;
-            const double fn = more ? f[C::fidx(l, inext)] : 0.0;
+            const double dp = fma_(-cpk, dprev, rr * rdk);
             f[C::fidx(l, i)] = dp;
             dprev = dp;
+            cpk = cpn;
+            rdk = rdn;
             w0 = w1;
             w1 = w2;
             w2 = w3;
             w3 = w4;
             w4 = fn;
         }
-        for (int k = m - 1; k >= 1; --k) {
-            const int ix = C::fidx(l, lo + k);
-            const double x = f[ix] - cp[k] * dprev;
-            f[ix] = x;
-            dprev = x;
+        // backward: x_m = d_m, x_k = d_k - c'_k x_{k+1}; k runs from the plan's
+        // longest run down, lanes of shorter runs wait until k < m
+        double fcur = f[C::fidx(l, lo + max(min(kmax - 1, m - 1), 1))];
+        cpk = cp[max(kmax - 1, 1)];
+        for (int k = kmax - 1; k >= 1; --k) {
+            const double fnx = f[C::fidx(l, lo + max(min(k - 1, m - 1), 1))];
+            const double cpx = cp[max(k - 1, 1)];
+            if (k < m) {
+                const double x = fma_(-cpk, dprev, fcur);
+                f[C::fidx(l, lo + k)] = x;
+                dprev = x;
+            }
+            fcur = fnx;
+            cpk = cpx;
         }
     }
     __syncthreads();

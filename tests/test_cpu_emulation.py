@@ -77,22 +77,29 @@ def test_emulated_rhs(driver, tmp_path):
         assert _rel(R[c], Ro[c]) <= 1e-12
 
 
-def test_emulated_rk_step_matches_oracle_bitwise(driver, tmp_path):
-    """One segment per direction: the kernels follow the oracle's operation order."""
+def test_emulated_rk_step_matches_oracle(driver, tmp_path):
+    """One segment per direction: the kernels follow the oracle's operation order
+    except in the Thomas elimination, which multiplies by reciprocal pivots
+    (one rounding per row apart from the oracle's division)."""
     p = dict(inputs.AIR)
     Q = inputs.rti_state(16, seed=0)
     qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
     Q.tofile(qin)
     _run(driver, ["rk", 16, 16, 16, 1, 1, 1, 1.0, 1.0, 1.0, 1, 1, 2e-5, 2, qin, qout], tmp_path)
     G = np.fromfile(qout).reshape(Q.shape)
-    assert np.array_equal(G, oracle.rk4(p, Q, 2e-5, 2))
+    O = oracle.rk4(p, Q, 2e-5, 2)
+    assert np.array_equal(G[0], O[0])          # continuity: fluxes rho u_j, no elimination order
+    for c in range(1, 5):
+        assert _rel(G[c], O[c]) <= 1e-12
 
 
 @pytest.mark.parametrize("shape, v, g", [((60, 30, 20), 1, 1), ((30, 14, 131), 1, 0)])
-def test_emulated_rhs_tiles_bitwise(driver, tmp_path, shape, v, g):
+def test_emulated_rhs_tiles(driver, tmp_path, shape, v, g):
     """No extra cuts and one segment per direction: interior tiles (no wall
     inside the halo), wall tiles, shifted edge tiles and several z chunks of
-    the viscous kernel all reproduce the oracle bit for bit."""
+    the viscous kernel all reproduce the oracle to rounding (the viscous terms
+    and fluxes in the oracle's operation order, the Thomas elimination with
+    reciprocal pivots)."""
     p = dict(inputs.AIR, viscous=v, gravity=g)
     Q = inputs.smooth_state(shape, seed=11)
     qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
@@ -100,7 +107,9 @@ def test_emulated_rhs_tiles_bitwise(driver, tmp_path, shape, v, g):
     L = (1.0, 0.6, 1.4)
     _run(driver, ["rhs", *shape, 1, 1, 1, *L, v, g, qin, rout], tmp_path, piece=0)
     R = np.fromfile(rout).reshape(Q.shape)
-    assert np.array_equal(R, oracle.rhs(p, Q, L))
+    Ro = oracle.rhs(p, Q, L)
+    for c in range(5):
+        assert _rel(R[c], Ro[c]) <= 4e-15
 
 
 @pytest.mark.parametrize("shape, nseg, piece", [((8, 36, 100), (1, 2, 3), 16), ((8, 20, 200), (1, 1, 2), -1)])
