@@ -2,9 +2,9 @@
 //
 // Lines along y and z are strided in memory.  Staging whole lines in LDS gives
 // narrow pencils (a few consecutive x per row, scattered over many DRAM pages);
-// here a block owns 64 neighbouring lines (consecutive x, so every load and
-// store is one 512-byte row) and walks along the line direction, one wavefront
-// per flux component:
+// here a block owns 128 neighbouring lines (consecutive x, so every load and
+// store is one 1 KB row; 512-byte rows measured 25-30 % slower) and walks
+// along the line direction, two wavefronts per flux component:
 //
 //   k_closure_march  one pass over the rows that carry taps accumulates every
 //       closure row of the NOHAP split (Eqs. CS:fpCf, CS:fpCf_i) in a few
@@ -20,10 +20,11 @@
 //       back substitution fused with R -= f'.  The known rows bounding the runs
 //       come from the closure pass or from the explicit wall rows.
 //
-// Rows of the state reach the block through a two-chunk LDS ring: wavefront w
-// fetches field w of the next CH rows into registers while the block works on
-// the current chunk, and publishes them at the chunk boundary (one barrier per
-// chunk).  Every wavefront forms its own flux component from the staged row.
+// Rows of the state reach the block through a two-chunk LDS ring: the threads
+// of component w fetch field w of the next CH rows into registers while the
+// block works on the current chunk, and publish them at the chunk boundary
+// (one barrier per chunk).  Every thread forms its own flux component from the
+// staged row.
 // Arithmetic of the walls, the runs and the R update is operation for
 // operation that of the LDS sweeps.
 #include "kernels.hpp"
@@ -32,45 +33,59 @@ namespace nopcs {
 
 namespace {
 
-constexpr int MW = 64;      // lines per block (consecutive x)
+constexpr int MW = 128;     // lines per block (consecutive x; two wavefronts per component)
 constexpr int MRL = 32;     // longest run a thread keeps in registers
-constexpr int NCOMP = 5;    // flux components (one wavefront each) = state fields
-constexpr int CH = 8;       // rows per LDS chunk
+constexpr int NCOMP = 5;    // flux components (one row of MW threads each) = state fields
+constexpr int CH = 4;       // rows per LDS chunk
 
 // Convective flux component comp along DIR (ge3-ge5) from the staged row of
-// one line, formed as in the LDS sweeps.
+// one line.  Field 0 of a staged row holds 1/rho (the density threads take
+// the reciprocal once per row when they publish); the products are those of
+// prim_from, so the fluxes equal the LDS sweeps' bit for bit.
 template <int DIR>
 __device__ inline double flux_row(const double (*L)[MW], int lane, int comp, const NdConst &c) {
     if (comp == 0) return L[DIR + 1][lane];
-    const double rho = L[0][lane], md = L[DIR + 1][lane];
+    const double ri = L[0][lane], md = L[DIR + 1][lane];
     if (comp == 4 || comp == DIR + 1) {
-        const Prim pr = prim_from(c, rho, L[1][lane], L[2][lane], L[3][lane], L[4][lane]);
-        const double ud = DIR == 1 ? pr.v : pr.w;
-        if (comp == 4) return ((L[4][lane] + pr.pp) + c.H) * ud;
-        return md * ud + pr.pp;
+        const double mx = L[1][lane], my = L[2][lane], mz = L[3][lane], Ep = L[4][lane];
+        const double u = mx * ri, v = my * ri, w = mz * ri;
+        const double ke = 0.5 * (mx * u + my * v + mz * w);
+        const double pp = (c.gamma - 1.0) * (Ep - ke);
+        const double ud = DIR == 1 ? v : w;
+        if (comp == 4) return ((Ep + pp) + c.H) * ud;
+        return md * ud + pp;
     }
-    const double ri = 1.0 / rho;
     const double ud = md * ri;
     return L[comp][lane] * ud;
 }
 
-// Rows [row0, rowN] of the block's 64 lines pass through a two-chunk LDS ring
+// Rows [row0, rowN] of the block's MW lines pass through a two-chunk LDS ring
 // and are read strictly in order through next().
 struct RowPipe {
     double (*L)[CH][NCOMP][MW];   // [2][CH][field][lane]
-    const double *src;            // this wavefront's field at row 0 of its line (a valid
+    const double *src;            // this thread's field at row 0 of its line (a valid
                                   // address also for lanes past the last line)
     long long sD;
     int row0, rowN, lane, field;
     int u, k;                     // next row to read: slot u of chunk k
     double pre[CH];               // next chunk, in flight
     // unconditional loads (no branches: the compiler's memory waits stay
-    // precise); rows past rowN repeat row rowN and are never used
+    // precise); rows past rowN repeat row rowN and are never used.  The row
+    // offset steps by sD (a uniform select stops it at rowN).
     __device__ void fetch(int rb) {
+        long long off = sD * min(rb, rowN);
 #pragma unroll
-        for (int v = 0; v < CH; ++v) pre[v] = src[sD * min(rb + v, rowN)];
+        for (int v = 0; v < CH; ++v) {
+            pre[v] = src[off];
+            off += rb + v < rowN ? sD : 0;
+        }
     }
+    // field 0 (density) is published as 1/rho, the only form flux_row uses
     __device__ void publish(int buf) {
+        if (field == 0) {
+#pragma unroll
+            for (int v = 0; v < CH; ++v) pre[v] = 1.0 / pre[v];
+        }
 #pragma unroll
         for (int v = 0; v < CH; ++v) L[buf][v][field][lane] = pre[v];
     }
@@ -147,7 +162,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
     auto accumulate = [&](int j, double f) {
         const auto wj = k1_w + (size_t)j * S;
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] += wj[s] * (f - fr[s]);
+        for (int s = 0; s < S; ++s) acc[s] = fma_(wj[s], f - fr[s], acc[s]);
     };
     int j = jlo;
     for (int e = 0; e < pl.k1_nev; ++e) {
