@@ -21,7 +21,7 @@
 //       come from the closure pass or from the explicit wall rows.
 //
 // Rows of the state reach the block through a two-chunk LDS ring: the threads
-// of component w fetch field w of the next CH rows into registers while the
+// of component w fetch field w of the next few rows into registers while the
 // block works on the current chunk, and publish them at the chunk boundary
 // (one barrier per chunk).  Every thread forms its own flux component from the
 // staged row.
@@ -36,7 +36,8 @@ namespace {
 constexpr int MW = 128;     // lines per block (consecutive x; two wavefronts per component)
 constexpr int MRL = 32;     // longest run a thread keeps in registers
 constexpr int NCOMP = 5;    // flux components (one row of MW threads each) = state fields
-constexpr int CH = 4;       // rows per LDS chunk
+constexpr int CHC = 4;      // rows per LDS chunk: closure pass
+constexpr int CHM = 4;      // rows per LDS chunk: run march
 
 // Convective flux component comp along DIR (ge3-ge5) from the staged row of
 // one line.  Field 0 of a staged row holds 1/rho (the density threads take
@@ -61,6 +62,7 @@ __device__ inline double flux_row(const double (*L)[MW], int lane, int comp, con
 
 // Rows [row0, rowN] of the block's MW lines pass through a two-chunk LDS ring
 // and are read strictly in order through next().
+template <int CH>
 struct RowPipe {
     double (*L)[CH][NCOMP][MW];   // [2][CH][field][lane]
     const double *src;            // this thread's field at row 0 of its line (a valid
@@ -121,7 +123,7 @@ struct RowPipe {
 template <int DIR, int S>
 __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__restrict__ Q, double *__restrict__ clo,
                                                               MarchGeom g, LinePlanDev pl, NdConst c) {
-    __shared__ double L[2][CH][NCOMP][MW];
+    __shared__ double L[2][CHC][NCOMP][MW];
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int xc = b % g.nxc, o = b / g.nxc;
     const int lane = threadIdx.x;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
     const auto cl_wsum = NOPCS_SCALAR_PTR(double, pl.cl_wsum);
     const int jlo = cl_j0[0];
     const int jhi = cl_j0[pl.ncl - 1] + cl_len[pl.ncl - 1] - 1;
-    RowPipe P;
+    RowPipe<CHC> P;
     P.L = L;
     P.src = Q + comp * g.N3 + (ok ? base : 0);
     P.sD = g.sD;
@@ -203,7 +205,7 @@ template <int DIR, bool FULL, class TR, class TC>
 __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, TR *R,
                                                             const double *__restrict__ clo, MarchGeom g,
                                                             LinePlanDev pl, NdConst c) {
-    __shared__ double L[2][CH][NCOMP][MW];
+    __shared__ double L[2][CHM][NCOMP][MW];
     __shared__ double KV[2 * kGroupRuns][NCOMP][MW];   // closure values bounding the group's runs
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int xc = b % g.nxc, rest = b / g.nxc, o = rest % g.no, grp = rest / g.no;
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
         if (slot.x >= 4) KV[j][comp][lane] = ok ? clc[(long long)(slot.x - 4) * nlines] : 0.0;
         if (slot.y >= 4) KV[j + 1][comp][lane] = ok ? clc[(long long)(slot.y - 4) * nlines] : 0.0;
     }
-    RowPipe P;
+    RowPipe<CHM> P;
     P.L = L;
     P.src = Q + comp * g.N3 + (ok ? base : 0);
     P.sD = sD;

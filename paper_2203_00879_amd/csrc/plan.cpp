@@ -307,7 +307,7 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     const size_t o_len = off;  off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_coef = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
     const size_t o_c32 = off;  off = align256(off + sizeof(float) * ((size_t)ncl * kTaps + 1));
-    const size_t o_coefT = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
+    const size_t o_coefA = off; off = align256(off + sizeof(double) * ((size_t)ncl * 128 + 2));
     const size_t o_kind = off; off = align256(off + (size_t)n);
     const size_t o_den = off;  off = align256(off + sizeof(double) * (n + 1));
     const size_t o_cp = off;   off = align256(off + sizeof(double) * (n + 1));
@@ -334,10 +334,17 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     cpy(o_coef, P.cl_coef.data(), sizeof(double) * (size_t)ncl * kTaps);
     std::vector<float> c32(P.cl_coef.begin(), P.cl_coef.end());
     cpy(o_c32, c32.data(), sizeof(float) * c32.size());
-    std::vector<double> coefT((size_t)ncl * kTaps, 0.0);
-    for (int q = 0; q < ncl; ++q)
-        for (int t = 0; t < kTaps; ++t) coefT[(size_t)t * ncl + q] = P.cl_coef[(size_t)q * kTaps + t];
-    cpy(o_coefT, coefT.data(), sizeof(double) * coefT.size());
+    // closure taps on the four aligned 32-row blocks that hold the tap window
+    // (a window of 97 rows starting anywhere in a block ends in the fourth)
+    std::vector<double> coefA((size_t)ncl * 128, 0.0);
+    for (int q = 0; q < ncl; ++q) {
+        const int a0 = P.cl_j0[q] - 32 * (P.cl_j0[q] / 32);
+        for (int t = 0; t < P.cl_len[q]; ++t) {
+            const int a = a0 + t;
+            coefA[((size_t)(a / 2) * ncl + q) * 2 + (a % 2)] = P.cl_coef[(size_t)q * kTaps + t];
+        }
+    }
+    cpy(o_coefA, coefA.data(), sizeof(double) * coefA.size());
     cpy(o_kind, P.row_kind.data(), (size_t)n);
     cpy(o_den, P.rden.data(), sizeof(double) * (n + 1));
     cpy(o_cp, P.cp.data(), sizeof(double) * (n + 1));
@@ -379,7 +386,7 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.rden = reinterpret_cast<const double *>(b + o_den);
     d.cp = reinterpret_cast<const double *>(b + o_cp);
     d.rden32 = reinterpret_cast<const float *>(b + o_d32);
-    d.cl_coefT = reinterpret_cast<const double *>(b + o_coefT);
+    d.cl_coefA = reinterpret_cast<const double *>(b + o_coefA);
     d.cp32 = reinterpret_cast<const float *>(b + o_c32b);
     d.max_m = P.max_m;
     d.ngrp = ngrp;

@@ -31,7 +31,8 @@ struct LinePlanDev {
     const double *cp;      // [n] c'_k = alpha / den_k
     const float *rden32;   // FP32 copies
     const float *cp32;
-    const double *cl_coefT;// [97][ncl] cl_coef transposed (tap-major), 0 past cl_len
+    const double *cl_coefA;// [64][ncl][2] closure q's taps on the 128 rows from 32 * (cl_j0[q] / 32):
+                           // row a at [a / 2][q][a % 2], 0 outside the tap window
     // ---- line-march tables (sweeps that stream along the line) ----
     int max_m;             // longest run (unknowns)
     int ngrp;              // run groups (consecutive runs marched by one thread)

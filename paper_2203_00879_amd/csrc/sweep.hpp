@@ -35,6 +35,7 @@ struct SweepCfg {
     static constexpr int PAD = (NMAX >> 5) * 2 + 2;
     static constexpr int PITCH = NMAX + PAD + 1;                     // x layout line pitch
     static constexpr int FSZ = DIR == 0 ? P * PITCH : NMAX * P + PAD;
+    static constexpr int RSTEP = DIR == 0 ? 1 : P;                   // LDS step between rows of a line
     // LDS index of (line l, position i) inside one component buffer; the
     // 2-double step every 32 positions spreads concurrent runs over the banks
     __device__ static int fidx(int l, int i) {
@@ -91,6 +92,16 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
     const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
     const auto rden = NOPCS_SCALAR_PTR(double, pl.rden);
     const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
+    // rows n .. (n rounded up to 32) - 1 of every staged line read as zeros
+    // (phase A walks whole 32-row blocks)
+    const int ntail = ((n + 31) & ~31) - n;
+    if (ntail > 0) {
+        for (int q = tid; q < NC * C::P * ntail; q += C::NT) {
+            const int c = q / (C::P * ntail), rest = q - c * (C::P * ntail);
+            F(c)[C::fidx(rest % C::P, n + rest / C::P)] = 0.0;
+        }
+        __syncthreads();
+    }
     // ---- A: known rows, one thread per (component, line, row); the closure
     // items come first so that every thread has at most one of them ----
     const int ncl = pl.ncl;
@@ -104,26 +115,39 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         const double *f = F(c);
         double v;
         if (clo) {
-            // f'_e = sum_t C_{e,j0+t} (f_{j0+t} - f_e) / h over two interleaved
-            // partial sums, TB taps per batch: all coefficient loads of a batch are
-            // issued before the first is used.  Coefficients are tap-major and 0
-            // past the closure's length (the clamped row then adds 0), so the 8
-            // lanes sharing a closure and the closures of a wavefront read one row.
+            // f'_e = sum_t C_{e,j0+t} (f_{j0+t} - f_e) / h, walked over the aligned
+            // 32-row blocks that the tap window touches: inside a block the LDS
+            // offsets of the rows are compile-time constants, the table holds the
+            // taps of a block row pair in one 16-byte entry (zeros outside the
+            // window; rows past the line's end are zero in F), and the entries of
+            // the closures of a wavefront are adjacent.  Two interleaved partial
+            // sums; the loads of TB rows are issued before the first is used.
             constexpr int TB = 8;
-            const int row = pl.cl_row[s], j0 = pl.cl_j0[s];
-            const double *coef = pl.cl_coefT + s;
+            constexpr int RS = C::RSTEP;
+            const int row = pl.cl_row[s], j0 = pl.cl_j0[s], len = pl.cl_len[s];
+            const int b0 = j0 >> 5, nb = ((j0 + len - 1) >> 5) - b0 + 1;   // 1..4 blocks
+            const double2 *ctab = reinterpret_cast<const double2 *>(pl.cl_coefA);
             const double fe = f[C::fidx(l, row)];
             double a0 = 0.0, a1 = 0.0;
-            for (int t = 0; t < kTaps; t += TB, coef += TB * ncl) {
-                double cf[TB], fv[TB];
+            for (int bb = 0; bb < 4; ++bb) {
+                if (bb >= nb) break;
+                const int r0 = (b0 + bb) << 5;
+                const double *fb = f + C::fidx(l, r0);
+                NOPCS_LDS_BOUND(C::fidx(l, r0) + 31 * RS, C::FSZ);
+                const unsigned cofs = (unsigned)(16 * bb * ncl + s);
 #pragma unroll
-                for (int u = 0; u < TB; ++u) cf[u] = t + u < kTaps ? coef[u * ncl] : 0.0;
+                for (int j8 = 0; j8 < 32; j8 += TB) {
+                    double2 cf[TB / 2];
+                    double fv[TB];
 #pragma unroll
-                for (int u = 0; u < TB; ++u) fv[u] = f[C::fidx(l, min(j0 + t + u, n - 1))] - fe;
+                    for (int u = 0; u < TB / 2; ++u) cf[u] = (ctab + (size_t)(j8 / 2 + u) * ncl)[cofs];
 #pragma unroll
-                for (int u = 0; u < TB; u += 2) {
-                    a0 = fma_(cf[u], fv[u], a0);
-                    a1 = fma_(cf[u + 1], fv[u + 1], a1);
+                    for (int u = 0; u < TB; ++u) fv[u] = fb[(j8 + u) * RS] - fe;
+#pragma unroll
+                    for (int u = 0; u < TB / 2; ++u) {
+                        a0 = fma_(cf[u].x, fv[2 * u], a0);
+                        a1 = fma_(cf[u].y, fv[2 * u + 1], a1);
+                    }
                 }
             }
             v = (a0 + a1) * ih;
