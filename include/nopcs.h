@@ -90,8 +90,11 @@ int nopcs_version(void);
 int nopcs_release_plans(void);
 
 /* Workspace (device bytes) needed by nse_rhs and rk_step for this grid and
- * precision: three 5-field FP64 registers (the RK4 accumulator, the stage state
- * and the right-hand side; nse_rhs leaves them untouched) followed by the
+ * precision: three 5-field registers (the RK4 accumulator, the stage state and
+ * the right-hand side, FP64, the last FP32 under NOPCS_MIXED; nse_rhs leaves
+ * them untouched; in FP64, when the z sweep carries the RK4 update, the stage
+ * state is written over the right-hand side and those two swap roles every
+ * stage; their contents between calls are unspecified) followed by the
  * closure array of the sweeps along y and z (5 components x closure rows x
  * lines, the larger direction).  Depends on the piece length in force
  * (nopcs_set_piece_length).  Host only; returns 0 on invalid input. */

@@ -166,14 +166,18 @@ static size_t closure_bytes(const nopcs_grid *grid) {
 // convective sweep along d: line march (y, z) when the plan allows, LDS pencils
 // otherwise.  c32: the march eliminates in FP32 (mixed precision).
 static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, const LinePlanDev &pl, double *clo,
-                      bool c32, hipStream_t st) {
+                      bool c32, hipStream_t st, const RkFuse *rk = nullptr) {
     if (clo && march_usable(d, pl)) {
         NOPCS_HIP_CHECK(timed(NOPCS_K_CLOSURE_Y + (d - 1), st,
                               [&] { return launch_march_closures(d, a.Qin, clo, grid->n, pl, a.c, st); }));
         NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] {
-            return launch_march_runs(d, a.Qin, a.R, a.r32, c32, clo, grid->n, pl, a.c, st);
+            return launch_march_runs(d, a.Qin, a.R, a.r32, c32, clo, grid->n, pl, a.c, st, rk);
         }));
         return NOPCS_OK;
+    }
+    if (rk) {
+        set_error("internal: fused RK update requested on a sweep without the line march");
+        return NOPCS_EINVAL;
     }
     NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl, st); }));
     return NOPCS_OK;
@@ -204,17 +208,32 @@ static int launch_step(const nse_params &params, const nopcs_grid *grid, int pre
     a.dt = dt;
     a.half_dt = 0.5 * dt;
     a.sixth_dt = dt / 6.0;
+    // FP64 with the z line march: the stage update rides on the z sweep
+    // (RkFuse), which writes the next stage state over R; the two FP64 state
+    // buffers of the workspace (Qs, R) then swap roles every stage.
+    const bool fuse = !mixed && march_usable(2, pl[2]);
+    double *B[2] = {Qs, static_cast<double *>(R)};
     for (int stage = 0; stage < 4; ++stage) {
-        const double *Qin = stage == 0 ? Q : Qs;
+        void *Rs = fuse ? static_cast<void *>(B[(stage + 1) & 1]) : R;
+        const double *Qin = stage == 0 ? Q : (fuse ? B[stage & 1] : Qs);
         a.Qin = Qin;
+        a.R = Rs;
         a.stage = stage;
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, R, mixed, grid->n, ih, c, st); }));
-        for (int d = 0; d < 3; ++d) {
-            const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
-            if (rc != NOPCS_OK) return rc;
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st); }));
+        if (fuse) {
+            const RkFuse F{K, Q, stage, dt, 0.5 * dt, dt / 6.0};
+            for (int d = 0; d < 3; ++d) {
+                const int rc = conv_sweep(d, a, grid, pl[d], clo, false, st, d == 2 ? &F : nullptr);
+                if (rc != NOPCS_OK) return rc;
+            }
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
+                if (rc != NOPCS_OK) return rc;
+            }
+            NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
         }
-        NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
-        double *Qout = stage < 3 ? Qs : Q;
+        double *Qout = stage == 3 ? Q : fuse ? static_cast<double *>(Rs) : Qs;
         for (int d = 0; d < 3; ++d)
             NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
     }

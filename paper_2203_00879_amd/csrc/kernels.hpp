@@ -20,6 +20,17 @@ struct NseSweepArgs {
     NdConst c;
 };
 
+// RK4 stage update fused into the last convective sweep (FP64): the sweep's
+// k = R - f' goes straight into the stage registers instead of R; the new stage
+// state is written over R itself (each point's R is read and then written by
+// one thread only).
+struct RkFuse {
+    double *K;          // k1 + 2 k2 + 2 k3 accumulator
+    double *Qn;         // state at the start of the step (in/out at the last stage)
+    int stage;          // 0..3
+    double dt, half_dt, sixth_dt;
+};
+
 int nmax_class(int n);
 int sweep_lines_per_block(int dir, int n);
 int sweep_threads_per_block(int dir, int n);
@@ -50,7 +61,7 @@ hipError_t launch_march_closures(int dir, const double *Q, double *clo, const in
 // R <- R - D_dir(convective flux) for the 5 components, closures from clo;
 // r32: R is stored in FP32; c32: the elimination runs in FP32
 hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
-                             const LinePlanDev &pl, const NdConst &c, hipStream_t st);
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk = nullptr);
 
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,

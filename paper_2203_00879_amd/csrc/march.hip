@@ -200,11 +200,13 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
 // Run march
 // ---------------------------------------------------------------------------
 // TR: storage type of R; TC: arithmetic of the elimination (B f is formed in
-// FP64 from the FP64 window and rounded once; known rows stay FP64)
-template <int DIR, bool FULL, class TR, class TC>
+// FP64 from the FP64 window and rounded once; known rows stay FP64).
+// RKS >= 0 (FP64 only): RK4 stage RKS fused into the epilogue, see RkFuse.
+template <int DIR, bool FULL, class TR, class TC, int RKS>
 __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, TR *R,
                                                             const double *__restrict__ clo, MarchGeom g,
-                                                            LinePlanDev pl, NdConst c) {
+                                                            LinePlanDev pl, NdConst c, RkFuse F) {
+    static_assert(RKS < 0 || (sizeof(TR) == 8 && sizeof(TC) == 8), "the fused RK update is FP64 only");
     __shared__ double L[2][CHM][NCOMP][MW];
     __shared__ double KV[2 * kGroupRuns][NCOMP][MW];   // closure values bounding the group's runs
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -268,6 +270,71 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
         ++i;
     };
 
+    // Fused RK4 stage (RKS >= 0): back substitution in place, then per row
+    // k = R - f' and the register update of RKS (operation for operation that
+    // of k_rk_update); stage 0-2 write K and the next stage state (over R),
+    // stage 3 writes Qn.  Rows are fetched RB steps ahead at clamped rows;
+    // steps past the run store nothing.
+    double *const Kc = RKS >= 0 ? F.K + comp * g.N3 + (ok ? base : 0) : nullptr;
+    double *const Nc = RKS >= 0 ? F.Qn + comp * g.N3 + (ok ? base : 0) : nullptr;
+    auto rk_point = [&](long long off, double rv, double kk, double qn, double x) {
+        const double kv = rv - x;
+        if constexpr (RKS == 0) {
+            Kc[off] = kv;
+            reinterpret_cast<double *>(Rc)[off] = qn + F.half_dt * kv;
+        } else if constexpr (RKS == 1) {
+            Kc[off] = kk + 2.0 * kv;
+            reinterpret_cast<double *>(Rc)[off] = qn + F.half_dt * kv;
+        } else if constexpr (RKS == 2) {
+            Kc[off] = kk + 2.0 * kv;
+            reinterpret_cast<double *>(Rc)[off] = qn + F.dt * kv;
+        } else {
+            Nc[off] = qn + F.sixth_dt * (kk + kv);
+        }
+    };
+    auto rk_epilogue = [&](TC (&d)[MRL], int m, int lo, int hi, int own, double xlo, double xhi, double v0,
+                           double vn) {
+        TC xn = TC(0);
+#pragma unroll
+        for (int t = MRL - 1; t >= 0; --t) {
+            const int k = t + 1;
+            const TC xs = k == m ? d[t] : fma_(-cp[k], xn, d[t]);
+            d[t] = t < m ? xs : TC(0);
+            xn = d[t];
+        }
+        constexpr int RB = 4;
+        auto rrow = [&](int t) { return sD * (lo + 1 + (t < m ? t : m - 1)); };
+        double fr[RB], fk[RB], fq[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            fr[t] = double(Rc[rrow(t)]);
+            fk[t] = RKS > 0 ? Kc[rrow(t)] : 0.0;
+            fq[t] = Nc[rrow(t)];
+        }
+        // the known rows this run may update (rows outside lo+1 .. hi-1)
+        const long long klo = sD * lo, khi = sD * hi, kn = sD * (n - 1);
+        const double rlo = double(Rc[klo]), rhi = double(Rc[khi]), r0 = double(Rc[0]), rn = double(Rc[kn]);
+        const double klo_k = RKS > 0 ? Kc[klo] : 0.0, khi_k = RKS > 0 ? Kc[khi] : 0.0;
+        const double k0_k = RKS > 0 ? Kc[0] : 0.0, kn_k = RKS > 0 ? Kc[kn] : 0.0;
+        const double qlo = Nc[klo], qhi = Nc[khi], q0 = Nc[0], qnn = Nc[kn];
+#pragma unroll
+        for (int t = 0; t < MRL; ++t) {
+            const double rv = fr[t % RB], kk = fk[t % RB], qn = fq[t % RB];
+            if (t + RB < MRL) {
+                fr[t % RB] = double(Rc[rrow(t + RB)]);
+                if (RKS > 0) fk[t % RB] = Kc[rrow(t + RB)];
+                fq[t % RB] = Nc[rrow(t + RB)];
+            }
+            if (ok && t < m) rk_point(rrow(t), rv, kk, qn, double(d[t]));
+        }
+        if (ok) {
+            if (own & 1) rk_point(klo, rlo, klo_k, qlo, xlo);
+            if (own & 2) rk_point(khi, rhi, khi_k, qhi, xhi);
+            if (own & 4) rk_point(0, r0, k0_k, q0, v0);
+            if (own & 8) rk_point(kn, rn, kn_k, qnn, vn);
+        }
+    };
+
     for (int r = gr.x; r < gr.y; ++r) {
         const int2 run = runs(r);
         const int lo = run.x, hi = run.y, m = hi - lo - 1;
@@ -307,6 +374,10 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
                 dprev = dp;
                 advance();
             }
+        }
+        if constexpr (RKS >= 0) {
+            rk_epilogue(d, m, lo, hi, own, xlo, xhi, v0, vn);
+            continue;
         }
         // back substitution (x_m = d_m, x_k = d_k - c'_k x_{k+1}) fused with
         // R -= f'.  The loop is straight-line over MRL steps so that memory
@@ -391,17 +462,41 @@ static hipError_t launch_runs_t(int dir, const double *Q, TR *R, const double *c
                                 const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
     const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
     const bool full = g.nx % MW == 0;
-    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
-    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false, TR, TC>), grd, blk, 0, st, Q, R, clo, g, pl, c);
+    const RkFuse F{};
+    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+// z sweep with the RK4 stage update fused (FP64)
+template <int S>
+static hipError_t launch_runs_rk(const double *Q, double *R, const double *clo, const MarchGeom &g,
+                                 const LinePlanDev &pl, const NdConst &c, const RkFuse &F, hipStream_t st) {
+    const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
+    if (g.nx % MW == 0)
+        hipLaunchKernelGGL((k_march_sweep<2, true, double, double, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+    else
+        hipLaunchKernelGGL((k_march_sweep<2, false, double, double, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+    return hipGetLastError();
+}
+
 hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
-                             const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk) {
     const MarchGeom g = march_geom(n, dir);
+    if (rk) {
+        if (dir != 2 || r32 || c32) return hipErrorInvalidValue;
+        double *Rd = static_cast<double *>(R);
+        switch (rk->stage) {
+            case 0: return launch_runs_rk<0>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 1: return launch_runs_rk<1>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 2: return launch_runs_rk<2>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 3: return launch_runs_rk<3>(Q, Rd, clo, g, pl, c, *rk, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (!c32) return launch_runs_t<double, double>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
     if (!r32) return launch_runs_t<double, float>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
     return launch_runs_t<float, float>(dir, Q, static_cast<float *>(R), clo, g, pl, c, st);
