@@ -249,8 +249,9 @@ typedef struct {
  * admits queued requests in arrival order while a slot is free and their device
  * footprint (state + nopcs_workspace_bytes) fits hbm_budget_bytes, and keeps every
  * resident request advancing in chunks of RK4 steps on its own stream (continuous
- * batching; a request's arithmetic is that of rk_step on its box alone).  Serves the
- * FP64 path.  *out is owned by the caller until solver_destroy. */
+ * batching; a request's arithmetic is that of rk_step on its box alone, in the
+ * request's precision, NOPCS_FP64 or NOPCS_MIXED).  *out is owned by the caller
+ * until solver_destroy. */
 int solver_create(const solver_config *cfg, nopcs_solver **out);
 
 /* Queue a request (non-blocking; the initial state is copied).  NOPCS_EBUSY if the

@@ -242,7 +242,10 @@ int solver_submit(nopcs_solver *s, const solve_request *req, uint64_t *id_out) {
         nopcs::set_error("request: need nsteps >= 1, dt > 0 finite and Q0_host");
         return NOPCS_EINVAL;
     }
-    if (req->precision != NOPCS_FP64) { nopcs::set_error("request: only NOPCS_FP64 is served"); return NOPCS_EINVAL; }
+    if (req->precision != NOPCS_FP64 && req->precision != NOPCS_MIXED) {
+        nopcs::set_error("request: precision must be NOPCS_FP64 or NOPCS_MIXED");
+        return NOPCS_EINVAL;
+    }
     size_t ws = 0;
     const size_t fp = footprint_of(*req, &ws);
     if (fp == 0) return NOPCS_EINVAL;   // grid error already recorded

@@ -7,11 +7,13 @@ fixed step of inputs.stable_dt, max(1, N // 64) segments per direction;
 exponential inter-arrival times (mean 50 ms, 20 requests/s).  Every draw comes
 from numpy.random.default_rng(4), in the order (gap, N, dT, steps) per request.
 
+Every request runs in one precision (--precision: mixed, the default, or fp64).
+
 Prints one JSON line: aggregate Mpoint-stage/s, p50 / p99 latency (submit to
 done), admission delay percentiles, the number of requests, and (with --check)
 whether each checked request equals the same box run alone, bit for bit.
 
-    python -m paper_2203_00879_amd.serve_bench [--requests 256] [--step-scale 1.0]
+    python -m paper_2203_00879_amd.serve_bench [--requests 256] [--step-scale 1.0] [--precision mixed]
 """
 import argparse
 import json
@@ -47,8 +49,9 @@ def request_state(w, seed):
     return inputs.rti_state(w["n"], T_upper=300.0, T_lower=300.0 + w["dT"], seed=seed)
 
 
-def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False):
+def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False, precision="mixed"):
     import torch
+    prec = nopcs.MIXED if precision == "mixed" else nopcs.FP64
     params = nopcs.make_params(inputs.AIR)
     W = workload(n_req, step_scale=step_scale)
     states = [request_state(w, i) for i, w in enumerate(W)]
@@ -63,7 +66,7 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
         while k < n_req or pending:
             now = time.perf_counter() - t0
             while k < n_req and W[k]["t"] <= now:
-                rid = S.submit(params, grids[k], states[k], W[k]["steps"], dts[k])
+                rid = S.submit(params, grids[k], states[k], W[k]["steps"], dts[k], precision=prec)
                 ids[rid] = k
                 pending.add(rid)
                 k += 1
@@ -84,7 +87,9 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
     first = min(r[1] for r in results.values())
     last = max(r[3] for r in results.values())
     out = {
-        "metric": "serving: Mpoint-stage/s and request latency (RTI boxes 32^3..192^3, FP64)",
+        "metric": "serving: Mpoint-stage/s and request latency (RTI boxes 32^3..192^3, %s)" %
+                  ("mixed precision" if prec == nopcs.MIXED else "FP64"),
+        "precision": precision,
         "requests": n_req, "all_ok": ok, "slots": slots,
         "Mpoint_stage_per_s": pst / (last - first) / 1e6,
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
@@ -97,8 +102,8 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
         same = []
         for i in range(check):
             Qd = torch.from_numpy(states[i]).to("cuda")
-            ws = nopcs.alloc_workspace(grids[i])
-            nopcs.rk_step(params, grids[i], Qd, dts[i], W[i]["steps"], ws)
+            ws = nopcs.alloc_workspace(grids[i], prec)
+            nopcs.rk_step(params, grids[i], Qd, dts[i], W[i]["steps"], ws, precision=prec)
             torch.cuda.synchronize()
             same.append(bool(np.array_equal(Qd.cpu().numpy(), results[i][4])))
         out["mix_equals_alone"] = all(same)
@@ -114,8 +119,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--check", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     a = ap.parse_args()
-    print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose)), flush=True)
+    print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose, a.precision)), flush=True)
 
 
 if __name__ == "__main__":

@@ -151,6 +151,9 @@ static int serve_checks() {
         rq.nsteps = 0;
         SERVE_CHECK(solver_submit(s, &rq, &id) == NOPCS_EINVAL, "nsteps 0 rejected");
         rq.nsteps = 8;   // one chunk: keeps the slot busy while the queue fills
+        rq.precision = 7;
+        SERVE_CHECK(solver_submit(s, &rq, &id) == NOPCS_EINVAL, "unknown precision rejected");
+        rq.precision = NOPCS_FP64;
         nopcs_grid big = g;
         big.n[0] = 16;
         solve_request rb = rq;

@@ -11,11 +11,11 @@ from paper_2203_00879_amd import inputs, nopcs
 pytestmark = pytest.mark.gpu
 
 
-def _alone(params, grid, Q0, steps, dt):
+def _alone(params, grid, Q0, steps, dt, precision=nopcs.FP64):
     import torch
     Q = torch.from_numpy(Q0).to("cuda")
-    ws = nopcs.alloc_workspace(grid)
-    nopcs.rk_step(params, grid, Q, dt, steps, ws)
+    ws = nopcs.alloc_workspace(grid, precision)
+    nopcs.rk_step(params, grid, Q, dt, steps, ws, precision=precision)
     torch.cuda.synchronize()
     return Q.cpu().numpy()
 
@@ -48,6 +48,26 @@ def test_mix_equals_alone_bitwise():
             assert rc == nopcs.NOPCS_OK and res.steps_done == steps
             assert np.array_equal(Q, ref)
             assert res.t_submit <= res.t_admit <= res.t_done
+
+
+def test_mixed_precision_requests_equal_alone_bitwise():
+    """Mixed-precision requests (FP32 eliminations and RHS register) served beside
+    FP64 ones: each equals its box advanced alone by rk_step in its precision."""
+    params = nopcs.make_params(inputs.AIR)
+    dt = 1e-5
+    work = []
+    for n, nseg, steps, seed, prec in [(48, 1, 5, 7, nopcs.MIXED), (72, 1, 4, 8, nopcs.FP64),
+                                        (96, 2, 3, 9, nopcs.MIXED)]:
+        Q0 = inputs.rti_state(n, seed=seed, T_lower=420.0)
+        g = nopcs.make_grid(n, nseg)
+        work.append((g, Q0, steps, prec, _alone(params, g, Q0, steps, dt, prec)))
+    with nopcs.Solver(16 << 30, max_slots=3, max_queue=8) as S:
+        ids = [S.submit(params, g, Q0, steps, dt, precision=prec) for g, Q0, steps, prec, _ in work]
+        for rid, (g, Q0, steps, prec, ref) in zip(ids, work):
+            rc, res, Q = _wait(S, rid)
+            print("request", rid, "precision", prec, "status", rc, flush=True)
+            assert rc == nopcs.NOPCS_OK and res.steps_done == steps
+            assert np.array_equal(Q, ref)
 
 
 def test_admission_order_and_budget():
