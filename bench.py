@@ -74,8 +74,9 @@ def source_hash(name):
     return h.hexdigest()[:16]
 
 
-def load_traffic(name, workload_key):
-    """HBM bytes per launch from committed counter runs, if taken on the current source."""
+def load_counter_record(name, workload_key, field):
+    """A per-launch figure of a committed counter run (profiles/traffic.json: HBM
+    bytes, FP64 flops), if taken on the kernel's current source."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -83,10 +84,15 @@ def load_traffic(name, workload_key):
         d = json.load(open(p))
         rec = d.get(workload_key, {}).get(name)
         if rec and rec.get("source_hash") == source_hash(name):
-            return rec.get("bytes_per_launch")
+            return rec.get(field)
     except Exception:
         return None
     return None
+
+
+def load_traffic(name, workload_key):
+    """HBM bytes per launch from committed counter runs, if taken on the current source."""
+    return load_counter_record(name, workload_key, "bytes_per_launch")
 
 
 def cpu_baseline(n=128, steps=1):
@@ -192,6 +198,7 @@ def main():
     achieved = bpl / avg_s / 1e9
     workload_key = "rti_%d_fp64_seg%d" % (n, args.nseg)
     traffic = load_traffic(dom, workload_key)
+    flop = load_counter_record(dom, workload_key, "fp64_flop_per_launch") if pr == "fp64" else None
     kernels = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
                    "alg_GBps": (bpp(k) * N3 / (v[0] / v[1] / 1e3) / 1e9) if bpp(k) else None}
                for k, v in per.items()}
@@ -217,6 +224,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": bpl, "mean_launch_ms": avg_s * 1e3},
         "step_algorithmic_frac": 170.0 * pstage / sec / 1e9 / HBM_PEAK_GBS,
+        # FP64 VALU rate of the dominant kernel: counter-measured FP64 flops per
+        # launch (64 lanes x (add + mul + trans + 2 fma) instructions) / its mean
+        # launch time, against the FP64 vector peak (null if the counters were
+        # taken on other sources)
+        "fp64_valu": None if flop is None else {
+            "kernel": dom, "achieved": flop / avg_s / 1e12, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": flop / avg_s / 1e12 / FP64_VALU_PEAK_TFLOPS},
         "kernels": kernels,
         "finite": finite,
         "wall_s": wall,
