@@ -151,44 +151,44 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
     P.start();
     const auto ev_row = NOPCS_SCALAR_PTR(int, pl.k1_evrow);
     const auto ev_msk = NOPCS_SCALAR_PTR(int, pl.k1_evmask);
-    double acc[S], fr[S], fe[S];
+    // slot sums against one reference per line, the flux f_r of the first row:
+    //   acc_s = sum_j C_ej (f_j - f_r) - (f_e - f_r) sum_j C_ej,
+    // the second term taken when the slot meets its closure row e; equal to
+    // sum_j C_ej (f_j - f_e) in real arithmetic and zero for a constant field
+    double acc[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        acc[s] = 0.0;
-        fr[s] = 0.0;
-        fe[s] = 0.0;
-    }
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    double fref = 0.0;
     // every slot accumulates every row (an idle slot carries a zero tap, which
     // leaves its sum unchanged); slots open, meet their closure row and close
     // only on the listed event rows, handled outside the plain row loop
-    auto accumulate = [&](int j, double f) {
+    auto accumulate = [&](int j, double g) {
         const auto wj = k1_w + (size_t)j * S;
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] = fma_(wj[s], f - fr[s], acc[s]);
+        for (int s = 0; s < S; ++s) acc[s] = fma_(wj[s], g, acc[s]);
     };
     int j = jlo;
     for (int e = 0; e < pl.k1_nev; ++e) {
         const int je = ev_row[e];
-        for (; j < je; ++j) accumulate(j, flux_row<DIR>(P.next(), lane, comp, c));
+        for (; j < je; ++j) accumulate(j, flux_row<DIR>(P.next(), lane, comp, c) - fref);
         const double f = flux_row<DIR>(P.next(), lane, comp, c);
+        if (e == 0) fref = f;   // the first event row is the line's first row (a slot opens there)
+        const double g = f - fref;
         const int open = ev_msk[3 * e], erow = ev_msk[3 * e + 1], close = ev_msk[3 * e + 2];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (open & (1 << s)) {
-                fr[s] = f;
-                acc[s] = 0.0;
-            }
-            if (erow & (1 << s)) fe[s] = f;
-        }
-        accumulate(j, f);
+        for (int s = 0; s < S; ++s)
+            if (open & (1 << s)) acc[s] = 0.0;
+        accumulate(j, g);
+        const auto rec = k1_rec + (size_t)j * S;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (erow & (1 << s)) acc[s] = acc[s] - g * cl_wsum[rec[s] & 0xfff];
         if (close) {
-            const auto rec = k1_rec + (size_t)j * S;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 if (close & (1 << s)) {
                     const int qi = rec[s] & 0xfff;
-                    const double v = (acc[s] - (fe[s] - fr[s]) * cl_wsum[qi]) * pl.ih;
-                    if (ok) clo[((long long)comp * pl.ncl + qi) * nlines + line] = v;
+                    if (ok) clo[((long long)comp * pl.ncl + qi) * nlines + line] = acc[s] * pl.ih;
                 }
             }
         }
