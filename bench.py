@@ -121,8 +121,8 @@ def main():
     ap.add_argument("--dt", type=float, default=1e-6)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=192)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-n", type=int, default=256)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="GiB: run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
