@@ -236,6 +236,33 @@ def test_rk_quiescent_state_unchanged():
     assert np.array_equal(G, Q)
 
 
+def test_rk_512_one_step_bench_configuration():
+    """The timed configuration itself: 512^3 RTI box, 4 segments per direction,
+    default pieces (so the z line march carries the RK4 update), dt = 1e-6, one
+    RK4 step, every point of all 5 fields against the oracle's global solves."""
+    n = 512
+    p = dict(inputs.AIR)
+    say("building 512^3 RTI state")
+    Q = inputs.rti_state(n, seed=0)
+    g = nopcs.make_grid(n, 4)
+    Qd = to_dev(Q)
+    ws = nopcs.alloc_workspace(g)
+    nopcs.rk_step(nopcs.make_params(p), g, Qd, 1e-6, 1, ws)
+    torch.cuda.synchronize()
+    G = Qd.cpu().numpy()
+    del Qd, ws
+    torch.cuda.empty_cache()
+    say("oracle: one RK4 step at 512^3 on the host")
+    O = oracle.rk4(p, Q, 1e-6, 1)
+    for c in range(5):
+        e = rel_err(G[c], O[c])
+        ch = float(np.max(np.abs(G[c] - O[c])) / max(np.max(np.abs(O[c] - Q[c])), 1e-300))
+        say("  field", c, "err %.3e of the field, %.3e of its change" % (e, ch))
+        # one step is short enough for the wall-density conditioning of the RTI
+        # momentum (test_rk_rti_segmented_short) to stay far below the tolerance
+        assert e <= TOL and ch <= TOL
+
+
 def test_rk_rti_segmented_short():
     """RTI box 40 x 36 x 44 with 2 x 3 x 2 segments, 4 RK4 steps at dt = 1e-5: all 5 fields."""
     p = dict(inputs.AIR)
