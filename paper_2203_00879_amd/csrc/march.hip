@@ -10,13 +10,14 @@
 //       closure row of the NOHAP split (Eqs. CS:fpCf, CS:fpCf_i) in a few
 //       register slots,
 //         f'_e = [sum_j C_ej (f_j - f_r) - (f_e - f_r) sum_j C_ej] / h,
-//       with f_r the flux at the first tap.  In exact arithmetic this is
+//       with f_r the flux at the line's first row.  In exact arithmetic this is
 //       sum_j C_ej (f_j - f_e) (the form the LDS sweeps use); both vanish
 //       exactly for a constant field.  Results go to a small array
 //       [component][closure][line].
 //   k_march_sweep  walks a group of consecutive Thomas runs of a line: (B f)_i
 //       from a five-value register window, forward elimination with the
-//       tabulated pivots (Section 3) into registers (runs of <= 32 unknowns),
+//       tabulated reciprocal pivots (Section 3) into registers (runs of <= 32
+//       unknowns),
 //       back substitution fused with R -= f'.  The known rows bounding the runs
 //       come from the closure pass or from the explicit wall rows.
 //

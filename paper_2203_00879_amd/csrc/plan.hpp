@@ -49,7 +49,7 @@ struct LinePlanDev {
 };
 
 // Closure-slot record flags (line-march closure pass).
-constexpr int kRecOpen = 1 << 20;   // first tap: the reference value is this row's flux
+constexpr int kRecOpen = 1 << 20;   // first tap: the slot's sum starts at this row
 constexpr int kRecRow = 1 << 21;    // this row is the closure row e itself
 constexpr int kRecClose = 1 << 22;  // last tap: the closure value is complete
 constexpr int kMaxSlots = 16;

@@ -6,11 +6,12 @@
 //   A  known rows: the explicit wall rows and the segment-end (closure) rows
 //      f'_e = sum_j C_{e,j} (f_j - f_e) / h with C the global A^-1 B truncated
 //      to |j - e| <= 48 (Eqs. CS:fpCf, CS:fpCf_i; the f_e shift is exact for the
-//      untruncated row and makes constant fields differentiate to exactly 0).
+//      untruncated row and makes constant fields differentiate to exactly 0),
+//      walked over aligned 32-row blocks with a per-plan coefficient table.
 //      Results go to a side array KN, so known rows of F keep their f values.
 //   C  one thread per (line, run) -- a run is the set of compact rows between
 //      two known rows -- forms (B f)_i from a five-point register window and
-//      runs the Thomas algorithm (tabulated pivots) with the known rows as
+//      runs the Thomas algorithm (tabulated reciprocal pivots) with the known rows as
 //      boundary values, overwriting the run's rows of F with f'.  The rows just
 //      outside a run are known rows and are never overwritten, so runs need no
 //      halo exchange.
