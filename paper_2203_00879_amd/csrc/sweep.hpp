@@ -188,15 +188,29 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         double w2 = f[C::fidx(l, lo + 1)];
         double w3 = f[C::fidx(l, min(lo + 2, hi + 1))];
         double w4 = f[C::fidx(l, min(lo + 3, hi + 1))];
-        double dprev = 0.0;
-        double cpk = cp[1], rdk = rden[1];
-        for (int k = 1; k <= m; ++k) {
+        // row k = 1 (every lane starts there) with the lower known value; the
+        // upper known value enters row m after the loop: d_m gains
+        // -alpha x_hi / den_m, the only place where it appears
+        double dprev;
+        {
+            const double fn = f[C::fidx(l, min(lo + 4, hi + 1))];
+            double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+            rr = rr - kAlpha * xlo;
+            dprev = rr * rden[1];
+            f[C::fidx(l, lo + 1)] = dprev;
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            w3 = w4;
+            w4 = fn;
+        }
+        double cpk = cp[2], rdk = rden[2];
+#pragma unroll 2
+        for (int k = 2; k <= m; ++k) {
             const int i = lo + k;
             const double fn = f[C::fidx(l, min(i + 3, hi + 1))];
             const double cpn = cp[k + 1], rdn = rden[k + 1];
-            double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
-            if (k == 1) rr = rr - kAlpha * xlo;
-            if (k == m) rr = rr - kAlpha * xhi;
+            const double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
             const double dp = fma_(-cpk, dprev, rr * rdk);
             f[C::fidx(l, i)] = dp;
             dprev = dp;
@@ -208,6 +222,8 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             w3 = w4;
             w4 = fn;
         }
+        dprev = fma_(-kAlpha * xhi, pl.rden[m], dprev);
+        f[C::fidx(l, lo + m)] = dprev;
         // backward: x_m = d_m, x_k = d_k - c'_k x_{k+1}; k runs from the plan's
         // longest run down, lanes of shorter runs wait until k < m
         double fcur = f[C::fidx(l, lo + max(min(kmax - 1, m - 1), 1))];

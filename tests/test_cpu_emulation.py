@@ -53,13 +53,16 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / (s if s > 0 else 1.0)
 
 
-def test_emulated_derivative_segmented(driver, tmp_path):
-    f = np.random.default_rng(1).normal(size=(22, 19, 27))
+@pytest.mark.parametrize("shape, nseg", [((27, 19, 22), (3, 2, 4)), ((16, 17, 20), (4, 4, 5))])
+def test_emulated_derivative_segmented(driver, tmp_path, shape, nseg):
+    """Segmented lines, the second case with 4-point segments (Thomas runs of a
+    single unknown, whose first row is also its last)."""
+    f = np.random.default_rng(1).normal(size=shape[::-1])
     fin, fout = tmp_path / "f.raw", tmp_path / "d.raw"
     f.tofile(fin)
     L = (1.0, 0.8, 1.1)
     for d in range(3):
-        _run(driver, ["deriv", 27, 19, 22, 3, 2, 4, *L, d, fin, fout], tmp_path)
+        _run(driver, ["deriv", *shape, *nseg, *L, d, fin, fout], tmp_path)
         out = np.fromfile(fout).reshape(2, *f.shape)
         assert _rel(out[0], oracle.d1(f, d, L)) <= 1e-12
         assert _rel(out[1], oracle.d2(f, d, L)) <= 1e-12
