@@ -305,10 +305,7 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     const size_t o_row = off;  off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_j0 = off;   off = align256(off + sizeof(int) * (ncl + 1));
     const size_t o_len = off;  off = align256(off + sizeof(int) * (ncl + 1));
-    const size_t o_coef = off; off = align256(off + sizeof(double) * ((size_t)ncl * kTaps + 1));
-    const size_t o_c32 = off;  off = align256(off + sizeof(float) * ((size_t)ncl * kTaps + 1));
     const size_t o_coefA = off; off = align256(off + sizeof(double) * ((size_t)ncl * 128 + 2));
-    const size_t o_kind = off; off = align256(off + (size_t)n);
     const size_t o_den = off;  off = align256(off + sizeof(double) * (n + 1));
     const size_t o_cp = off;   off = align256(off + sizeof(double) * (n + 1));
     const size_t o_d32 = off;  off = align256(off + sizeof(float) * (n + 1));
@@ -331,9 +328,6 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     cpy(o_row, P.cl_row.data(), sizeof(int) * ncl);
     cpy(o_j0, P.cl_j0.data(), sizeof(int) * ncl);
     cpy(o_len, P.cl_len.data(), sizeof(int) * ncl);
-    cpy(o_coef, P.cl_coef.data(), sizeof(double) * (size_t)ncl * kTaps);
-    std::vector<float> c32(P.cl_coef.begin(), P.cl_coef.end());
-    cpy(o_c32, c32.data(), sizeof(float) * c32.size());
     // closure taps on the four aligned 32-row blocks that hold the tap window
     // (a window of 97 rows starting anywhere in a block ends in the fourth)
     std::vector<double> coefA((size_t)ncl * 128, 0.0);
@@ -345,7 +339,6 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
         }
     }
     cpy(o_coefA, coefA.data(), sizeof(double) * coefA.size());
-    cpy(o_kind, P.row_kind.data(), (size_t)n);
     cpy(o_den, P.rden.data(), sizeof(double) * (n + 1));
     cpy(o_cp, P.cp.data(), sizeof(double) * (n + 1));
     std::vector<float> d32(P.rden.begin(), P.rden.end()), cp32(P.cp.begin(), P.cp.end());
@@ -380,9 +373,6 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     d.cl_row = reinterpret_cast<const int *>(b + o_row);
     d.cl_j0 = reinterpret_cast<const int *>(b + o_j0);
     d.cl_len = reinterpret_cast<const int *>(b + o_len);
-    d.cl_coef = reinterpret_cast<const double *>(b + o_coef);
-    d.cl_coef32 = reinterpret_cast<const float *>(b + o_c32);
-    d.row_kind = reinterpret_cast<const uint8_t *>(b + o_kind);
     d.rden = reinterpret_cast<const double *>(b + o_den);
     d.cp = reinterpret_cast<const double *>(b + o_cp);
     d.rden32 = reinterpret_cast<const float *>(b + o_d32);

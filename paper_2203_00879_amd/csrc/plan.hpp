@@ -24,9 +24,6 @@ struct LinePlanDev {
     const int *cl_row;     // [ncl] row index e of each closure
     const int *cl_j0;      // [ncl] first tap column
     const int *cl_len;     // [ncl] number of taps (<= 97)
-    const double *cl_coef; // [ncl][97] coefficients C_{e,j} * h, taps j0 .. j0+len-1
-    const float *cl_coef32;// [ncl][97] the same rounded to FP32 (mixed precision)
-    const uint8_t *row_kind;  // [n]
     const double *rden;    // [n] reciprocal elimination pivots 1 / (1 - alpha c'_{k-1}), k = 1..
     const double *cp;      // [n] c'_k = alpha / den_k
     const float *rden32;   // FP32 copies
