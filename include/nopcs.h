@@ -276,10 +276,11 @@ enum {
     NOPCS_K_VISCOUS = 0,  /* viscous fluxes + gravity source (writes R)          */
     NOPCS_K_SWEEP_X = 1,  /* convective x sweep (R -= D_x E)                      */
     NOPCS_K_SWEEP_Y = 2,  /* convective y sweep (R -= D_y F)                      */
-    NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G)                      */
+    NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G; in FP64 rk_step with  */
+                          /* the z line march it also makes the RK4 update)       */
     NOPCS_K_WALL = 4,     /* wall conditions (one launch per face pair)          */
     NOPCS_K_DERIV = 5,    /* standalone derivative                                */
-    NOPCS_K_RK = 6,       /* RK4 register update of one stage                     */
+    NOPCS_K_RK = 6,       /* RK4 register update of one stage (when not fused)    */
     NOPCS_K_CLOSURE_Y = 7,/* closure rows of the y sweep (line-march pass)         */
     NOPCS_K_CLOSURE_Z = 8,/* closure rows of the z sweep (line-march pass)         */
     NOPCS_K_COUNT = 9
