@@ -189,7 +189,7 @@ def main():
     pstage = N3 * 4 * args.steps
     value = pstage / sec / 1e6
     pr = args.precision
-    fused = pr == "fp64" and "rk_update" not in per
+    fused = "rk_update" not in per
     bpp = lambda k: kernel_bytes_per_point(k, pr, fused)   # noqa: E731
     dom = max((k for k in per if k in KERNEL_SOURCES and bpp(k) > 0), key=lambda k: per[k][0])
     tot_ms, cnt = per[dom]

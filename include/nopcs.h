@@ -92,12 +92,14 @@ int nopcs_release_plans(void);
 /* Workspace (device bytes) needed by nse_rhs and rk_step for this grid and
  * precision: three 5-field registers (the RK4 accumulator, the stage state and
  * the right-hand side, FP64, the last FP32 under NOPCS_MIXED; nse_rhs leaves
- * them untouched; in FP64, when the z sweep carries the RK4 update, the stage
- * state is written over the right-hand side and those two swap roles every
- * stage; their contents between calls are unspecified) followed by the
- * closure array of the sweeps along y and z (5 components x closure rows x
- * lines, the larger direction).  Depends on the piece length in force
- * (nopcs_set_piece_length).  Host only; returns 0 on invalid input. */
+ * them untouched), then the closure array of the sweeps along y and z (5
+ * components x closure rows x lines, the larger direction), and under
+ * NOPCS_MIXED a second FP64 stage register.  When the z sweep carries the RK4
+ * update it writes the next stage state over the right-hand side (FP64) or
+ * into the other stage register (mixed), so registers swap roles between
+ * stages; their contents between calls are unspecified.  Depends on the piece
+ * length in force (nopcs_set_piece_length).  Host only; returns 0 on invalid
+ * input. */
 size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision);
 
 /*
@@ -276,8 +278,8 @@ enum {
     NOPCS_K_VISCOUS = 0,  /* viscous fluxes + gravity source (writes R)          */
     NOPCS_K_SWEEP_X = 1,  /* convective x sweep (R -= D_x E)                      */
     NOPCS_K_SWEEP_Y = 2,  /* convective y sweep (R -= D_y F)                      */
-    NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G; in FP64 rk_step with  */
-                          /* the z line march it also makes the RK4 update)       */
+    NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G; in rk_step with the  */
+                          /* z line march it also makes the RK4 update)           */
     NOPCS_K_WALL = 4,     /* wall conditions (one launch per face pair)          */
     NOPCS_K_DERIV = 5,    /* standalone derivative                                */
     NOPCS_K_RK = 6,       /* RK4 register update of one stage (when not fused)    */

@@ -208,22 +208,28 @@ static int launch_step(const nse_params &params, const nopcs_grid *grid, int pre
     a.dt = dt;
     a.half_dt = 0.5 * dt;
     a.sixth_dt = dt / 6.0;
-    // FP64 with the z line march: the stage update rides on the z sweep
-    // (RkFuse), which writes the next stage state over R; the two FP64 state
-    // buffers of the workspace (Qs, R) then swap roles every stage.
-    const bool fuse = !mixed && march_usable(2, pl[2]);
-    double *B[2] = {Qs, static_cast<double *>(R)};
+    // With the z line march the stage update rides on the z sweep (RkFuse),
+    // which must not write the state it reads.  FP64: the next stage state goes
+    // over R, and the two FP64 registers (Qs, R) swap roles every stage.  Mixed
+    // precision (FP32 R): the next stage state alternates between Qs and a
+    // second FP64 stage register.
+    const bool fuse = march_usable(2, pl[2]);
+    double *Qs2 = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * reg + closure_bytes(grid));
+    double *B[2] = {Qs, mixed ? Qs2 : static_cast<double *>(R)};
     for (int stage = 0; stage < 4; ++stage) {
-        void *Rs = fuse ? static_cast<void *>(B[(stage + 1) & 1]) : R;
-        const double *Qin = stage == 0 ? Q : (fuse ? B[stage & 1] : Qs);
+        // FP64: R in B[(s + 1) % 2], input B[s % 2]; mixed: R fixed, input
+        // B[(s + 1) % 2], output B[s % 2]
+        void *Rs = fuse && !mixed ? static_cast<void *>(B[(stage + 1) & 1]) : R;
+        double *Sout = !fuse ? Qs : mixed ? B[stage & 1] : B[(stage + 1) & 1];
+        const double *Qin = stage == 0 ? Q : !fuse ? Qs : mixed ? B[(stage + 1) & 1] : B[stage & 1];
         a.Qin = Qin;
         a.R = Rs;
         a.stage = stage;
         NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st); }));
         if (fuse) {
-            const RkFuse F{K, Q, stage, dt, 0.5 * dt, dt / 6.0};
+            const RkFuse F{K, Q, Sout, stage, dt, 0.5 * dt, dt / 6.0};
             for (int d = 0; d < 3; ++d) {
-                const int rc = conv_sweep(d, a, grid, pl[d], clo, false, st, d == 2 ? &F : nullptr);
+                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st, d == 2 ? &F : nullptr);
                 if (rc != NOPCS_OK) return rc;
             }
         } else {
@@ -233,7 +239,7 @@ static int launch_step(const nse_params &params, const nopcs_grid *grid, int pre
             }
             NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
         }
-        double *Qout = stage == 3 ? Q : fuse ? static_cast<double *>(Rs) : Qs;
+        double *Qout = stage == 3 ? Q : Sout;
         for (int d = 0; d < 3; ++d)
             NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
     }
@@ -335,7 +341,9 @@ int nopcs_release_plans(void) {
 
 size_t nopcs_workspace_bytes(const nopcs_grid *grid, int precision) {
     if (!check_grid(grid) || (precision != NOPCS_FP64 && precision != NOPCS_MIXED)) return 0;
-    return 3 * state_bytes(grid) + closure_bytes(grid);
+    // mixed precision: a second FP64 stage register after the closure array
+    // (the z sweep that carries the RK4 update writes the next stage state there)
+    return (precision == NOPCS_MIXED ? 4 : 3) * state_bytes(grid) + closure_bytes(grid);
 }
 
 int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int32_t *nrun, int32_t *runs,

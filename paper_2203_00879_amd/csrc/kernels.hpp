@@ -20,13 +20,15 @@ struct NseSweepArgs {
     NdConst c;
 };
 
-// RK4 stage update fused into the last convective sweep (FP64): the sweep's
-// k = R - f' goes straight into the stage registers instead of R; the new stage
-// state is written over R itself (each point's R is read and then written by
-// one thread only).
+// RK4 stage update fused into the last convective sweep: the sweep's
+// k = R - f' goes straight into the stage registers instead of R.  The next
+// stage state goes to S, which must not be the sweep's input state: in FP64 it
+// is R itself (each point's R is read and then written by one thread only), in
+// mixed precision (FP32 R) a second FP64 stage buffer.
 struct RkFuse {
     double *K;          // k1 + 2 k2 + 2 k3 accumulator
     double *Qn;         // state at the start of the step (in/out at the last stage)
+    double *S;          // next stage state (stages 0-2; in FP64 it must be R)
     int stage;          // 0..3
     double dt, half_dt, sixth_dt;
 };

@@ -202,12 +202,13 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
 // ---------------------------------------------------------------------------
 // TR: storage type of R; TC: arithmetic of the elimination (B f is formed in
 // FP64 from the FP64 window and rounded once; known rows stay FP64).
-// RKS >= 0 (FP64 only): RK4 stage RKS fused into the epilogue, see RkFuse.
+// RKS >= 0: RK4 stage RKS fused into the epilogue, see RkFuse (R and the
+// elimination both FP64, or both FP32).
 template <int DIR, bool FULL, class TR, class TC, int RKS>
 __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, TR *R,
                                                             const double *__restrict__ clo, MarchGeom g,
                                                             LinePlanDev pl, NdConst c, RkFuse F) {
-    static_assert(RKS < 0 || (sizeof(TR) == 8 && sizeof(TC) == 8), "the fused RK update is FP64 only");
+    static_assert(RKS < 0 || sizeof(TR) == sizeof(TC), "the fused RK update: FP64 or mixed precision");
     __shared__ double L[2][CHM][NCOMP][MW];
     __shared__ double KV[2 * kGroupRuns][NCOMP][MW];   // closure values bounding the group's runs
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -273,22 +274,29 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
 
     // Fused RK4 stage (RKS >= 0): back substitution in place, then per row
     // k = R - f' and the register update of RKS (operation for operation that
-    // of k_rk_update); stage 0-2 write K and the next stage state (over R),
-    // stage 3 writes Qn.  Rows are fetched RB steps ahead at clamped rows;
-    // steps past the run store nothing.
+    // of k_rk_update, k rounded from R's type to FP64 as there); stage 0-2 write
+    // K and the next stage state S, stage 3 writes Qn.  Rows are fetched RB
+    // steps ahead at clamped rows; steps past the run store nothing.
     double *const Kc = RKS >= 0 ? F.K + comp * g.N3 + (ok ? base : 0) : nullptr;
     double *const Nc = RKS >= 0 ? F.Qn + comp * g.N3 + (ok ? base : 0) : nullptr;
+    // FP64: the next stage state goes over R (same element offsets as Rc);
+    // mixed precision: into F.S
+    double *const Sm = RKS < 0 || RKS == 3 || sizeof(TR) == 8 ? nullptr : F.S + comp * g.N3 + (ok ? base : 0);
+    auto store_s = [&](long long off, double v) {
+        if constexpr (sizeof(TR) == 8) reinterpret_cast<double *>(Rc)[off] = v;
+        else Sm[off] = v;
+    };
     auto rk_point = [&](long long off, double rv, double kk, double qn, double x) {
-        const double kv = rv - x;
+        const double kv = double(TR(TR(rv) - TR(x)));   // R - f' in R's type, as the unfused march
         if constexpr (RKS == 0) {
             Kc[off] = kv;
-            reinterpret_cast<double *>(Rc)[off] = qn + F.half_dt * kv;
+            store_s(off, qn + F.half_dt * kv);
         } else if constexpr (RKS == 1) {
             Kc[off] = kk + 2.0 * kv;
-            reinterpret_cast<double *>(Rc)[off] = qn + F.half_dt * kv;
+            store_s(off, qn + F.half_dt * kv);
         } else if constexpr (RKS == 2) {
             Kc[off] = kk + 2.0 * kv;
-            reinterpret_cast<double *>(Rc)[off] = qn + F.dt * kv;
+            store_s(off, qn + F.dt * kv);
         } else {
             Nc[off] = qn + F.sixth_dt * (kk + kv);
         }
@@ -472,15 +480,15 @@ static hipError_t launch_runs_t(int dir, const double *Q, TR *R, const double *c
     return hipGetLastError();
 }
 
-// z sweep with the RK4 stage update fused (FP64)
-template <int S>
-static hipError_t launch_runs_rk(const double *Q, double *R, const double *clo, const MarchGeom &g,
+// z sweep with the RK4 stage update fused (T: R and the elimination, FP64 or FP32)
+template <int S, class T>
+static hipError_t launch_runs_rk(const double *Q, T *R, const double *clo, const MarchGeom &g,
                                  const LinePlanDev &pl, const NdConst &c, const RkFuse &F, hipStream_t st) {
     const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
     if (g.nx % MW == 0)
-        hipLaunchKernelGGL((k_march_sweep<2, true, double, double, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+        hipLaunchKernelGGL((k_march_sweep<2, true, T, T, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
     else
-        hipLaunchKernelGGL((k_march_sweep<2, false, double, double, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
+        hipLaunchKernelGGL((k_march_sweep<2, false, T, T, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
     return hipGetLastError();
 }
 
@@ -488,13 +496,23 @@ hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c
                              const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk) {
     const MarchGeom g = march_geom(n, dir);
     if (rk) {
-        if (dir != 2 || r32 || c32) return hipErrorInvalidValue;
+        if (dir != 2 || r32 != c32) return hipErrorInvalidValue;
+        if (r32) {
+            float *Rf = static_cast<float *>(R);
+            switch (rk->stage) {
+                case 0: return launch_runs_rk<0, float>(Q, Rf, clo, g, pl, c, *rk, st);
+                case 1: return launch_runs_rk<1, float>(Q, Rf, clo, g, pl, c, *rk, st);
+                case 2: return launch_runs_rk<2, float>(Q, Rf, clo, g, pl, c, *rk, st);
+                case 3: return launch_runs_rk<3, float>(Q, Rf, clo, g, pl, c, *rk, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
         double *Rd = static_cast<double *>(R);
         switch (rk->stage) {
-            case 0: return launch_runs_rk<0>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 1: return launch_runs_rk<1>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 2: return launch_runs_rk<2>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 3: return launch_runs_rk<3>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 0: return launch_runs_rk<0, double>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 1: return launch_runs_rk<1, double>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 2: return launch_runs_rk<2, double>(Q, Rd, clo, g, pl, c, *rk, st);
+            case 3: return launch_runs_rk<3, double>(Q, Rd, clo, g, pl, c, *rk, st);
             default: return hipErrorInvalidValue;
         }
     }

@@ -219,7 +219,7 @@ int main(int argc, char **argv) {
         std::vector<double> Qh = read_raw(argv[13], 5 * N);
         Buf Q(5 * N), R(5 * N);
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
-        const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
+        const size_t wsb = nopcs_workspace_bytes(&g, prec);
         Buf ws((wsb + 7) / 8);
         rc = nse_rhs(&p, &g, prec, Q.p, R.p, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[14], R.p, 5 * N);
@@ -231,7 +231,7 @@ int main(int argc, char **argv) {
         std::vector<double> Qh = read_raw(argv[15], 5 * N);
         Buf Q(5 * N);
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
-        const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
+        const size_t wsb = nopcs_workspace_bytes(&g, prec);
         Buf ws((wsb + 7) / 8);
         rc = rk_step(&p, &g, prec, Q.p, dt, nsteps, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[16], Q.p, 5 * N);

@@ -74,8 +74,11 @@ def test_invalid_arguments_rejected():
 
 def test_workspace_includes_closure_array():
     """Three 5-field states plus, for y and z, 5 components x closure rows x lines
-    (the larger of the two), 256-byte aligned."""
+    (the larger of the two), 256-byte aligned; mixed precision adds a second FP64
+    stage register (the z sweep that carries the RK4 update writes the next stage
+    state there)."""
     g = nopcs.make_grid((16, 16, 16), nseg=(1, 2, 3))
     # y: 2 segments -> closure rows 7, 8; z: 3 segments of 6, 5, 5 -> rows 5, 6, 10, 11
     clo = max(5 * 2 * 16 * 16, 5 * 4 * 16 * 16) * 8
     assert nopcs.workspace_bytes(g) == 3 * 5 * 16 ** 3 * 8 + (clo + 255) // 256 * 256
+    assert nopcs.workspace_bytes(g, nopcs.MIXED) == 4 * 5 * 16 ** 3 * 8 + (clo + 255) // 256 * 256

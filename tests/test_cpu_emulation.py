@@ -96,11 +96,13 @@ def test_emulated_rk_step_matches_oracle(driver, tmp_path):
         assert _rel(G[c], O[c]) <= 1e-12
 
 
-def test_emulated_rk_line_march(driver, tmp_path):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_emulated_rk_line_march(driver, tmp_path, mixed):
     """One RK4 step of a box whose y and z lines are cut into pieces (line
-    marches; the stage update rides on the z march and the stage state is
-    written over R, so the two state buffers swap roles every stage), against
-    the oracle's RK4 with global line solves.  The state change over the run is
+    marches; the stage update rides on the z march: in FP64 the stage state is
+    written over R, so the two state buffers swap roles every stage; in mixed
+    precision it alternates between two FP64 stage buffers), against the
+    oracle's RK4 with global line solves.  The state change over the run is
     compared, relative to its largest value per field."""
     p = dict(inputs.AIR)
     shape = (8, 20, 44)
@@ -108,10 +110,10 @@ def test_emulated_rk_line_march(driver, tmp_path):
     qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
     Q.tofile(qin)
     dt, steps = 5e-5, 1
-    _run(driver, ["rk", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, dt, steps, qin, qout], tmp_path, piece=16)
+    _run(driver, ["rk", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, dt, steps, qin, qout], tmp_path, piece=16, mixed=mixed)
     G = np.fromfile(qout).reshape(Q.shape)
     O = oracle.rk4(p, Q, dt, steps)
-    tol = 1e-11
+    tol = 1e-6 if mixed else 1e-11
     for c in range(5):
         d = np.max(np.abs(O[c] - Q[c]))
         assert np.max(np.abs(G[c] - O[c])) <= tol * d, (c, np.max(np.abs(G[c] - O[c])) / d)
