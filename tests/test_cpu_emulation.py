@@ -30,11 +30,18 @@ def driver():
     deps = _sources() + [os.path.join(EMU, "driver.cpp"), os.path.join(EMU, "include", "hip", "hip_runtime.h")]
     deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
     if not os.path.exists(BIN) or os.path.getmtime(BIN) < max(os.path.getmtime(d) for d in deps):
-        cmd = ["g++", "-std=c++20", "-O1", "-g", "-DNOPCS_CPU_EMUL", "-fsanitize=address,undefined",
-               "-fno-omit-frame-pointer", "-fno-strict-aliasing", "-ffp-contract=off", "-pthread", "-I", os.path.join(EMU, "include"),
-               "-x", "c++"] + _sources() + [os.path.join(EMU, "driver.cpp"), "-o", BIN + ".tmp"]
-        subprocess.check_call(cmd)
+        flags = ["-std=c++20", "-O1", "-g", "-DNOPCS_CPU_EMUL", "-fsanitize=address,undefined",
+                 "-fno-omit-frame-pointer", "-fno-strict-aliasing", "-ffp-contract=off", "-pthread",
+                 "-I", os.path.join(EMU, "include")]
+        # one compiler per translation unit, in parallel, then one link
+        srcs = _sources() + [os.path.join(EMU, "driver.cpp")]
+        objs = [BIN + ".%d.o" % k for k in range(len(srcs))]
+        procs = [subprocess.Popen(["g++"] + flags + ["-x", "c++", "-c", src, "-o", obj]) for src, obj in zip(srcs, objs)]
+        assert all(p.wait() == 0 for p in procs), "CPU build of the kernels failed"
+        subprocess.check_call(["g++"] + flags + objs + ["-o", BIN + ".tmp"])
         os.replace(BIN + ".tmp", BIN)
+        for obj in objs:
+            os.remove(obj)
     return BIN
 
 
