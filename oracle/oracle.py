@@ -20,7 +20,7 @@ _lib = None
 __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
-    "scales", "segment_starts", "num_threads",
+    "scales", "segment_starts", "num_threads", "vorticity_budget",
 ]
 
 
@@ -234,3 +234,35 @@ def scales(params):
     p = OraParams.from_dict(params)
     lib().ora_scales(ctypes.byref(p), _ptr(out))
     return tuple(out)
+
+
+def vorticity_budget(params, Q, length=1.0):
+    """Vorticity and the three source terms on the right of the inviscid
+    vorticity transport equation (Eq. eqn12_1, the terms the paper's results
+    section plots): omega = curl V; stretching (omega . grad) V; dilatation
+    -omega (div V); baroclinic (grad rho x grad p) / rho^2.  Every derivative
+    is the compact first derivative ``d1`` (global line solves); V = (rho u,
+    rho v, rho w) / rho and p' = (gamma - 1)(E' - rho |V|^2 / 2) (ge12, ge13;
+    the constant p - p' drops out of grad p).  Returns [12, nz, ny, nx]: omega,
+    stretching, dilatation, baroclinic (x, y, z each); sums run over x, y, z.
+    """
+    Q = _f64(Q)
+    rho = Q[0]
+    V = [Q[1] / rho, Q[2] / rho, Q[3] / rho]
+    ke = 0.5 * (Q[1] * V[0] + Q[2] * V[1] + Q[3] * V[2])
+    pp = (params["gamma"] - 1.0) * (Q[4] - ke)
+    g = [[d1(V[i], j, length) for j in range(3)] for i in range(3)]      # g[i][j] = d V_i / d x_j
+    grho = [d1(rho, j, length) for j in range(3)]
+    gp = [d1(pp, j, length) for j in range(3)]
+    om = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+    div = (g[0][0] + g[1][1]) + g[2][2]
+    out = np.empty((12,) + rho.shape)
+    for i in range(3):
+        out[i] = om[i]
+        out[3 + i] = (om[0] * g[i][0] + om[1] * g[i][1]) + om[2] * g[i][2]
+        out[6 + i] = -(om[i] * div)
+    r2 = rho * rho
+    out[9] = (grho[1] * gp[2] - grho[2] * gp[1]) / r2
+    out[10] = (grho[2] * gp[0] - grho[0] * gp[2]) / r2
+    out[11] = (grho[0] * gp[1] - grho[1] * gp[0]) / r2
+    return out

@@ -455,3 +455,92 @@ def test_mass_drift_small_and_shrinking():
         drift.append(abs(m1 - m0) / m0)
     assert drift[1] < 1e-6
     assert drift[1] < drift[0]
+
+
+# ---------------------------------------------------------------------------
+# Vorticity budget (Eq. eqn12_1)
+# ---------------------------------------------------------------------------
+def _linear_flow(shape, M, v0, grho, rho0, gp, p0, gamma, length=1.0):
+    """Conserved state whose V = M x + v0, rho = rho0 + grho.x, p' = p0 + gp.x
+    (x, y, z node coordinates on [0, length]); array axes are (z, y, x)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(*(np.linspace(0.0, length, n) for n in (nz, ny, nx)), indexing="ij")
+    X = (x, y, z)
+    V = [v0[i] + sum(M[i][j] * X[j] for j in range(3)) for i in range(3)]
+    rho = rho0 + sum(grho[j] * X[j] for j in range(3))
+    p = p0 + sum(gp[j] * X[j] for j in range(3))
+    Q = np.empty((5,) + shape)
+    Q[0] = rho
+    for i in range(3):
+        Q[1 + i] = rho * V[i]
+    Q[4] = p / (gamma - 1.0) + 0.5 * rho * (V[0] ** 2 + V[1] ** 2 + V[2] ** 2)
+    return Q, rho
+
+
+def test_vorticity_budget_linear_flow_closed_form():
+    """For V = M x (M[i, j] = dV_i/dx_j) every compact derivative is exact, so
+    omega_i = eps_ijk M[k, j], stretching = M omega, dilatation = -omega tr M and
+    the baroclinic term is (grad rho x grad p) / rho^2 with constant gradients.
+    An asymmetric M with a trace, and gradients of rho and p along all three
+    axes, make a transposed gradient, a wrong sign or a swapped component fail."""
+    rng = np.random.default_rng(7)
+    M = rng.uniform(-0.3, 0.3, (3, 3))
+    v0 = rng.uniform(-0.1, 0.1, 3)
+    grho = rng.uniform(-0.2, 0.2, 3)
+    gp = rng.uniform(-0.5, 0.5, 3)
+    p = _params()
+    shape = (9, 12, 14)
+    Q, rho = _linear_flow(shape, M, v0, grho, 1.3, gp, 0.7, p["gamma"])
+    out = oracle.vorticity_budget(p, Q)
+    om = np.array([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]])
+    stretch = M @ om
+    dil = -om * np.trace(M)
+    baro = np.cross(grho, gp)
+    for i in range(3):
+        assert np.max(np.abs(out[i] - om[i])) < 1e-12
+        assert np.max(np.abs(out[3 + i] - stretch[i])) < 1e-12
+        assert np.max(np.abs(out[6 + i] - dil[i])) < 1e-12
+        assert np.max(np.abs(out[9 + i] * rho * rho - baro[i])) < 1e-11
+    # solid-body rotation about z at rate W: omega = (0, 0, 2W), no sources
+    W = 0.25
+    Mr = np.array([[0.0, -W, 0.0], [W, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    Q, _ = _linear_flow(shape, Mr, np.zeros(3), np.zeros(3), 1.0, np.zeros(3), 0.5, p["gamma"])
+    out = oracle.vorticity_budget(p, Q)
+    assert np.max(np.abs(out[2] - 2 * W)) < 1e-12
+    assert np.max(np.abs(out[[0, 1]])) < 1e-12 and np.max(np.abs(out[3:])) < 1e-12
+
+
+def test_vorticity_budget_domain_length_scales():
+    """On a box of length Lx, Ly, Lz the same node values give gradients divided
+    by the lengths: omega of V = (-W y, W x, 0) with y, x in node units."""
+    p = _params()
+    shape = (8, 10, 12)
+    W = 0.3
+    Mr = np.array([[0.0, -W, 0.0], [W, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    Q, _ = _linear_flow(shape, Mr, np.zeros(3), np.zeros(3), 1.0, np.zeros(3), 0.5, p["gamma"])
+    L = np.array([2.0, 0.5, 1.0])   # x, y, z
+    out = oracle.vorticity_budget(p, Q, length=L)
+    # dv/dx = W / Lx, du/dy = -W / Ly
+    assert np.max(np.abs(out[2] - (W / L[0] + W / L[1]))) < 1e-12
+
+
+def test_vorticity_of_a_discrete_gradient_vanishes():
+    """Compact derivatives along different axes commute on the tensor grid, so
+    V = grad_h phi (built with d1) has zero discrete curl for any smooth phi."""
+    p = _params()
+    shape = (10, 11, 13)
+    rng = np.random.default_rng(3)
+    z, y, x = np.meshgrid(*(np.linspace(0.0, 1.0, n) for n in shape), indexing="ij")
+    phi = np.sin(2.1 * x + 0.4) * np.cos(1.7 * y) * np.exp(0.6 * z) + 0.3 * x * y * z
+    rho = 1.0 + 0.1 * rng.uniform(size=shape)
+    Q = np.empty((5,) + shape)
+    Q[0] = rho
+    for i in range(3):
+        Q[1 + i] = rho * oracle.d1(phi, i)
+    Q[4] = 2.5 + 0.1 * rng.uniform(size=shape)
+    out = oracle.vorticity_budget(p, Q)
+    scale = max(np.max(np.abs(oracle.d1(oracle.d1(phi, 0), 1))), 1.0)
+    assert np.max(np.abs(out[0:3])) < 1e-12 * scale * 10
+    assert np.max(np.abs(out[3:9])) < 1e-11 * scale * scale * 10
+    # the baroclinic term is not zero here (rho and p' independent)
+    assert np.max(np.abs(out[9:12])) > 1e-3
