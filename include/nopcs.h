@@ -143,6 +143,36 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
                      void *hip_stream);
 
 /*
+ * nopcs_vorticity_workspace_bytes -- bytes of device workspace that
+ * nopcs_vorticity_budget needs for this grid (19 fields, each rounded up to
+ * 32 doubles); 0 (with an error message) for an invalid grid.
+ */
+size_t nopcs_vorticity_workspace_bytes(const nopcs_grid *grid);
+
+/*
+ * nopcs_vorticity_budget -- vorticity and the three source terms on the right of
+ * the inviscid vorticity transport equation (Eq. eqn12_1), the terms the
+ * paper's analysis of RTI onset compares (Section 5): vortex stretching
+ * (omega . grad) V, dilatation -omega (div V) and the baroclinic term
+ * (grad rho x grad p) / rho^2.
+ *
+ * V = (rho u, rho v, rho w) / rho and p' = (gamma - 1)(E' - rho |V|^2 / 2)
+ * (ge12, ge13; the reference pressure is constant and drops out of grad p).
+ * Every derivative is the compact first derivative of nopcs_derivative along
+ * x, y or z (with grid->nseg segments), so all 15 gradients share its accuracy.
+ *
+ * params: only gamma is used (all fields are still checked).  Q: device state,
+ * 5 fields of n0*n1*n2 doubles (read only).  out: device output, 12 fields of
+ * n0*n1*n2 doubles: omega_x, omega_y, omega_z, stretching (x, y, z),
+ * dilatation (x, y, z), baroclinic (x, y, z); must not overlap Q or ws.  ws:
+ * device workspace of at least nopcs_vorticity_workspace_bytes(grid) bytes,
+ * 256-byte aligned (NOPCS_EINVAL otherwise); its contents on return are
+ * unspecified.  Work is queued on hip_stream; the call does not wait for it.
+ */
+int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, const double *Q, double *out, void *ws,
+                           size_t ws_bytes, void *hip_stream);
+
+/*
  * nse_rhs -- right-hand side of the non-dimensional compressible NSE (ge17):
  *   R = dEv/dx + dFv/dy + dGv/dz + S - (dE/dx + dF/dy + dG/dz)
  * with convective fluxes ge3-ge5 differentiated by the NOHAP compact scheme
@@ -281,11 +311,13 @@ enum {
     NOPCS_K_SWEEP_Z = 3,  /* convective z sweep (R -= D_z G; in rk_step with the  */
                           /* z line march it also makes the RK4 update)           */
     NOPCS_K_WALL = 4,     /* wall conditions (one launch per face pair)          */
-    NOPCS_K_DERIV = 5,    /* standalone derivative                                */
+    NOPCS_K_DERIV = 5,    /* standalone derivative; the vorticity budget's 15     */
+                          /* first derivatives                                    */
     NOPCS_K_RK = 6,       /* RK4 register update of one stage (when not fused)    */
     NOPCS_K_CLOSURE_Y = 7,/* closure rows of the y sweep (line-march pass)         */
     NOPCS_K_CLOSURE_Z = 8,/* closure rows of the z sweep (line-march pass)         */
-    NOPCS_K_COUNT = 9
+    NOPCS_K_VORT = 9,     /* point-wise parts of the vorticity budget             */
+    NOPCS_K_COUNT = 10
 };
 
 /* on != 0: from now on every kernel launched by this library is bracketed by a

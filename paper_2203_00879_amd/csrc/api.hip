@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "vort.hpp"
 
 namespace nopcs {
 
@@ -385,6 +386,44 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
     const SweepGeom g = sweep_geom(grid->n, dir);
     NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, (hipStream_t)hip_stream,
                           [&] { return launch_deriv(dir, f, d1, d2, g, pl[dir], (hipStream_t)hip_stream); }));
+    return NOPCS_OK;
+}
+
+// Fields of the vorticity workspace: u, v, w, p' and 15 gradients, each padded
+// to a multiple of 32 doubles so that every field starts 256-byte aligned.
+static long long vort_stride(const nopcs_grid *g) { return ((long long)field_elems(g) + 31) / 32 * 32; }
+
+size_t nopcs_vorticity_workspace_bytes(const nopcs_grid *grid) {
+    if (!check_grid(grid)) return 0;
+    return (size_t)19 * (size_t)vort_stride(grid) * sizeof(double);
+}
+
+int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, const double *Q, double *out, void *ws,
+                           size_t ws_bytes, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (!Q || !out) { set_error("Q and out must be non-NULL"); return NOPCS_EINVAL; }
+    const size_t need = nopcs_vorticity_workspace_bytes(grid);
+    if (!ws || ws_bytes < need) {
+        set_error("vorticity workspace too small: need " + std::to_string(need) + " bytes");
+        return NOPCS_EINVAL;
+    }
+    if (((uintptr_t)ws & 255) != 0) { set_error("workspace must be 256-byte aligned"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long long N = (long long)field_elems(grid), S = vort_stride(grid);
+    double *P = static_cast<double *>(ws), *G = P + 4 * S;
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_prims(Q, N, S, params->gamma - 1.0, P, st); }));
+    // gradients of u, v, w (from P), rho (field 0 of Q) and p' (P field 3)
+    const double *src[5] = {P, P + S, P + 2 * S, Q, P + 3 * S};
+    for (int a = 0; a < 5; ++a)
+        for (int d = 0; d < 3; ++d) {
+            const SweepGeom g = sweep_geom(grid->n, d);
+            double *dst = G + (3 * a + d) * S;
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src[a], dst, nullptr, g, pl[d], st); }));
+        }
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_combine(Q, G, N, S, out, st); }));
     return NOPCS_OK;
 }
 

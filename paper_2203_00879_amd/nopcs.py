@@ -85,6 +85,10 @@ def lib():
         L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
                                      ctypes.POINTER(ctypes.c_int32 * 3)]
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
+        L.nopcs_vorticity_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
+        L.nopcs_vorticity_budget.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, ctypes.c_size_t,
+                                             _V]
         if hasattr(L, "solver_create"):
             L.solver_create.argtypes = [ctypes.POINTER(SolverConfig), ctypes.POINTER(_V)]
             L.solver_submit.argtypes = [_V, ctypes.POINTER(SolveRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -145,6 +149,24 @@ def nopcs_derivative(grid, direction, f, d1=None, d2=None, precision=FP64, strea
     """D1 and/or D2 of a device field f (float64 tensor of n0*n1*n2 elements)."""
     _check(lib().nopcs_derivative(ctypes.byref(grid), int(direction), int(precision), _ptr(f), _ptr(d1), _ptr(d2),
                                   _stream(stream)))
+
+
+def vorticity_workspace_bytes(grid):
+    return lib().nopcs_vorticity_workspace_bytes(ctypes.byref(grid))
+
+
+def vorticity_budget(params, grid, Q, out, ws=None, stream=None):
+    """out (12 fields) = omega, stretching, dilatation and baroclinic terms of
+    Eq. eqn12_1 at Q.  ws: device workspace of vorticity_workspace_bytes(grid)
+    bytes; allocated here when not given."""
+    if ws is None:
+        import torch
+        nb = vorticity_workspace_bytes(grid)
+        if nb == 0:
+            raise NopcsError(NOPCS_EINVAL, last_error())
+        ws = torch.empty(nb, dtype=torch.uint8, device=Q.device)
+    _check(lib().nopcs_vorticity_budget(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(out), _ptr(ws),
+                                        ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):

@@ -235,6 +235,14 @@ int main(int argc, char **argv) {
         Buf ws((wsb + 7) / 8);
         rc = rk_step(&p, &g, prec, Q.p, dt, nsteps, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[16], Q.p, 5 * N);
+    } else if (mode == "vort") {
+        std::vector<double> Qh = read_raw(argv[11], 5 * N);
+        Buf Q(5 * N), out(12 * N);
+        std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
+        const size_t wsb = nopcs_vorticity_workspace_bytes(&g);
+        Buf ws((wsb + 7) / 8);
+        rc = nopcs_vorticity_budget(&p, &g, Q.p, out.p, ws.p, wsb, nullptr);
+        if (rc == 0) write_raw(argv[12], out.p, 12 * N);
     } else {
         return 2;
     }

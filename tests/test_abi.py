@@ -82,3 +82,26 @@ def test_workspace_includes_closure_array():
     clo = max(5 * 2 * 16 * 16, 5 * 4 * 16 * 16) * 8
     assert nopcs.workspace_bytes(g) == 3 * 5 * 16 ** 3 * 8 + (clo + 255) // 256 * 256
     assert nopcs.workspace_bytes(g, nopcs.MIXED) == 4 * 5 * 16 ** 3 * 8 + (clo + 255) // 256 * 256
+
+
+def test_vorticity_workspace_and_argument_checks():
+    """19 fields padded to 32 doubles; NULL arrays, a short or misaligned
+    workspace and bad parameters are rejected before any device work."""
+    from paper_2203_00879_amd import inputs
+    lib = nopcs.lib()
+    g = nopcs.make_grid((9, 10, 11))
+    S = (9 * 10 * 11 + 31) // 32 * 32
+    ws = nopcs.vorticity_workspace_bytes(g)
+    assert ws == 19 * S * 8
+    assert nopcs.vorticity_workspace_bytes(nopcs.make_grid(4)) == 0
+    p = nopcs.make_params(inputs.AIR)
+    V = ctypes.c_void_p
+    call = lib.nopcs_vorticity_budget
+    assert call(ctypes.byref(p), ctypes.byref(g), None, V(256), V(4096), ws, None) == -1
+    assert call(ctypes.byref(p), ctypes.byref(g), V(256), None, V(4096), ws, None) == -1
+    assert call(ctypes.byref(p), ctypes.byref(g), V(256), V(512), V(4096), ws - 8, None) == -1
+    assert b"workspace" in lib.nopcs_last_error()
+    assert call(ctypes.byref(p), ctypes.byref(g), V(256), V(512), V(4104), ws, None) == -1
+    assert b"aligned" in lib.nopcs_last_error()
+    pb = nopcs.make_params(dict(inputs.AIR, gamma=1.0))
+    assert call(ctypes.byref(pb), ctypes.byref(g), V(256), V(512), V(4096), ws, None) == -1

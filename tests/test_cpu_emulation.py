@@ -22,7 +22,8 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("api.hip", "sweep.hip", "march.hip", "visc.hip", "plan.cpp", "solver.cpp")]
+    names = ("api.hip", "sweep.hip", "march.hip", "visc.hip", "vort.hip", "plan.cpp", "solver.cpp")
+    return [os.path.join(CSRC, f) for f in names]
 
 
 @pytest.fixture(scope="module")
@@ -189,3 +190,19 @@ def test_emulated_rhs_mixed_precision(driver, tmp_path):
     print("mixed rhs rel errors", errs)
     assert max(errs) <= 1e-6
     assert max(errs) > 0.0     # the FP32 path really ran
+
+
+def test_emulated_vorticity_budget(driver, tmp_path):
+    """Vorticity budget of Eq. eqn12_1 on a ragged box with segmented lines and
+    unequal lengths, against the oracle's global line solves."""
+    p = dict(inputs.AIR)
+    shape = (18, 13, 16)   # x, y, z
+    Q = inputs.smooth_state(shape, seed=6)
+    L = (1.0, 0.8, 1.1)
+    qin, oout = tmp_path / "q.raw", tmp_path / "o.raw"
+    Q.tofile(qin)
+    _run(driver, ["vort", *shape, 3, 1, 2, *L, qin, oout], tmp_path)
+    G = np.fromfile(oout).reshape((12,) + Q.shape[1:])
+    O = oracle.vorticity_budget(p, Q, np.array(L))
+    for c in range(12):
+        assert _rel(G[c], O[c]) <= 1e-12, c
