@@ -20,7 +20,7 @@ _lib = None
 __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
-    "scales", "segment_starts", "num_threads", "vorticity_budget",
+    "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum",
 ]
 
 
@@ -266,3 +266,27 @@ def vorticity_budget(params, Q, length=1.0):
     out[10] = (grho[2] * gp[0] - grho[0] * gp[2]) / r2
     out[11] = (grho[0] * gp[1] - grho[1] * gp[0]) / r2
     return out
+
+
+def disturbance_pressure(params, Q, Q0):
+    """Disturbance pressure p - p_h (Section 4: the instantaneous pressure minus
+    the initial hydrostatic one): p' of Q minus p' of the initial state Q0, with
+    p' = (gamma - 1)(E' - rho |V|^2 / 2) (ge12, ge13), taken as
+    (gamma - 1)((E' - E'_0) - (k - k_0)) with k = (rho u u + rho v v + rho w w) / 2,
+    the same difference without forming the two large pressures first."""
+    Q = _f64(Q)
+    Q0 = _f64(Q0)
+
+    def ke(S):
+        r = S[0]
+        return 0.5 * ((S[1] * (S[1] / r) + S[2] * (S[2] / r)) + S[3] * (S[3] / r))
+
+    return (params["gamma"] - 1.0) * ((Q[4] - Q0[4]) - (ke(Q) - ke(Q0)))
+
+
+def line_spectrum(f):
+    """Amplitude spectrum of a line of n samples (the Fourier transform of the
+    disturbance pressure along y, Section 4): |sum_j f_j exp(-2 pi i j k / n)| / n
+    for k = 0 .. n // 2, by the library FFT."""
+    f = np.asarray(f, dtype=np.float64)
+    return np.abs(np.fft.rfft(f)) / f.size

@@ -544,3 +544,57 @@ def test_vorticity_of_a_discrete_gradient_vanishes():
     assert np.max(np.abs(out[3:9])) < 1e-11 * scale * scale * 10
     # the baroclinic term is not zero here (rho and p' independent)
     assert np.max(np.abs(out[9:12])) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Disturbance pressure, its line spectrum and the acoustic pulses (Section 4)
+# ---------------------------------------------------------------------------
+def test_disturbance_pressure_closed_form():
+    """Uniform states have p' = Rh (rho T - 1) whatever their velocity, so the
+    disturbance pressure between two of them is Rh (rho1 T1 - rho0 T0)."""
+    p = _params()
+    Rh = inputs.rh_of(p)
+    shape = (8, 9, 10)
+    Q0 = inputs.uniform_state(shape, T=1.0, rho=1.0, velocity=(0.0, 0.0, 0.0), params=p)
+    Q1 = inputs.uniform_state(shape, T=1.25, rho=0.9, velocity=(0.3, -0.2, 0.1), params=p)
+    dp = oracle.disturbance_pressure(p, Q1, Q0)
+    assert np.max(np.abs(dp - Rh * (0.9 * 1.25 - 1.0))) <= 1e-9 * Rh
+    assert np.all(oracle.disturbance_pressure(p, Q1, Q1) == 0.0)
+    # the same pressure carried by a moving state: zero disturbance up to rounding of E'
+    Qm = inputs.uniform_state(shape, T=1.0, rho=1.0, velocity=(0.5, 0.0, -0.4), params=p)
+    assert np.max(np.abs(oracle.disturbance_pressure(p, Qm, Q0))) <= 1e-10 * Rh
+
+
+def test_line_spectrum_closed_forms():
+    """A constant c gives amp[0] = |c|; A cos(2 pi m j / n + phi) gives A / 2 at
+    k = m (A at k = n/2 for even n) and zero elsewhere."""
+    for n in (7, 16, 33):
+        j = np.arange(n)
+        assert np.allclose(oracle.line_spectrum(np.full(n, -2.5)), np.r_[2.5, np.zeros(n // 2)], atol=1e-14)
+        for m in range(1, n // 2 + 1):
+            f = 1.7 * np.cos(2 * np.pi * m * j / n + 0.3)
+            want = np.zeros(n // 2 + 1)
+            want[m] = 1.7 / 2 if 2 * m != n else 1.7 * abs(np.cos(0.3))
+            assert np.allclose(oracle.line_spectrum(f), want, atol=1e-13)
+
+
+def test_pressure_pulses_travel_at_the_local_sound_speed():
+    """The pulses that the interface of the RTI box sends up and down travel at
+    a = sqrt(T)/M, 200.46 m/s in the 100 K air above and 347.21 m/s in the
+    300 K air below (Section 4).  A 9 x 192 x 9 box (the line x = z = L/2),
+    records every 5e-5 from t = 1.5e-4 to 6e-4, slopes within 4 %."""
+    from acoustics import pulse_speeds
+    p = _params()
+    ny, dt, every = 192, 2e-6, 25
+    Q0 = inputs.rti_state((9, ny, 9), T_upper=100.0, T_lower=300.0, noise_K=0.0, params=p)
+    Q = Q0.copy()
+    times, lines = [], []
+    for k in range(1, 13):
+        Q = oracle.rk4(p, Q, dt, every)
+        if k >= 3:
+            times.append(k * every * dt)
+            lines.append(oracle.disturbance_pressure(p, Q, Q0)[4, :, 4])
+    su, sl = pulse_speeds(times, lines, ny)
+    Us = oracle.scales(p)[0]
+    assert abs(su * Us / PC["c_100K"] - 1.0) < 0.04, su * Us
+    assert abs(sl * Us / PC["c_300K"] - 1.0) < 0.04, sl * Us
