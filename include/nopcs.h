@@ -173,6 +173,29 @@ int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, con
                            size_t ws_bytes, void *hip_stream);
 
 /*
+ * nopcs_disturbance_pressure -- the disturbance pressure of Section 4: the
+ * pressure of state Q minus that of a reference state Q0 (the initial,
+ * hydrostatic box), out = (gamma - 1)((E' - E'_0) - (K - K_0)) with
+ * K = (rho u u + rho v v + rho w w) / 2 (ge12, ge13), i.e. p(Q) - p(Q0) formed
+ * without the two large pressures.  Q, Q0: device states (5 fields of
+ * n0*n1*n2 doubles, read only); out: device, n0*n1*n2 doubles, must not overlap
+ * them.  params: only gamma is used.  Asynchronous on hip_stream.
+ */
+int nopcs_disturbance_pressure(const nse_params *params, const nopcs_grid *grid, const double *Q, const double *Q0,
+                               double *out, void *hip_stream);
+
+/*
+ * nopcs_line_spectrum -- amplitude spectrum of one line of samples, as the
+ * paper takes of the disturbance pressure along y (Section 4):
+ *   amp[k] = |sum_{j<n} f[j*stride] exp(-2 pi i j k / n)| / n,  k = 0 .. n/2,
+ * by a direct transform (one block per k; phases reduced exactly in integers).
+ * f: device, read at f[j*stride] for j < n (the caller guarantees those
+ * elements exist); amp: device, n/2 + 1 doubles.  2 <= n <= 16384 and
+ * stride >= 1, else NOPCS_EINVAL.  Asynchronous on hip_stream.
+ */
+int nopcs_line_spectrum(const double *f, int32_t n, int64_t stride, double *amp, void *hip_stream);
+
+/*
  * nse_rhs -- right-hand side of the non-dimensional compressible NSE (ge17):
  *   R = dEv/dx + dFv/dy + dGv/dz + S - (dE/dx + dF/dy + dG/dz)
  * with convective fluxes ge3-ge5 differentiated by the NOHAP compact scheme
@@ -316,7 +339,8 @@ enum {
     NOPCS_K_RK = 6,       /* RK4 register update of one stage (when not fused)    */
     NOPCS_K_CLOSURE_Y = 7,/* closure rows of the y sweep (line-march pass)         */
     NOPCS_K_CLOSURE_Z = 8,/* closure rows of the z sweep (line-march pass)         */
-    NOPCS_K_VORT = 9,     /* point-wise parts of the vorticity budget             */
+    NOPCS_K_VORT = 9,     /* diagnostics: point-wise parts of the vorticity       */
+                          /* budget, disturbance pressure, line spectrum          */
     NOPCS_K_COUNT = 10
 };
 

@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "kernels.hpp"
-#include "vort.hpp"
+#include "diag.hpp"
 
 namespace nopcs {
 
@@ -424,6 +424,26 @@ int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, con
             NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src[a], dst, nullptr, g, pl[d], st); }));
         }
     NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_combine(Q, G, N, S, out, st); }));
+    return NOPCS_OK;
+}
+
+int nopcs_disturbance_pressure(const nse_params *params, const nopcs_grid *grid, const double *Q, const double *Q0,
+                               double *out, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (!Q || !Q0 || !out) { set_error("Q, Q0 and out must be non-NULL"); return NOPCS_EINVAL; }
+    const long long N = (long long)field_elems(grid);
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, (hipStream_t)hip_stream, [&] {
+        return launch_disturbance_pressure(Q, Q0, N, params->gamma - 1.0, out, (hipStream_t)hip_stream);
+    }));
+    return NOPCS_OK;
+}
+
+int nopcs_line_spectrum(const double *f, int32_t n, int64_t stride, double *amp, void *hip_stream) {
+    if (!f || !amp) { set_error("f and amp must be non-NULL"); return NOPCS_EINVAL; }
+    if (n < 2 || n > 16384) { set_error("line length must be in [2, 16384]"); return NOPCS_EINVAL; }
+    if (stride < 1) { set_error("stride must be >= 1"); return NOPCS_EINVAL; }
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, (hipStream_t)hip_stream,
+                          [&] { return launch_line_spectrum(f, n, stride, amp, (hipStream_t)hip_stream); }));
     return NOPCS_OK;
 }
 

@@ -1,9 +1,11 @@
-// vort.hip -- point-wise kernels of the vorticity budget (Eq. eqn12_1): the
-// primitive fields whose gradients enter it, and the vorticity with the three
-// source terms of the inviscid vorticity transport equation built from those
-// gradients.  The derivatives in between are the compact first derivative of
-// the sweep kernels.
-#include "vort.hpp"
+// diag.hip -- kernels of the flow diagnostics.
+//  * Vorticity budget (Eq. eqn12_1): the primitive fields whose gradients enter
+//    it, and the vorticity with the three source terms of the inviscid
+//    vorticity transport equation built from those gradients.  The derivatives
+//    in between are the compact first derivative of the sweep kernels.
+//  * Disturbance pressure p - p_h (Section 4) and the amplitude spectrum of one
+//    line of it (a direct DFT; lines hold at most a few thousand points).
+#include "diag.hpp"
 
 namespace nopcs {
 
@@ -56,6 +58,50 @@ __global__ void __launch_bounds__(256) k_vort_combine(const double *__restrict__
     }
 }
 
+// out = p'(Q) - p'(Q0) = (gamma - 1)((E' - E'_0) - (k - k_0)), k = rho |V|^2 / 2
+__global__ void __launch_bounds__(256) k_disturbance_pressure(const double *__restrict__ Q,
+                                                              const double *__restrict__ Q0, long long N, double gm1,
+                                                              double *__restrict__ out) {
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += step) {
+        const double r = Q[i], m0 = Q[N + i], m1 = Q[2 * N + i], m2 = Q[3 * N + i];
+        const double k = 0.5 * ((m0 * (m0 / r) + m1 * (m1 / r)) + m2 * (m2 / r));
+        const double r0 = Q0[i], n0 = Q0[N + i], n1 = Q0[2 * N + i], n2 = Q0[3 * N + i];
+        const double k0 = 0.5 * ((n0 * (n0 / r0) + n1 * (n1 / r0)) + n2 * (n2 / r0));
+        out[i] = gm1 * ((Q[4 * N + i] - Q0[4 * N + i]) - (k - k0));
+    }
+}
+
+// amp[k] = |sum_j f[j stride] exp(-2 pi i j k / n)| / n, one block per k.  The
+// phase index j k mod n is exact in integers, so every twiddle is one
+// sincospi of an argument in [0, 2).
+constexpr int kSpecThreads = 256;
+__global__ void __launch_bounds__(kSpecThreads) k_line_spectrum(const double *__restrict__ f, int n, long long stride,
+                                                                double *__restrict__ amp) {
+    __shared__ double sre[kSpecThreads], sim[kSpecThreads];
+    const int k = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int j = threadIdx.x; j < n; j += kSpecThreads) {
+        const long long m = ((long long)j * k) % n;
+        double s, c;
+        sincospi(2.0 * (double)m / (double)n, &s, &c);
+        const double v = f[(long long)j * stride];
+        re = fma_(v, c, re);
+        im = fma_(-v, s, im);
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = kSpecThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sre[threadIdx.x] += sre[threadIdx.x + w];
+            sim[threadIdx.x] += sim[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) amp[k] = sqrt(sre[0] * sre[0] + sim[0] * sim[0]) / (double)n;
+}
+
 int pointwise_blocks(long long N) {
     const long long b = (N + 255) / 256;
     return (int)(b < 8192 ? b : 8192);
@@ -71,6 +117,17 @@ hipError_t launch_vort_prims(const double *Q, long long N, long long S, double g
 hipError_t launch_vort_combine(const double *Q, const double *G, long long N, long long S, double *out,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_vort_combine, dim3(pointwise_blocks(N)), dim3(256), 0, st, Q, G, N, S, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_disturbance_pressure(const double *Q, const double *Q0, long long N, double gm1, double *out,
+                                      hipStream_t st) {
+    hipLaunchKernelGGL(k_disturbance_pressure, dim3(pointwise_blocks(N)), dim3(256), 0, st, Q, Q0, N, gm1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_spectrum(const double *f, int n, long long stride, double *amp, hipStream_t st) {
+    hipLaunchKernelGGL(k_line_spectrum, dim3(n / 2 + 1), dim3(kSpecThreads), 0, st, f, n, stride, amp);
     return hipGetLastError();
 }
 

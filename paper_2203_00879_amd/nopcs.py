@@ -85,6 +85,8 @@ def lib():
         L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
                                      ctypes.POINTER(ctypes.c_int32 * 3)]
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.nopcs_disturbance_pressure.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, _V]
+        L.nopcs_line_spectrum.argtypes = [_V, ctypes.c_int32, ctypes.c_int64, _V, _V]
         L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
         L.nopcs_vorticity_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.nopcs_vorticity_budget.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, ctypes.c_size_t,
@@ -167,6 +169,18 @@ def vorticity_budget(params, grid, Q, out, ws=None, stream=None):
         ws = torch.empty(nb, dtype=torch.uint8, device=Q.device)
     _check(lib().nopcs_vorticity_budget(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(out), _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def disturbance_pressure(params, grid, Q, Q0, out, stream=None):
+    """out = p(Q) - p(Q0) (Section 4's disturbance pressure for Q0 the initial box)."""
+    _check(lib().nopcs_disturbance_pressure(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(Q0), _ptr(out),
+                                            _stream(stream)))
+
+
+def line_spectrum(f, n, stride, amp, stream=None):
+    """amp[k] = |DFT_k of f[j*stride], j < n| / n for k <= n // 2 (device tensors;
+    f may be a view whose data_ptr() is the line's first sample)."""
+    _check(lib().nopcs_line_spectrum(_ptr(f), int(n), int(stride), _ptr(amp), _stream(stream)))
 
 
 def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):

@@ -243,6 +243,20 @@ int main(int argc, char **argv) {
         Buf ws((wsb + 7) / 8);
         rc = nopcs_vorticity_budget(&p, &g, Q.p, out.p, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[12], out.p, 12 * N);
+    } else if (mode == "dpress") {   // disturbance pressure and the spectrum of its centre line along y
+        std::vector<double> Qh = read_raw(argv[11], 5 * N), Q0h = read_raw(argv[12], 5 * N);
+        Buf Q(5 * N), Q0(5 * N), dp(N);
+        std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
+        std::memcpy(Q0.p, Q0h.data(), 5 * N * sizeof(double));
+        const int ny = g.n[1];
+        Buf amp(ny / 2 + 1);
+        rc = nopcs_disturbance_pressure(&p, &g, Q.p, Q0.p, dp.p, nullptr);
+        const size_t c0 = ((size_t)(g.n[2] / 2) * ny) * g.n[0] + g.n[0] / 2;
+        if (rc == 0) rc = nopcs_line_spectrum(dp.p + c0, ny, g.n[0], amp.p, nullptr);
+        if (rc == 0) {
+            write_raw(argv[13], dp.p, N);
+            write_raw(argv[14], amp.p, ny / 2 + 1);
+        }
     } else {
         return 2;
     }

@@ -100,6 +100,9 @@ inline double __shfl_xor(double v, int mask, int width = 64) {
     return r;
 }
 
+// sin(pi x), cos(pi x) (host libm; the device function is more accurate)
+inline void sincospi(double x, double *s, double *c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
+
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
 typedef void *hipStream_t;

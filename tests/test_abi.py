@@ -105,3 +105,19 @@ def test_vorticity_workspace_and_argument_checks():
     assert b"aligned" in lib.nopcs_last_error()
     pb = nopcs.make_params(dict(inputs.AIR, gamma=1.0))
     assert call(ctypes.byref(pb), ctypes.byref(g), V(256), V(512), V(4096), ws, None) == -1
+
+
+def test_disturbance_pressure_and_spectrum_argument_checks():
+    from paper_2203_00879_amd import inputs
+    lib = nopcs.lib()
+    g = nopcs.make_grid(16)
+    p = nopcs.make_params(inputs.AIR)
+    V = ctypes.c_void_p
+    assert lib.nopcs_disturbance_pressure(ctypes.byref(p), ctypes.byref(g), V(256), None, V(512), None) == -1
+    assert lib.nopcs_disturbance_pressure(ctypes.byref(p), ctypes.byref(nopcs.make_grid(4)), V(256), V(512), V(768),
+                                          None) == -1
+    assert lib.nopcs_line_spectrum(V(256), 1, 1, V(512), None) == -1
+    assert lib.nopcs_line_spectrum(V(256), 16385, 1, V(512), None) == -1
+    assert lib.nopcs_line_spectrum(V(256), 64, 0, V(512), None) == -1
+    assert lib.nopcs_line_spectrum(None, 64, 1, V(512), None) == -1
+    assert b"NULL" in lib.nopcs_last_error()

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _sources():
-    names = ("api.hip", "sweep.hip", "march.hip", "visc.hip", "vort.hip", "plan.cpp", "solver.cpp")
+    names = ("api.hip", "sweep.hip", "march.hip", "visc.hip", "diag.hip", "plan.cpp", "solver.cpp")
     return [os.path.join(CSRC, f) for f in names]
 
 
@@ -206,3 +206,22 @@ def test_emulated_vorticity_budget(driver, tmp_path):
     O = oracle.vorticity_budget(p, Q, np.array(L))
     for c in range(12):
         assert _rel(G[c], O[c]) <= 1e-12, c
+
+
+def test_emulated_disturbance_pressure_and_line_spectrum(driver, tmp_path):
+    """p - p_h of an RTI box two oracle steps after release, and the amplitude
+    spectrum of its vertical centre line (odd length)."""
+    p = dict(inputs.AIR)
+    shape = (9, 37, 10)   # x, y, z
+    Q0 = inputs.rti_state(shape, seed=1, noise_K=1e-3)
+    Q = oracle.rk4(p, Q0, 2e-5, 2)
+    qin, q0in, dout, aout = (tmp_path / s for s in ("q.raw", "q0.raw", "d.raw", "a.raw"))
+    Q.tofile(qin)
+    Q0.tofile(q0in)
+    _run(driver, ["dpress", *shape, 1, 1, 1, 1.0, 1.0, 1.0, qin, q0in, dout, aout], tmp_path)
+    dp = np.fromfile(dout).reshape(Q.shape[1:])
+    want = oracle.disturbance_pressure(p, Q, Q0)
+    assert _rel(dp, want) <= 1e-12
+    amp = np.fromfile(aout)
+    # the emulated twiddles use the host libm, so compare at 1e-12 of the largest amplitude
+    assert _rel(amp, oracle.line_spectrum(want[shape[2] // 2, :, shape[0] // 2])) <= 1e-12

@@ -1,10 +1,14 @@
-"""GPU parity of the vorticity budget (Eq. eqn12_1) through the C ABI.
+"""GPU parity of the diagnostics through the C ABI.
 
-Small boxes: element by element against the oracle (global compact line
-solves), per output component, max|gpu - oracle| / max|oracle| <= 1e-12.  The
-512^3 box of the RK benchmark: a linear flow, for which every compact
-derivative is exact, against its closed form at every point.
+Vorticity budget (Eq. eqn12_1): small boxes element by element against the
+oracle (global compact line solves), per output component, max|gpu - oracle| /
+max|oracle| <= 1e-12; the 512^3 box of the RK benchmark with a linear flow, for
+which every compact derivative is exact, against its closed form at every
+point.  Disturbance pressure and line spectrum (Section 4): against the oracle
+at 1e-12, and the speed of the interface's pressure pulses in a 512-node column
+against the paper's sound speeds.
 """
+import os
 import sys
 
 import numpy as np
@@ -116,3 +120,74 @@ def test_vorticity_budget_512_linear_flow_closed_form():
         err = float((out[9 + k] * rho * rho - baro[k]).abs().max()) / np.max(np.abs(baro))
         say("baroclinic", k, "err", err)
         assert err <= 1e-10, (k, err)
+
+
+# ---------------------------------------------------------------------------
+# Disturbance pressure, line spectrum, pressure pulses (Section 4)
+# ---------------------------------------------------------------------------
+def test_disturbance_pressure_parity():
+    say("disturbance pressure parity")
+    for shape, Q0, steps in (((24, 24, 24), inputs.rti_state(24, seed=2, noise_K=1e-3), 3),
+                             ((40, 33, 37), inputs.smooth_state((40, 33, 37), seed=4), 0)):
+        Q = oracle.rk4(PARAMS, Q0, 2e-5, steps) if steps else inputs.smooth_state(shape, seed=5)
+        g = nopcs.make_grid(shape)
+        out = torch.empty(Q.shape[1:], dtype=torch.float64, device=DEV)
+        nopcs.disturbance_pressure(nopcs.make_params(PARAMS), g, torch.from_numpy(Q).to(DEV),
+                                   torch.from_numpy(Q0).to(DEV), out)
+        torch.cuda.synchronize()
+        want = oracle.disturbance_pressure(PARAMS, Q, Q0)
+        err = np.max(np.abs(out.cpu().numpy() - want)) / np.max(np.abs(want))
+        say("  ", shape, "err", err)
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("n, stride", [(2, 1), (7, 3), (512, 1), (1000, 5), (16384, 2)])
+def test_line_spectrum_parity(n, stride):
+    say("line spectrum", n, stride)
+    f = np.random.default_rng(n).normal(size=n * stride) + 0.3
+    amp = torch.empty(n // 2 + 1, dtype=torch.float64, device=DEV)
+    nopcs.line_spectrum(torch.from_numpy(f).to(DEV), n, stride, amp)
+    torch.cuda.synchronize()
+    want = oracle.line_spectrum(f[::stride][:n])
+    err = np.max(np.abs(amp.cpu().numpy() - want)) / np.max(want)
+    say("  err", err)
+    assert err <= TOL
+
+
+def test_pressure_pulses_travel_at_the_local_sound_speed():
+    """RTI column 9 x 512 x 9 at 100 K over 300 K (Section 4), stepped on the GPU;
+    the disturbance pressure of the line x = z = L/2 every 5e-5 from t = 1.5e-4
+    to 6e-4: the pulse peaks move at 200.46 and 347.21 m/s within 4 %, and the
+    spectrum of the last line satisfies Parseval's identity."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from acoustics import pulse_speeds
+    from conftest import paper_constants
+    pc = paper_constants()
+    ny, dt, every = 512, 1e-6, 50
+    say("pressure pulses", ny)
+    Q0h = inputs.rti_state((9, ny, 9), T_upper=100.0, T_lower=300.0, noise_K=0.0)
+    Q0 = torch.from_numpy(Q0h).to(DEV)
+    Q = Q0.clone()
+    g = nopcs.make_grid((9, ny, 9))
+    prm = nopcs.make_params(PARAMS)
+    ws = nopcs.alloc_workspace(g)
+    dp = torch.empty(Q.shape[1:], dtype=torch.float64, device=DEV)
+    times, lines = [], []
+    for k in range(1, 13):
+        nopcs.rk_step(prm, g, Q, dt, every, ws)
+        if k >= 3:
+            nopcs.disturbance_pressure(prm, g, Q, Q0, dp)
+            times.append(k * every * dt)
+            lines.append(dp[4, :, 4].cpu().numpy())
+    torch.cuda.synchronize()
+    su, sl = pulse_speeds(times, lines, ny)
+    Us = oracle.scales(PARAMS)[0]
+    say("  speeds (m/s)", su * Us, sl * Us)
+    assert abs(su * Us / pc["c_100K"] - 1.0) < 0.04
+    assert abs(sl * Us / pc["c_300K"] - 1.0) < 0.04
+    amp = torch.empty(ny // 2 + 1, dtype=torch.float64, device=DEV)
+    nopcs.line_spectrum(dp[4, :, 4], ny, 9, amp)
+    torch.cuda.synchronize()
+    a = amp.cpu().numpy()
+    energy = ny * (a[0] ** 2 + 2.0 * np.sum(a[1:-1] ** 2) + a[-1] ** 2)   # even ny
+    assert abs(energy / np.sum(lines[-1] ** 2) - 1.0) <= TOL
