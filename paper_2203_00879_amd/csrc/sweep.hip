@@ -27,10 +27,21 @@ __device__ inline int wall_row(int s, int n) {
 // ---------------------------------------------------------------------------
 // Standalone first / second derivative along DIR (nopcs_derivative).
 // ---------------------------------------------------------------------------
+// Lines per pencil of the standalone derivative: along y and z the lines of a
+// pencil are neighbours in x, so every row is one contiguous run of P values;
+// with a single LDS component the pencil holds 4096 values (twice the
+// multi-component sweeps' share): 16 lines of up to 256 points, 8 of 512, 4 of
+// 1024.
+template <int DIR, int NMAX>
+constexpr int deriv_pencil_width() {
+    return DIR == 0 || NMAX <= 128 ? 0 : 4096 / NMAX;
+}
+
 template <int DIR, int NMAX>
 __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, double *d1, double *d2, SweepGeom g,
                                                LinePlanDev pl) {
-    using C = SweepCfg<DIR, NMAX>;
+    constexpr int PW = deriv_pencil_width<DIR, NMAX>();
+    using C = SweepCfg<DIR, NMAX, PW>;
     __shared__ double F[C::FSZ];
     __shared__ double KN[C::P * C::KMAX];
     int np;
@@ -38,7 +49,7 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
     pencil_of<C>(g, np, base);
     const int n = g.n;
     int ks[C::PTS];
-    owned_slots<DIR, NMAX>(pl, ks);
+    owned_slots<DIR, NMAX, PW>(pl, ks);
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
@@ -46,13 +57,13 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
         if (l < np && i < n) F[C::fidx(l, i)] = f[base + l * g.sA + i * g.sD];
     }
     __syncthreads();
-    lds_line_solve<DIR, NMAX, 1>(F, KN, pl, np);
+    lds_line_solve<DIR, NMAX, 1, PW>(F, KN, pl, np);
     if (d1) {
 #pragma unroll
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, ks[s], l, i);
+            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
         }
     }
     if (d2) {
@@ -65,12 +76,12 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
             F[C::fidx(l, row)] = KN[C::kidx(s, l)];
         }
         __syncthreads();
-        lds_line_solve<DIR, NMAX, 1>(F, KN, pl, np);
+        lds_line_solve<DIR, NMAX, 1, PW>(F, KN, pl, np);
 #pragma unroll
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX>(F, KN, 0, ks[s], l, i);
+            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
         }
     }
 }
@@ -267,7 +278,7 @@ hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st) {
 template <int DIR, int NMAX>
 static hipError_t launch_deriv_t(const double *f, double *d1, double *d2, const SweepGeom &g, const LinePlanDev &pl,
                                  hipStream_t st) {
-    using C = SweepCfg<DIR, NMAX>;
+    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>()>;
     const int npa = (g.nA + C::P - 1) / C::P;
     const long long blocks = (long long)npa * g.nB;
     hipLaunchKernelGGL((k_deriv<DIR, NMAX>), dim3((unsigned)blocks), dim3(C::NT), 0, st, f, d1, d2, g, pl);

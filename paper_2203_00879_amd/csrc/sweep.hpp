@@ -25,10 +25,11 @@
 
 namespace nopcs {
 
-template <int DIR, int NMAX>
+template <int DIR, int NMAX, int PW = 0>
 struct SweepCfg {
-    // lines per pencil: every configuration keeps the block within 64 KB of LDS
-    static constexpr int P = NMAX <= 128 ? 1024 / NMAX : 2048 / NMAX;
+    // lines per pencil: every configuration keeps the block within 64 KB of LDS;
+    // PW > 0 sets it (a single-component kernel can afford wider pencils)
+    static constexpr int P = PW > 0 ? PW : NMAX <= 128 ? 1024 / NMAX : 2048 / NMAX;
     static constexpr int NT = 256;                                   // threads per block
     static constexpr int PTS = (P * NMAX) / NT;                      // owned slots per thread
     static constexpr int G = 2;                                      // components per LDS pass
@@ -79,9 +80,9 @@ inline SweepGeom sweep_geom(const int n[3], int dir) {
 // Phases A and C for NC components staged in F[c] (FP64).  Known-row values
 // land in KN(c)[slot * P + l].  All threads of the block call it; it ends with
 // a barrier; f' is then in F (compact rows) and KN (known rows).
-template <int DIR, int NMAX, int NC>
+template <int DIR, int NMAX, int NC, int PW = 0>
 __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev &pl, int np) {
-    using C = SweepCfg<DIR, NMAX>;
+    using C = SweepCfg<DIR, NMAX, PW>;
     constexpr int KS = C::P * C::KMAX;
     auto F = [&](int c) -> double * { return Fb + c * C::FSZ; };
     auto KN = [&](int c) -> double * { return KNb + c * KS; };
@@ -245,16 +246,16 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
 
 // f' of component c at (l, i) after lds_line_solve; ks = pl.kslot[i] (the
 // known-row slot of row i, -1 for a compact row), read once by the caller
-template <int DIR, int NMAX>
+template <int DIR, int NMAX, int PW = 0>
 __device__ inline double lds_result(const double *Fb, const double *KNb, int c, int ks, int l, int i) {
-    using C = SweepCfg<DIR, NMAX>;
+    using C = SweepCfg<DIR, NMAX, PW>;
     return ks < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(ks, l)];
 }
 
 // known-row slots of a thread's owned points (clamped index: always a valid read)
-template <int DIR, int NMAX>
-__device__ inline void owned_slots(const LinePlanDev &pl, int ks[SweepCfg<DIR, NMAX>::PTS]) {
-    using C = SweepCfg<DIR, NMAX>;
+template <int DIR, int NMAX, int PW = 0>
+__device__ inline void owned_slots(const LinePlanDev &pl, int ks[SweepCfg<DIR, NMAX, PW>::PTS]) {
+    using C = SweepCfg<DIR, NMAX, PW>;
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;

@@ -61,10 +61,13 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / (s if s > 0 else 1.0)
 
 
-@pytest.mark.parametrize("shape, nseg", [((27, 19, 22), (3, 2, 4)), ((16, 17, 20), (4, 4, 5))])
+@pytest.mark.parametrize("shape, nseg", [((27, 19, 22), (3, 2, 4)), ((16, 17, 20), (4, 4, 5)),
+                                         ((10, 300, 9), (1, 3, 1)), ((9, 8, 600), (1, 1, 4))])
 def test_emulated_derivative_segmented(driver, tmp_path, shape, nseg):
     """Segmented lines, the second case with 4-point segments (Thomas runs of a
-    single unknown, whose first row is also its last)."""
+    single unknown, whose first row is also its last); the last two take the
+    wide pencils of 300-point y lines (8 per block) and 600-point z lines (4 per
+    block), with a ragged last pencil."""
     f = np.random.default_rng(1).normal(size=shape[::-1])
     fin, fout = tmp_path / "f.raw", tmp_path / "d.raw"
     f.tofile(fin)
