@@ -398,7 +398,8 @@ static void idx3(const int n[3], size_t c, int *i, int *j, int *k)
  * accumulated in that order.  Convective terms use the OUCS3 global solve,
  * viscous terms the explicit second-order differences (Section 4).
  * Q, R: 5 fields of n0*n1*n2 each, field-major. */
-void ora_rhs(const ora_params *p, const int n[3], const double len[3], const double *Q, double *R)
+static void rhs_impl(const ora_params *p, const int n[3], const double len[3], const double *Q, double *R,
+                     int compact_visc)
 {
     ora_nd o;
     ora_nondim(p, &o);
@@ -421,6 +422,15 @@ void ora_rhs(const ora_params *p, const int n[3], const double len[3], const dou
     /* ---- viscous fluxes (ge6-ge8, ge19, ge20, bv1-bv3) and their divergence ---- */
     if (o.viscous) {
         double *Fv = malloc(sizeof(double) * 12 * N);   /* [dir][comp 1..4][N] */
+        /* compact variant: the twelve gradients of (u, v, w, T) by the compact
+         * first derivative (global line solves), [a][d][N] */
+        double *Gc = NULL;
+        if (compact_visc) {
+            const double *fa[4] = {u, v, w, T};
+            Gc = malloc(sizeof(double) * 12 * N);
+            for (int a = 0; a < 4; ++a)
+                for (int d = 0; d < 3; ++d) ora_d1_3d(n, len, d, fa[a], Gc + (size_t)(a * 3 + d) * N);
+        }
         #pragma omp parallel for schedule(static)
         for (size_t c = 0; c < N; ++c) {
             int i, j, k;
@@ -431,7 +441,8 @@ void ora_rhs(const ora_params *p, const int n[3], const double len[3], const dou
             for (int a = 0; a < 4; ++a)
                 for (int d = 0; d < 3; ++d) {
                     size_t base = c - (size_t)ijk[d] * (size_t)st[d];
-                    g[a][d] = d2nd(fld[a] + base, st[d], ijk[d], n[d], ih[d]);
+                    g[a][d] = compact_visc ? Gc[(size_t)(a * 3 + d) * N + c]
+                                           : d2nd(fld[a] + base, st[d], ijk[d], n[d], ih[d]);
                 }
             double m = mu[c], b = be[c];
             double A = (4.0 / 3.0) * m + b, B = b - (2.0 / 3.0) * m;
@@ -452,6 +463,12 @@ void ora_rhs(const ora_params *p, const int n[3], const double len[3], const dou
                 Fv[(size_t)(d * 4 + 3) * N + c] = uu * t[d][0] + vv * t[d][1] + ww * t[d][2] - q3[d];
             }
         }
+        /* compact variant: each flux component differentiated along its own
+         * direction by the compact first derivative, [d][comp][N] */
+        if (compact_visc)
+            for (int d = 0; d < 3; ++d)
+                for (int q = 0; q < 4; ++q)
+                    ora_d1_3d(n, len, d, Fv + (size_t)(d * 4 + q) * N, Gc + (size_t)(d * 4 + q) * N);
         #pragma omp parallel for schedule(static)
         for (size_t c = 0; c < N; ++c) {
             int i, j, k;
@@ -461,12 +478,14 @@ void ora_rhs(const ora_params *p, const int n[3], const double len[3], const dou
                 double acc = 0.0;
                 for (int d = 0; d < 3; ++d) {
                     size_t base = c - (size_t)ijk[d] * (size_t)st[d];
-                    acc += d2nd(Fv + (size_t)(d * 4 + comp - 1) * N + base, st[d], ijk[d], n[d], ih[d]);
+                    acc += compact_visc ? Gc[(size_t)(d * 4 + comp - 1) * N + c]
+                                        : d2nd(Fv + (size_t)(d * 4 + comp - 1) * N + base, st[d], ijk[d], n[d], ih[d]);
                 }
                 R[(size_t)comp * N + c] = acc;
             }
         }
         free(Fv);
+        free(Gc);
     }
 
     /* ---- gravity source (ge8a): S = [0, 0, -rho g, 0, -rho v g] ---- */
@@ -500,6 +519,22 @@ void ora_rhs(const ora_params *p, const int n[3], const double len[3], const dou
     }
     free(F); free(DF);
     free(u); free(v); free(w); free(T); free(pp); free(mu); free(be);
+}
+
+/* Right-hand side of ge17 with the viscous terms by the explicit second-order
+ * differences of Section 4 (the paper's scheme for the viscous fluxes). */
+void ora_rhs(const ora_params *p, const int n[3], const double len[3], const double *Q, double *R)
+{
+    rhs_impl(p, n, len, Q, R, 0);
+}
+
+/* The same right-hand side with every derivative of the viscous terms (the
+ * gradients of u, v, w, T inside Ev, Fv, Gv and their divergence) taken by the
+ * compact first derivative instead: the D1-based viscous variant.  Operation
+ * order otherwise as ora_rhs. */
+void ora_rhs_compact_visc(const ora_params *p, const int n[3], const double len[3], const double *Q, double *R)
+{
+    rhs_impl(p, n, len, Q, R, 1);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -20,7 +20,7 @@ _lib = None
 __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
-    "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum",
+    "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum", "rhs_compact_viscous",
 ]
 
 
@@ -68,6 +68,7 @@ def lib():
         L.ora_d1_3d_seg.argtypes = [_P, _P, _I, _I, _P, _P, _P]
         L.ora_d2_3d.argtypes = [_P, _P, _I, _P, _P]
         L.ora_rhs.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _P]
+        L.ora_rhs_compact_visc.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _P]
         L.ora_rhs_points.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _I, _P, _P]
         L.ora_apply_bc.argtypes = [ctypes.POINTER(OraParams), _P, _P]
         L.ora_rk4.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _D, _I]
@@ -190,6 +191,17 @@ def rhs(params, Q, length=1.0):
     R = np.empty_like(Q)
     p = OraParams.from_dict(params)
     lib().ora_rhs(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), _ptr(R))
+    return R
+
+
+def rhs_compact_viscous(params, Q, length=1.0):
+    """Right-hand side of ge17 with the viscous terms differentiated by the
+    compact first derivative (gradients of u, v, w, T and the divergence of
+    Ev, Fv, Gv) instead of the explicit second-order differences."""
+    Q = _f64(Q)
+    R = np.empty_like(Q)
+    p = OraParams.from_dict(params)
+    lib().ora_rhs_compact_visc(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), _ptr(R))
     return R
 
 

@@ -598,3 +598,84 @@ def test_pressure_pulses_travel_at_the_local_sound_speed():
     Us = oracle.scales(p)[0]
     assert abs(su * Us / PC["c_100K"] - 1.0) < 0.04, su * Us
     assert abs(sl * Us / PC["c_300K"] - 1.0) < 0.04, sl * Us
+
+
+# ---------------------------------------------------------------------------
+# D1-based (compact) viscous variant of the right-hand side
+# ---------------------------------------------------------------------------
+def _poly_velocity_state(shape, a, B, C, params):
+    """rho = 1, T = 1 (so p' = 0 and mu, beta are constants) and
+    V_i = a_i + B_ij x_j + C_ijk x_j x_k on the unit box; axes (z, y, x)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(*(np.linspace(0.0, 1.0, n) for n in (nz, ny, nx)), indexing="ij")
+    X = (x, y, z)
+    V = [a[i] + sum(B[i, j] * X[j] for j in range(3)) + sum(C[i, j, k] * X[j] * X[k] for j in range(3)
+                                                          for k in range(3)) for i in range(3)]
+    Q = np.zeros((5,) + shape)
+    Q[0] = 1.0
+    for i in range(3):
+        Q[1 + i] = V[i]
+    Q[4] = 0.5 * (V[0] ** 2 + V[1] ** 2 + V[2] ** 2)
+    return Q
+
+
+def _viscous_part(rhs_fn, p, Q):
+    return rhs_fn(dict(p, viscous=1), Q) - rhs_fn(dict(p, viscous=0), Q)
+
+
+@pytest.mark.parametrize("rhs_name", ["rhs", "rhs_compact_viscous"])
+def test_viscous_momentum_of_quadratic_flow_closed_form(rhs_name):
+    """With rho, T uniform, mu and beta are constants and the viscous momentum
+    term is (mu lap V_i + (beta + mu/3) d_i div V) / Re (ge19, bv1-bv3); for a
+    quadratic V every derivative of both schemes is exact, so both give it."""
+    p = _params(gravity=0)
+    rng = np.random.default_rng(12)
+    a = rng.uniform(-0.01, 0.01, 3)
+    B = rng.uniform(-0.01, 0.01, (3, 3))
+    C = rng.uniform(-0.01, 0.01, (3, 3, 3))
+    C = 0.5 * (C + C.transpose(0, 2, 1))
+    Q = _poly_velocity_state((9, 11, 10), a, B, C, p)
+    V = _viscous_part(getattr(oracle, rhs_name), p, Q)
+    Us, ts, Rh, M, Re, mu_s = oracle.scales(p)
+    mu = 1.0
+    beta = (p["mub_a"] * p["T_s"] - p["mub_b"]) / mu_s
+    lap = np.array([2.0 * np.trace(C[i]) for i in range(3)])
+    gdiv = np.array([2.0 * sum(C[j, j, i] for j in range(3)) for i in range(3)])
+    want = (mu * lap + (beta + mu / 3.0) * gdiv) / Re
+    for i in range(3):
+        assert np.max(np.abs(V[1 + i] - want[i])) <= 1e-9 * np.max(np.abs(want)), (i, want[i])
+    assert np.all(V[0] == 0.0)
+
+
+@pytest.mark.parametrize("rhs_name", ["rhs", "rhs_compact_viscous"])
+def test_viscous_heating_of_linear_flow_closed_form(rhs_name):
+    """Linear V, uniform T: the viscous energy term is the dissipation
+    B_ij tau_ij with constant stresses (no heat flux); both schemes are exact."""
+    p = _params(gravity=0)
+    rng = np.random.default_rng(13)
+    B = rng.uniform(-0.3, 0.3, (3, 3))
+    Q = _poly_velocity_state((9, 11, 10), np.zeros(3), B, np.zeros((3, 3, 3)), p)
+    V = _viscous_part(getattr(oracle, rhs_name), p, Q)
+    Us, ts, Rh, M, Re, mu_s = oracle.scales(p)
+    beta = (p["mub_a"] * p["T_s"] - p["mub_b"]) / mu_s
+    tau = ((B + B.T) + (beta - 2.0 / 3.0) * np.trace(B) * np.eye(3)) / Re
+    want = float(np.sum(B * tau))
+    assert np.max(np.abs(V[4] - want)) <= 1e-6 * abs(want)
+    assert np.max(np.abs(V[1:4])) <= 1e-6 * abs(want)
+
+
+def test_compact_and_explicit_viscous_terms_converge_together():
+    """On a smooth state the two viscous discretisations differ by the explicit
+    scheme's O(h^2) error: in the central half of the box (away from the
+    one-sided wall rows) the gap shrinks fourfold when h halves."""
+    p = _params(gravity=0)
+    gaps = []
+    for n in (17, 33):
+        Q = inputs.smooth_state((n, n, n), seed=8, amp_u=0.2, amp_p=0.5, kmax=1)
+        Ve = _viscous_part(oracle.rhs, p, Q)
+        Vc = _viscous_part(oracle.rhs_compact_viscous, p, Q)
+        m = (n - 1) // 4
+        inner = (slice(None), slice(m, -m), slice(m, -m), slice(m, -m))
+        gaps.append(np.max(np.abs(Ve[inner] - Vc[inner])) / np.max(np.abs(Vc[inner])))
+    assert gaps[1] < gaps[0] / 3.5, gaps
+    assert gaps[1] < 0.02, gaps
