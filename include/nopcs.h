@@ -213,6 +213,32 @@ int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, con
             size_t ws_bytes, void *hip_stream);
 
 /*
+ * nopcs_compact_viscous_workspace_bytes -- bytes of device workspace that
+ * nse_rhs_compact_viscous needs: nopcs_workspace_bytes(grid, NOPCS_FP64) plus
+ * 28 fields (u, v, w, T, 12 gradients, 12 viscous flux components), each
+ * rounded up to 32 doubles; 0 (with an error message) for an invalid grid.
+ */
+size_t nopcs_compact_viscous_workspace_bytes(const nopcs_grid *grid);
+
+/*
+ * nse_rhs_compact_viscous -- the right-hand side of ge17 as nse_rhs, with the
+ * viscous terms differentiated by the compact first derivative instead of the
+ * explicit second-order differences: the gradients of u, v, w and T inside Ev,
+ * Fv, Gv (ge6-ge8, ge19, ge20, bv1-bv3) and the divergence of those fluxes
+ * each take the NOHAP compact D1 of nopcs_derivative along x, y or z (with
+ * grid->nseg segments).  This is the D1-based viscous variant of the paper's
+ * own setup (Section 4 uses the explicit scheme, which nse_rhs implements).
+ * Convective terms and the gravity source are as in nse_rhs; FP64 only.
+ *
+ * Q: device state (5 fields, read only); R: device output (5 fields), must not
+ * overlap Q or ws.  ws: device workspace of at least
+ * nopcs_compact_viscous_workspace_bytes(grid) bytes, 256-byte aligned
+ * (NOPCS_EINVAL otherwise); its contents on return are unspecified.
+ */
+int nse_rhs_compact_viscous(const nse_params *params, const nopcs_grid *grid, const double *Q, double *R, void *ws,
+                            size_t ws_bytes, void *hip_stream);
+
+/*
  * rk_step -- advance Q by nsteps steps of the classical four-stage RK4
  * (Section 4) at fixed dt (non-dimensional time, units of sqrt(L/g)):
  *   k1 = R(Q), k2 = R(Q + dt/2 k1), k3 = R(Q + dt/2 k2), k4 = R(Q + dt k3),

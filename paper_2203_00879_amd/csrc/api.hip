@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "cvisc.hpp"
 #include "diag.hpp"
 
 namespace nopcs {
@@ -389,13 +390,14 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
     return NOPCS_OK;
 }
 
-// Fields of the vorticity workspace: u, v, w, p' and 15 gradients, each padded
-// to a multiple of 32 doubles so that every field starts 256-byte aligned.
-static long long vort_stride(const nopcs_grid *g) { return ((long long)field_elems(g) + 31) / 32 * 32; }
+// Stride of the scratch fields of the vorticity budget (u, v, w, p' and 15
+// gradients) and of the D1-based viscous variant: each field is padded to a
+// multiple of 32 doubles so that every field starts 256-byte aligned.
+static long long field_stride(const nopcs_grid *g) { return ((long long)field_elems(g) + 31) / 32 * 32; }
 
 size_t nopcs_vorticity_workspace_bytes(const nopcs_grid *grid) {
     if (!check_grid(grid)) return 0;
-    return (size_t)19 * (size_t)vort_stride(grid) * sizeof(double);
+    return (size_t)19 * (size_t)field_stride(grid) * sizeof(double);
 }
 
 int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, const double *Q, double *out, void *ws,
@@ -412,7 +414,7 @@ int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, con
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    const long long N = (long long)field_elems(grid), S = vort_stride(grid);
+    const long long N = (long long)field_elems(grid), S = field_stride(grid);
     double *P = static_cast<double *>(ws), *G = P + 4 * S;
     NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_prims(Q, N, S, params->gamma - 1.0, P, st); }));
     // gradients of u, v, w (from P), rho (field 0 of Q) and p' (P field 3)
@@ -460,6 +462,72 @@ static int rhs_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev 
     a.c = c;
     for (int d = 0; d < 3; ++d) {
         const int rc = conv_sweep(d, a, grid, pl[d], clo, c32, st);
+        if (rc != NOPCS_OK) return rc;
+    }
+    return NOPCS_OK;
+}
+
+// Workspace of the D1-based viscous variant: the right-hand side's own
+// workspace, then u, v, w, T, 12 gradients (later the 12 flux derivatives)
+// and 12 flux components, each field padded as in the vorticity budget.
+size_t nopcs_compact_viscous_workspace_bytes(const nopcs_grid *grid) {
+    if (!check_grid(grid)) return 0;
+    return nopcs_workspace_bytes(grid, NOPCS_FP64) + (size_t)28 * (size_t)field_stride(grid) * sizeof(double);
+}
+
+int nse_rhs_compact_viscous(const nse_params *params, const nopcs_grid *grid, const double *Q, double *R, void *ws,
+                            size_t ws_bytes, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (!Q || !R) { set_error("Q and R must be non-NULL"); return NOPCS_EINVAL; }
+    const size_t need = nopcs_compact_viscous_workspace_bytes(grid);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return NOPCS_EINVAL;
+    }
+    if (((uintptr_t)ws & 255) != 0) { set_error("workspace must be 256-byte aligned"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const NdConst c = make_nd(*params);
+    double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * state_bytes(grid));
+    if (!c.viscous) {
+        double ih[3];
+        for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, false, grid->n, ih, c, st); }));
+    } else {
+        const long long N = (long long)field_elems(grid), S = field_stride(grid);
+        double *P = reinterpret_cast<double *>(static_cast<char *>(ws) + nopcs_workspace_bytes(grid, NOPCS_FP64));
+        double *G = P + 4 * S, *F = P + 16 * S;
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_prims(Q, N, S, c, P, st); }));
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d) {
+                const SweepGeom g = sweep_geom(grid->n, d);
+                double *dst = G + (3 * a + d) * S;
+                const double *src = P + a * S;
+                NOPCS_HIP_CHECK(
+                    timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+            }
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_flux(P, G, N, S, c, F, st); }));
+        // D_d of flux component 4d + q into the gradient slots
+        for (int d = 0; d < 3; ++d)
+            for (int q = 0; q < 4; ++q) {
+                const SweepGeom g = sweep_geom(grid->n, d);
+                double *dst = G + (4 * d + q) * S;
+                const double *src = F + (4 * d + q) * S;
+                NOPCS_HIP_CHECK(
+                    timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+            }
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_assemble(Q, G, N, S, c, R, st); }));
+    }
+    NseSweepArgs a{};
+    a.Qin = Q;
+    a.R = R;
+    a.r32 = false;
+    a.N3 = (long long)field_elems(grid);
+    a.c = c;
+    for (int d = 0; d < 3; ++d) {
+        rc = conv_sweep(d, a, grid, pl[d], clo, false, st);
         if (rc != NOPCS_OK) return rc;
     }
     return NOPCS_OK;

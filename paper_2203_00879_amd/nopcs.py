@@ -87,6 +87,10 @@ def lib():
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
         L.nopcs_disturbance_pressure.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, _V]
         L.nopcs_line_spectrum.argtypes = [_V, ctypes.c_int32, ctypes.c_int64, _V, _V]
+        L.nopcs_compact_viscous_workspace_bytes.restype = ctypes.c_size_t
+        L.nopcs_compact_viscous_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
+        L.nse_rhs_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V,
+                                              ctypes.c_size_t, _V]
         L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
         L.nopcs_vorticity_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.nopcs_vorticity_budget.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, ctypes.c_size_t,
@@ -191,6 +195,24 @@ def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):
     nbytes = ws.numel() * ws.element_size()
     _check(lib().nse_rhs(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(R), _ptr(ws),
                          nbytes, _stream(stream)))
+
+
+def compact_viscous_workspace_bytes(grid):
+    return lib().nopcs_compact_viscous_workspace_bytes(ctypes.byref(grid))
+
+
+def nse_rhs_compact_viscous(params, grid, Q, R, ws=None, stream=None):
+    """R = right-hand side of ge17 with the viscous terms by the compact first
+    derivative.  ws: device workspace of compact_viscous_workspace_bytes(grid)
+    bytes; allocated here when not given."""
+    if ws is None:
+        import torch
+        nb = compact_viscous_workspace_bytes(grid)
+        if nb == 0:
+            raise NopcsError(NOPCS_EINVAL, last_error())
+        ws = torch.empty(nb, dtype=torch.uint8, device=Q.device)
+    _check(lib().nse_rhs_compact_viscous(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(R), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def rk_step(params, grid, Q, dt, nsteps, ws, precision=FP64, stream=None):

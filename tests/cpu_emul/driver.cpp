@@ -235,6 +235,16 @@ int main(int argc, char **argv) {
         Buf ws((wsb + 7) / 8);
         rc = rk_step(&p, &g, prec, Q.p, dt, nsteps, ws.p, wsb, nullptr);
         if (rc == 0) write_raw(argv[16], Q.p, 5 * N);
+    } else if (mode == "cvisc") {
+        p.viscous = std::atoi(argv[11]);
+        p.gravity = std::atoi(argv[12]);
+        std::vector<double> Qh = read_raw(argv[13], 5 * N);
+        Buf Q(5 * N), R(5 * N);
+        std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
+        const size_t wsb = nopcs_compact_viscous_workspace_bytes(&g);
+        Buf ws((wsb + 7) / 8);
+        rc = nse_rhs_compact_viscous(&p, &g, Q.p, R.p, ws.p, wsb, nullptr);
+        if (rc == 0) write_raw(argv[14], R.p, 5 * N);
     } else if (mode == "vort") {
         std::vector<double> Qh = read_raw(argv[11], 5 * N);
         Buf Q(5 * N), out(12 * N);

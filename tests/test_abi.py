@@ -121,3 +121,21 @@ def test_disturbance_pressure_and_spectrum_argument_checks():
     assert lib.nopcs_line_spectrum(V(256), 64, 0, V(512), None) == -1
     assert lib.nopcs_line_spectrum(None, 64, 1, V(512), None) == -1
     assert b"NULL" in lib.nopcs_last_error()
+
+
+def test_compact_viscous_workspace_and_argument_checks():
+    from paper_2203_00879_amd import inputs
+    lib = nopcs.lib()
+    g = nopcs.make_grid((9, 10, 11))
+    S = (9 * 10 * 11 + 31) // 32 * 32
+    ws = nopcs.compact_viscous_workspace_bytes(g)
+    assert ws == nopcs.workspace_bytes(g) + 28 * S * 8
+    assert nopcs.compact_viscous_workspace_bytes(nopcs.make_grid(4)) == 0
+    p = nopcs.make_params(inputs.AIR)
+    V = ctypes.c_void_p
+    call = lib.nse_rhs_compact_viscous
+    assert call(ctypes.byref(p), ctypes.byref(g), None, V(512), V(4096), ws, None) == -1
+    assert call(ctypes.byref(p), ctypes.byref(g), V(256), V(512), V(4096), ws - 8, None) == -1
+    assert b"workspace" in lib.nopcs_last_error()
+    assert call(ctypes.byref(p), ctypes.byref(g), V(256), V(512), V(4104), ws, None) == -1
+    assert b"aligned" in lib.nopcs_last_error()

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
 def _sources():
-    names = ("api.hip", "sweep.hip", "march.hip", "visc.hip", "diag.hip", "plan.cpp", "solver.cpp")
+    names = ("api.hip", "sweep.hip", "march.hip", "visc.hip", "cvisc.hip", "diag.hip", "plan.cpp", "solver.cpp")
     return [os.path.join(CSRC, f) for f in names]
 
 
@@ -228,3 +228,18 @@ def test_emulated_disturbance_pressure_and_line_spectrum(driver, tmp_path):
     amp = np.fromfile(aout)
     # the emulated twiddles use the host libm, so compare at 1e-12 of the largest amplitude
     assert _rel(amp, oracle.line_spectrum(want[shape[2] // 2, :, shape[0] // 2])) <= 1e-12
+
+
+def test_emulated_rhs_compact_viscous(driver, tmp_path):
+    """D1-based viscous variant on a ragged, segmented box with unequal lengths."""
+    p = dict(inputs.AIR)
+    shape = (17, 14, 19)   # x, y, z
+    L = (1.0, 0.9, 1.2)
+    Q = inputs.smooth_state(shape, seed=9, length=L)
+    qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
+    Q.tofile(qin)
+    _run(driver, ["cvisc", *shape, 2, 1, 3, *L, 1, 1, qin, rout], tmp_path)
+    R = np.fromfile(rout).reshape(Q.shape)
+    Ro = oracle.rhs_compact_viscous(p, Q, np.array(L))
+    for c in range(5):
+        assert _rel(R[c], Ro[c]) <= 1e-12, c
