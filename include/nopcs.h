@@ -255,6 +255,16 @@ int nse_rhs_compact_viscous(const nse_params *params, const nopcs_grid *grid, co
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,
             void *ws, size_t ws_bytes, void *hip_stream);
 
+/*
+ * rk_step_compact_viscous -- rk_step in FP64 with the right-hand side of
+ * nse_rhs_compact_viscous (viscous terms by the compact first derivative):
+ * the same four stages, registers and wall conditions.  ws: at least
+ * nopcs_compact_viscous_workspace_bytes(grid) bytes, 256-byte aligned; Q
+ * 16-byte aligned.  Launches directly (no graph replay).
+ */
+int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, double *Q, double dt, int32_t nsteps,
+                            void *ws, size_t ws_bytes, void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning.                                                                    */
 /* ------------------------------------------------------------------------ */

@@ -625,6 +625,19 @@ void ora_rk4(const ora_params *p, const int n[3], const double len[3], double *Q
     ora_rk4_generic((size_t)5 * n[0] * n[1] * n[2], Q, dt, nsteps, nse_rhs_cb, nse_bc_cb, &c);
 }
 
+static void nse_rhs_cv_cb(void *ctx, const double *q, double *r)
+{
+    nse_ctx *c = (nse_ctx *)ctx;
+    ora_rhs_compact_visc(c->p, c->n, c->len, q, r);
+}
+
+/* The same stepping with the D1-based viscous variant of the right-hand side. */
+void ora_rk4_compact_visc(const ora_params *p, const int n[3], const double len[3], double *Q, double dt, int nsteps)
+{
+    nse_ctx c = {p, n, len};
+    ora_rk4_generic((size_t)5 * n[0] * n[1] * n[2], Q, dt, nsteps, nse_rhs_cv_cb, nse_bc_cb, &c);
+}
+
 /* RK4 on the scalar linear test problem dq/dt = lambda q (real lambda),
  * using the same stage driver; used to pin the stage combination. */
 typedef struct { double lam; } lin_ctx;

@@ -20,7 +20,7 @@ _lib = None
 __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
-    "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum", "rhs_compact_viscous",
+    "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum", "rhs_compact_viscous", "rk4_compact_viscous",
 ]
 
 
@@ -72,6 +72,7 @@ def lib():
         L.ora_rhs_points.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _I, _P, _P]
         L.ora_apply_bc.argtypes = [ctypes.POINTER(OraParams), _P, _P]
         L.ora_rk4.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _D, _I]
+        L.ora_rk4_compact_visc.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _D, _I]
         L.ora_rk4_linear.argtypes = [_D, _D, _D, _I]
         L.ora_rk4_linear.restype = _D
         L.ora_scales.argtypes = [ctypes.POINTER(OraParams), _P]
@@ -228,6 +229,15 @@ def rk4(params, Q, dt, nsteps, length=1.0):
     Q = _f64(Q).copy()
     p = OraParams.from_dict(params)
     lib().ora_rk4(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), float(dt), int(nsteps))
+    return Q
+
+
+def rk4_compact_viscous(params, Q, dt, nsteps, length=1.0):
+    """rk4 with the D1-based viscous variant of the right-hand side."""
+    Q = _f64(Q).copy()
+    p = OraParams.from_dict(params)
+    lib().ora_rk4_compact_visc(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), float(dt),
+                               int(nsteps))
     return Q
 
 

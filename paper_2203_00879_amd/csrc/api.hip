@@ -79,6 +79,10 @@ static int get_plans(const nopcs_grid *g, LinePlanDev pl[3]) {
 }
 
 static size_t field_elems(const nopcs_grid *g) { return (size_t)g->n[0] * g->n[1] * g->n[2]; }
+// Stride of the scratch fields of the vorticity budget (u, v, w, p' and 15
+// gradients) and of the D1-based viscous variant: each field is padded to a
+// multiple of 32 doubles so that every field starts 256-byte aligned.
+static long long field_stride(const nopcs_grid *g) { return ((long long)field_elems(g) + 31) / 32 * 32; }
 
 // ---------------------------------------------------------------------------
 // Event timing of kernel launches (instrumentation only).
@@ -187,8 +191,45 @@ static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, cons
 
 // One classical RK4 step (Section 4): per stage the viscous terms and source,
 // the three convective sweeps, the register update and the wall conditions.
+// Viscous terms and gravity source by the compact first derivative (the
+// D1-based variant) into R, FP64: point-wise u, v, w, T into X, their 12
+// gradients, the 12 flux components, the 12 flux derivatives along their own
+// directions, then the divergence plus source.  X: 28 fields of
+// field_stride(grid) doubles.  Without viscous terms: the source alone, as in
+// the explicit path.
+static int compact_visc_into(const NdConst &c, const nopcs_grid *grid, const LinePlanDev pl[3], const double *Q,
+                             double *R, double *X, hipStream_t st) {
+    if (!c.viscous) {
+        double ih[3];
+        for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
+        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, false, grid->n, ih, c, st); }));
+        return NOPCS_OK;
+    }
+    const long long N = (long long)field_elems(grid), S = field_stride(grid);
+    double *P = X, *G = X + 4 * S, *F = X + 16 * S;
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_prims(Q, N, S, c, P, st); }));
+    for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d) {
+            const SweepGeom g = sweep_geom(grid->n, d);
+            double *dst = G + (3 * a + d) * S;
+            const double *src = P + a * S;
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+        }
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_flux(P, G, N, S, c, F, st); }));
+    // D_d of flux component 4d + q into the gradient slots
+    for (int d = 0; d < 3; ++d)
+        for (int q = 0; q < 4; ++q) {
+            const SweepGeom g = sweep_geom(grid->n, d);
+            double *dst = G + (4 * d + q) * S;
+            const double *src = F + (4 * d + q) * S;
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+        }
+    NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_assemble(Q, G, N, S, c, R, st); }));
+    return NOPCS_OK;
+}
+
 static int launch_step(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
-                       const LinePlanDev pl[3], hipStream_t st) {
+                       const LinePlanDev pl[3], hipStream_t st, double *cvx = nullptr) {
     const NdConst c = make_nd(params);
     const size_t N = field_elems(grid);
     const size_t reg = state_bytes(grid);
@@ -227,7 +268,13 @@ static int launch_step(const nse_params &params, const nopcs_grid *grid, int pre
         a.Qin = Qin;
         a.R = Rs;
         a.stage = stage;
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st); }));
+        if (cvx) {   // D1-based viscous variant (FP64 only)
+            const int rc = compact_visc_into(c, grid, pl, Qin, static_cast<double *>(Rs), cvx, st);
+            if (rc != NOPCS_OK) return rc;
+        } else {
+            NOPCS_HIP_CHECK(
+                timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st); }));
+        }
         if (fuse) {
             const RkFuse F{K, Q, Sout, stage, dt, 0.5 * dt, dt / 6.0};
             for (int d = 0; d < 3; ++d) {
@@ -390,10 +437,6 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
     return NOPCS_OK;
 }
 
-// Stride of the scratch fields of the vorticity budget (u, v, w, p' and 15
-// gradients) and of the D1-based viscous variant: each field is padded to a
-// multiple of 32 doubles so that every field starts 256-byte aligned.
-static long long field_stride(const nopcs_grid *g) { return ((long long)field_elems(g) + 31) / 32 * 32; }
 
 size_t nopcs_vorticity_workspace_bytes(const nopcs_grid *grid) {
     if (!check_grid(grid)) return 0;
@@ -491,35 +534,9 @@ int nse_rhs_compact_viscous(const nse_params *params, const nopcs_grid *grid, co
     hipStream_t st = (hipStream_t)hip_stream;
     const NdConst c = make_nd(*params);
     double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * state_bytes(grid));
-    if (!c.viscous) {
-        double ih[3];
-        for (int d = 0; d < 3; ++d) ih[d] = (double)(grid->n[d] - 1) / grid->len[d];
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Q, R, false, grid->n, ih, c, st); }));
-    } else {
-        const long long N = (long long)field_elems(grid), S = field_stride(grid);
-        double *P = reinterpret_cast<double *>(static_cast<char *>(ws) + nopcs_workspace_bytes(grid, NOPCS_FP64));
-        double *G = P + 4 * S, *F = P + 16 * S;
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_prims(Q, N, S, c, P, st); }));
-        for (int a = 0; a < 4; ++a)
-            for (int d = 0; d < 3; ++d) {
-                const SweepGeom g = sweep_geom(grid->n, d);
-                double *dst = G + (3 * a + d) * S;
-                const double *src = P + a * S;
-                NOPCS_HIP_CHECK(
-                    timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
-            }
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_flux(P, G, N, S, c, F, st); }));
-        // D_d of flux component 4d + q into the gradient slots
-        for (int d = 0; d < 3; ++d)
-            for (int q = 0; q < 4; ++q) {
-                const SweepGeom g = sweep_geom(grid->n, d);
-                double *dst = G + (4 * d + q) * S;
-                const double *src = F + (4 * d + q) * S;
-                NOPCS_HIP_CHECK(
-                    timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
-            }
-        NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_assemble(Q, G, N, S, c, R, st); }));
-    }
+    double *X = reinterpret_cast<double *>(static_cast<char *>(ws) + nopcs_workspace_bytes(grid, NOPCS_FP64));
+    rc = compact_visc_into(c, grid, pl, Q, R, X, st);
+    if (rc != NOPCS_OK) return rc;
     NseSweepArgs a{};
     a.Qin = Q;
     a.R = R;
@@ -585,6 +602,30 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     rc = step_graph(*params, grid, precision, Q, dt, ws, pl, &exec);
     if (rc != NOPCS_OK) return rc;
     for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(exec, st));
+    return NOPCS_OK;
+}
+
+int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, double *Q, double dt, int32_t nsteps,
+                            void *ws, size_t ws_bytes, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
+    if (((uintptr_t)Q & 15) != 0) { set_error("Q must be 16-byte aligned"); return NOPCS_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
+    if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
+    const size_t need = nopcs_compact_viscous_workspace_bytes(grid);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return NOPCS_EINVAL;
+    }
+    if (((uintptr_t)ws & 255) != 0) { set_error("workspace must be 256-byte aligned"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl);
+    if (rc != NOPCS_OK) return rc;
+    double *cvx = reinterpret_cast<double *>(static_cast<char *>(ws) + nopcs_workspace_bytes(grid, NOPCS_FP64));
+    for (int step = 0; step < nsteps; ++step) {
+        rc = launch_step(*params, grid, NOPCS_FP64, Q, dt, ws, pl, (hipStream_t)hip_stream, cvx);
+        if (rc != NOPCS_OK) return rc;
+    }
     return NOPCS_OK;
 }
 

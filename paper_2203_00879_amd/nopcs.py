@@ -91,6 +91,8 @@ def lib():
         L.nopcs_compact_viscous_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.nse_rhs_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V,
                                               ctypes.c_size_t, _V]
+        L.rk_step_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, ctypes.c_double,
+                                              ctypes.c_int32, _V, ctypes.c_size_t, _V]
         L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
         L.nopcs_vorticity_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.nopcs_vorticity_budget.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, ctypes.c_size_t,
@@ -213,6 +215,13 @@ def nse_rhs_compact_viscous(params, grid, Q, R, ws=None, stream=None):
         ws = torch.empty(nb, dtype=torch.uint8, device=Q.device)
     _check(lib().nse_rhs_compact_viscous(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(R), _ptr(ws),
                                          ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def rk_step_compact_viscous(params, grid, Q, dt, nsteps, ws, stream=None):
+    """rk_step (FP64) with the D1-based viscous variant; ws of
+    compact_viscous_workspace_bytes(grid) bytes."""
+    _check(lib().rk_step_compact_viscous(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), float(dt), int(nsteps),
+                                         _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def rk_step(params, grid, Q, dt, nsteps, ws, precision=FP64, stream=None):

@@ -1,7 +1,7 @@
 """Time of one right-hand side on one GPU: nse_rhs (explicit second-order
 viscous terms, the paper's scheme) against nse_rhs_compact_viscous (viscous
 terms by the compact first derivative: 24 extra derivative launches and three
-point-wise kernels).
+point-wise kernels), and one RK4 step of rk_step against rk_step_compact_viscous.
 
 Workload (seeded, synthetic): the RTI box of the RK benchmark, 512^3 points,
 4 segments per direction.  HIP events on the launch stream over `reps` calls
@@ -41,6 +41,20 @@ def run(n=512, nseg=4, reps=5):
         torch.cuda.synchronize()
         ms = s.elapsed_time(e) / reps
         out[name] = {"ms": ms, "Mpoint_per_s": n ** 3 / (ms * 1e-3) / 1e6, "finite": bool(torch.isfinite(R).all())}
+    # one RK4 step of each (dt = 1e-6), after one untimed step
+    for name, fn in (("rk_step_explicit_viscous", lambda: nopcs.rk_step(p, g, Q, 1e-6, 1, ws, stream=stream)),
+                     ("rk_step_compact_viscous",
+                      lambda: nopcs.rk_step_compact_viscous(p, g, Q, 1e-6, 1, ws, stream=stream))):
+        fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        out[name] = {"ms_per_step": ms, "Mpoint_stage_per_s": 4 * n ** 3 / (ms * 1e-3) / 1e6,
+                     "finite": bool(torch.isfinite(Q).all())}
     return out
 
 

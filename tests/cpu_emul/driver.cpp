@@ -243,8 +243,16 @@ int main(int argc, char **argv) {
         std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
         const size_t wsb = nopcs_compact_viscous_workspace_bytes(&g);
         Buf ws((wsb + 7) / 8);
-        rc = nse_rhs_compact_viscous(&p, &g, Q.p, R.p, ws.p, wsb, nullptr);
-        if (rc == 0) write_raw(argv[14], R.p, 5 * N);
+        // argv[15] (optional): dt and steps "dt:n" -> rk_step_compact_viscous instead
+        if (argc > 15) {
+            const double dt = std::atof(argv[15]);
+            const int nst = std::atoi(std::strchr(argv[15], ':') + 1);
+            rc = rk_step_compact_viscous(&p, &g, Q.p, dt, nst, ws.p, wsb, nullptr);
+            if (rc == 0) write_raw(argv[14], Q.p, 5 * N);
+        } else {
+            rc = nse_rhs_compact_viscous(&p, &g, Q.p, R.p, ws.p, wsb, nullptr);
+            if (rc == 0) write_raw(argv[14], R.p, 5 * N);
+        }
     } else if (mode == "vort") {
         std::vector<double> Qh = read_raw(argv[11], 5 * N);
         Buf Q(5 * N), out(12 * N);

@@ -243,3 +243,20 @@ def test_emulated_rhs_compact_viscous(driver, tmp_path):
     Ro = oracle.rhs_compact_viscous(p, Q, np.array(L))
     for c in range(5):
         assert _rel(R[c], Ro[c]) <= 1e-12, c
+
+
+def test_emulated_rk_step_compact_viscous(driver, tmp_path):
+    """One RK4 step with the D1-based viscous variant (z line march carrying
+    the stage update on an 8 x 12 x 36 box with pieces), against the oracle:
+    the fields and their change over the step."""
+    p = dict(inputs.AIR)
+    shape = (8, 12, 36)
+    Q = inputs.rti_state(shape, seed=2, noise_K=1e-3)
+    qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
+    Q.tofile(qin)
+    _run(driver, ["cvisc", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, qin, qout, "2e-5:1"], tmp_path, piece=16)
+    G = np.fromfile(qout).reshape(Q.shape)
+    O = oracle.rk4_compact_viscous(p, Q, 2e-5, 1)
+    for c in range(5):
+        assert _rel(G[c], O[c]) <= 1e-12, c
+        assert _rel(G[c] - Q[c], O[c] - Q[c]) <= 1e-9, c

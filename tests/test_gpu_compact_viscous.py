@@ -77,3 +77,26 @@ def test_inviscid_variant_equals_nse_rhs_bitwise():
     p = dict(inputs.AIR, viscous=0)
     Q = inputs.smooth_state((24, 20, 28), seed=14)
     assert np.array_equal(gpu_rhs(p, Q, (2, 1, 2), 1.0), gpu_rhs(p, Q, (2, 1, 2), 1.0, compact=False))
+
+
+@pytest.mark.parametrize("shape, nseg", [((32, 32, 32), (2, 2, 2)), ((24, 40, 96), (1, 2, 3))])
+def test_rk_step_compact_viscous_parity(shape, nseg):
+    """Two RK4 steps with the variant against the oracle: fields <= 1e-12 and
+    their change over the steps <= 1e-9 (relative to each field's maximum)."""
+    say("rk compact viscous", shape, nseg)
+    p = dict(inputs.AIR)
+    Q0 = inputs.rti_state(shape, seed=4, noise_K=1e-3)
+    nx, ny, nz = shape
+    g = nopcs.make_grid(shape, nseg)
+    Qd = torch.from_numpy(Q0.copy()).to(DEV)
+    ws = torch.empty(nopcs.compact_viscous_workspace_bytes(g), dtype=torch.uint8, device=DEV)
+    nopcs.rk_step_compact_viscous(nopcs.make_params(p), g, Qd, 2e-5, 2, ws)
+    torch.cuda.synchronize()
+    G = Qd.cpu().numpy()
+    O = oracle.rk4_compact_viscous(p, Q0, 2e-5, 2)
+    for c in range(5):
+        s = np.max(np.abs(O[c]))
+        assert np.max(np.abs(G[c] - O[c])) / s <= TOL, c
+        ch = np.max(np.abs(O[c] - Q0[c]))
+        if ch > 0:
+            assert np.max(np.abs((G[c] - Q0[c]) - (O[c] - Q0[c]))) / ch <= 1e-9, c

@@ -679,3 +679,14 @@ def test_compact_and_explicit_viscous_terms_converge_together():
         gaps.append(np.max(np.abs(Ve[inner] - Vc[inner])) / np.max(np.abs(Vc[inner])))
     assert gaps[1] < gaps[0] / 3.5, gaps
     assert gaps[1] < 0.02, gaps
+
+
+def test_compact_viscous_stepping_keeps_quiescent_state():
+    """Every compact derivative of a constant field is exactly zero, so the
+    variant leaves a quiescent isothermal box unchanged bit for bit."""
+    p = _params(gravity=0)
+    Q = inputs.uniform_state((12, 10, 14), T=1.3, rho=0.8, params=p)
+    assert np.all(oracle.rhs_compact_viscous(p, Q) == 0.0)
+    # at T = rho = 1 the wall conditions also reproduce the stored E' exactly
+    Q = inputs.uniform_state((12, 10, 14), T=1.0, rho=1.0, params=p)
+    assert np.array_equal(oracle.rk4_compact_viscous(p, Q, 1e-4, 3), Q)
