@@ -265,6 +265,29 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
 int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, double *Q, double dt, int32_t nsteps,
                             void *ws, size_t ws_bytes, void *hip_stream);
 
+/*
+ * rk_step_batch -- rk_step for a batch of independent boxes of any sizes, all
+ * with the same parameters, precision and dt: the RK4 step of every box is
+ * captured once as a branch of one HIP graph (cached per batch: boxes, their
+ * states and workspaces, parameters, precision, dt and piece lengths), and
+ * each of the nsteps steps is one replay of that graph on hip_stream; the
+ * device runs the branches concurrently.  Every box gets exactly the result of
+ * rk_step on it alone.  1 <= nbox <= NOPCS_MAX_BATCH; each box: a valid grid,
+ * Q 16-byte aligned, ws of at least nopcs_workspace_bytes(grid, precision)
+ * bytes, 256-byte aligned; no two boxes may share a state or a workspace.
+ * NOPCS_EINVAL on argument errors (before any device work).
+ */
+#define NOPCS_MAX_BATCH 16
+typedef struct {
+    nopcs_grid grid;
+    double *Q;               /* device state, in/out */
+    void *ws;                /* device workspace of this box */
+    size_t ws_bytes;
+} nopcs_box;
+
+int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes, int precision, double dt,
+                  int32_t nsteps, void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning.                                                                    */
 /* ------------------------------------------------------------------------ */

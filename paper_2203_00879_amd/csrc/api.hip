@@ -629,6 +629,121 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
     return NOPCS_OK;
 }
 
+// One graph for a batch of boxes: the RK4 step of every box is captured as its
+// own branch (a private stream forked from the capture stream and joined back),
+// so one replay runs all boxes and the device overlaps the branches.
+static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
+                       const LinePlanDev (*pl)[3], hipGraphExec_t *out) {
+    int dev = 0;
+    NOPCS_HIP_CHECK(hipGetDevice(&dev));
+    std::string key = "batch";
+    put_bytes(key, dev);
+    put_bytes(key, params);
+    put_bytes(key, precision);
+    put_bytes(key, dt);
+    for (int b = 0; b < nbox; ++b) {
+        put_bytes(key, boxes[b].grid);
+        put_bytes(key, boxes[b].Q);
+        put_bytes(key, boxes[b].ws);
+        for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, boxes[b].grid.n[d]));
+    }
+    std::lock_guard<std::mutex> lk(g_gmu);
+    auto it = g_graph_cache.find(key);
+    if (it != g_graph_cache.end()) {
+        *out = it->second.exec;
+        return NOPCS_OK;
+    }
+    if (g_graph_cache.size() >= kMaxGraphs) {
+        drop_graph(g_graph_cache.begin()->second);
+        g_graph_cache.erase(g_graph_cache.begin());
+    }
+    hipStream_t &cs = g_capture_stream[dev];
+    if (!cs) NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // branch streams and fork/join events of this device, kept for the process
+    static std::map<int, std::vector<hipStream_t>> branch;
+    static std::map<int, std::vector<hipEvent_t>> events;
+    std::vector<hipStream_t> &bs = branch[dev];
+    std::vector<hipEvent_t> &ev = events[dev];
+    while ((int)bs.size() < nbox) {
+        hipStream_t s = nullptr;
+        NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        bs.push_back(s);
+    }
+    while ((int)ev.size() < nbox + 1) {
+        hipEvent_t e = nullptr;
+        NOPCS_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ev.push_back(e);
+    }
+    GraphEntry e;
+    NOPCS_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    t_capturing = true;
+    int rc = NOPCS_OK;
+    hipError_t he = hipEventRecord(ev[nbox], cs);
+    for (int b = 0; b < nbox && rc == NOPCS_OK && he == hipSuccess; ++b) {
+        he = hipStreamWaitEvent(bs[b], ev[nbox], 0);
+        if (he != hipSuccess) break;
+        rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dt, boxes[b].ws, pl[b], bs[b]);
+        if (rc != NOPCS_OK) break;
+        he = hipEventRecord(ev[b], bs[b]);
+        if (he == hipSuccess) he = hipStreamWaitEvent(cs, ev[b], 0);
+    }
+    t_capturing = false;
+    const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
+    if (rc != NOPCS_OK || he != hipSuccess || ec != hipSuccess) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        if (rc != NOPCS_OK) return rc;
+        set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he != hipSuccess ? he : ec));
+        return NOPCS_EDEVICE;
+    }
+    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(e.graph);
+        set_error("hipGraphInstantiate failed");
+        return NOPCS_EDEVICE;
+    }
+    g_graph_cache[key] = e;
+    *out = e.exec;
+    return NOPCS_OK;
+}
+
+int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes, int precision, double dt,
+                  int32_t nsteps, void *hip_stream) {
+    if (!check_params(params)) return NOPCS_EINVAL;
+    if (nbox < 1 || nbox > NOPCS_MAX_BATCH) {
+        set_error("nbox must be in [1, " + std::to_string(NOPCS_MAX_BATCH) + "]");
+        return NOPCS_EINVAL;
+    }
+    if (!boxes) { set_error("boxes is NULL"); return NOPCS_EINVAL; }
+    if (precision != NOPCS_FP64 && precision != NOPCS_MIXED) { set_error("unknown precision"); return NOPCS_EINVAL; }
+    if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return NOPCS_EINVAL; }
+    if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
+    for (int b = 0; b < nbox; ++b) {
+        const nopcs_box &x = boxes[b];
+        if (!check_grid(&x.grid)) return NOPCS_EINVAL;
+        if (!x.Q || ((uintptr_t)x.Q & 15) != 0) {
+            set_error("box " + std::to_string(b) + ": Q must be non-NULL and 16-byte aligned");
+            return NOPCS_EINVAL;
+        }
+        if (!check_ws(&x.grid, precision, x.ws, x.ws_bytes)) return NOPCS_EINVAL;
+        for (int c = 0; c < b; ++c)
+            if (boxes[c].Q == x.Q || boxes[c].ws == x.ws) {
+                set_error("boxes " + std::to_string(c) + " and " + std::to_string(b) + " share a state or workspace");
+                return NOPCS_EINVAL;
+            }
+    }
+    std::vector<LinePlanDev> plv((size_t)nbox * 3);
+    LinePlanDev(*pl)[3] = reinterpret_cast<LinePlanDev(*)[3]>(plv.data());
+    for (int b = 0; b < nbox; ++b) {
+        const int rc = get_plans(&boxes[b].grid, pl[b]);
+        if (rc != NOPCS_OK) return rc;
+    }
+    if (nsteps == 0) return NOPCS_OK;
+    hipGraphExec_t exec = nullptr;
+    const int rc = batch_graph(*params, nbox, boxes, precision, dt, pl, &exec);
+    if (rc != NOPCS_OK) return rc;
+    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(exec, (hipStream_t)hip_stream));
+    return NOPCS_OK;
+}
+
 int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,
                    size_t ws_bytes, void *hip_stream, int32_t piece_out[3]) {
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;

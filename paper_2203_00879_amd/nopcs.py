@@ -41,6 +41,13 @@ class Params(ctypes.Structure):
                [("viscous", ctypes.c_int32), ("gravity", ctypes.c_int32)]
 
 
+class Box(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("Q", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+
+
+MAX_BATCH = 16
+
+
 class SolverConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                 ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32)]
@@ -91,6 +98,8 @@ def lib():
         L.nopcs_compact_viscous_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.nse_rhs_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V,
                                               ctypes.c_size_t, _V]
+        L.rk_step_batch.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(Box), _I, ctypes.c_double,
+                                    ctypes.c_int32, _V]
         L.rk_step_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, ctypes.c_double,
                                               ctypes.c_int32, _V, ctypes.c_size_t, _V]
         L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
@@ -215,6 +224,19 @@ def nse_rhs_compact_viscous(params, grid, Q, R, ws=None, stream=None):
         ws = torch.empty(nb, dtype=torch.uint8, device=Q.device)
     _check(lib().nse_rhs_compact_viscous(ctypes.byref(params), ctypes.byref(grid), _ptr(Q), _ptr(R), _ptr(ws),
                                          ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def rk_step_batch(params, boxes, dt, nsteps, precision=FP64, stream=None):
+    """rk_step for a batch of boxes [(grid, Q, ws), ...] replayed as one graph
+    with a branch per box."""
+    arr = (Box * len(boxes))()
+    for i, (grid, Q, ws) in enumerate(boxes):
+        arr[i].grid = grid
+        arr[i].Q = Q.data_ptr()
+        arr[i].ws = ws.data_ptr()
+        arr[i].ws_bytes = ws.numel() * ws.element_size()
+    _check(lib().rk_step_batch(ctypes.byref(params), len(boxes), arr, int(precision), float(dt), int(nsteps),
+                               _stream(stream)))
 
 
 def rk_step_compact_viscous(params, grid, Q, dt, nsteps, ws, stream=None):

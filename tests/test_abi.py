@@ -139,3 +139,33 @@ def test_compact_viscous_workspace_and_argument_checks():
     assert b"workspace" in lib.nopcs_last_error()
     assert call(ctypes.byref(p), ctypes.byref(g), V(256), V(512), V(4104), ws, None) == -1
     assert b"aligned" in lib.nopcs_last_error()
+
+
+def test_batch_argument_checks():
+    """rk_step_batch rejects a bad batch before any device work."""
+    from paper_2203_00879_amd import inputs
+    lib = nopcs.lib()
+    p = nopcs.make_params(inputs.AIR)
+    g = nopcs.make_grid(16)
+    ws = nopcs.workspace_bytes(g)
+    arr = (nopcs.Box * 2)()
+    for i in range(2):
+        arr[i].grid = g
+        arr[i].Q = 256 * (i + 1)
+        arr[i].ws = 4096 * (i + 1)
+        arr[i].ws_bytes = ws
+    call = lib.rk_step_batch
+    assert call(ctypes.byref(p), 0, arr, 0, 1e-5, 1, None) == -1
+    assert call(ctypes.byref(p), nopcs.MAX_BATCH + 1, arr, 0, 1e-5, 1, None) == -1
+    assert call(ctypes.byref(p), 2, None, 0, 1e-5, 1, None) == -1
+    assert call(ctypes.byref(p), 2, arr, 7, 1e-5, 1, None) == -1
+    assert call(ctypes.byref(p), 2, arr, 0, -1.0, 1, None) == -1
+    arr[1].Q = 256                                   # same state twice
+    assert call(ctypes.byref(p), 2, arr, 0, 1e-5, 1, None) == -1
+    assert b"share" in lib.nopcs_last_error()
+    arr[1].Q = 520                                   # misaligned state
+    assert call(ctypes.byref(p), 2, arr, 0, 1e-5, 1, None) == -1
+    arr[1].Q = 512
+    arr[1].ws_bytes = ws - 8                         # short workspace
+    assert call(ctypes.byref(p), 2, arr, 0, 1e-5, 1, None) == -1
+    assert b"workspace" in lib.nopcs_last_error()

@@ -1,0 +1,67 @@
+"""GPU: RK4 stepping of a batch of uneven boxes replayed as one graph
+(rk_step_batch) gives every box exactly the result of rk_step on it alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_00879_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs an MI355X GPU", allow_module_level=True)
+
+from paper_2203_00879_amd import nopcs  # noqa: E402
+
+DEV = "cuda:0"
+P = dict(inputs.AIR)
+BOXES = [((32, 32, 32), (1, 1, 1), 0), ((48, 40, 36), (2, 1, 3), 1), ((24, 64, 28), (1, 2, 1), 2),
+         ((80, 20, 72), (2, 1, 2), 3)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(shape, nseg, seed, prec):
+    g = nopcs.make_grid(shape, nseg)
+    Q = torch.from_numpy(inputs.rti_state(shape, seed=seed, noise_K=1e-3)).to(DEV)
+    return g, Q, nopcs.alloc_workspace(g, prec)
+
+
+def lone(shape, nseg, seed, prec, dt, nsteps):
+    g, Q, ws = make(shape, nseg, seed, prec)
+    nopcs.rk_step(nopcs.make_params(P), g, Q, dt, nsteps, ws, precision=prec)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [nopcs.FP64, nopcs.MIXED])
+def test_batch_equals_lone_runs_bitwise_over_replays(prec):
+    """Four uneven boxes, 2 + 1 + 1 steps in three calls (the graph is captured
+    on the first and replayed after), with unrelated eager work in between."""
+    say("batch of", len(BOXES), "precision", prec)
+    dt = 1e-5
+    nopcs.lib().nopcs_set_graphs(0)
+    want = [lone(s, n, seed, prec, dt, 4) for s, n, seed in BOXES]
+    boxes = [make(s, n, seed, prec) for s, n, seed in BOXES]
+    prm = nopcs.make_params(P)
+    junk = torch.ones(1 << 20, dtype=torch.float64, device=DEV)
+    for k in (2, 1, 1):
+        nopcs.rk_step_batch(prm, boxes, dt, k, precision=prec)
+        junk.mul_(1.5).add_(1.0)
+        torch.cuda.synchronize()
+    for (g, Q, ws), w, (shape, _, _) in zip(boxes, want, BOXES):
+        got = Q.cpu().numpy()
+        say("  box", shape, "max diff", float(np.max(np.abs(got - w))))
+        assert np.array_equal(got, w)
+
+
+def test_batch_single_box_equals_rk_step():
+    g, Q, ws = make((40, 36, 44), (2, 3, 2), 7, nopcs.FP64)
+    nopcs.rk_step_batch(nopcs.make_params(P), [(g, Q, ws)], 1e-5, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(Q.cpu().numpy(), lone((40, 36, 44), (2, 3, 2), 7, nopcs.FP64, 1e-5, 3))
