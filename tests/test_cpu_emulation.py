@@ -62,11 +62,11 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("shape, nseg", [((27, 19, 22), (3, 2, 4)), ((16, 17, 20), (4, 4, 5)),
-                                         ((10, 300, 9), (1, 3, 1)), ((9, 8, 600), (1, 1, 4))])
+                                         ((10, 300, 9), (1, 3, 1)), ((9, 8, 520), (1, 1, 4))])
 def test_emulated_derivative_segmented(driver, tmp_path, shape, nseg):
     """Segmented lines, the second case with 4-point segments (Thomas runs of a
     single unknown, whose first row is also its last); the last two take the
-    wide pencils of 300-point y lines (8 per block) and 600-point z lines (4 per
+    wide pencils of 300-point y lines (8 per block) and 520-point z lines (4 per
     block), with a ragged last pencil."""
     f = np.random.default_rng(1).normal(size=shape[::-1])
     fin, fout = tmp_path / "f.raw", tmp_path / "d.raw"
@@ -247,10 +247,10 @@ def test_emulated_rhs_compact_viscous(driver, tmp_path):
 
 def test_emulated_rk_step_compact_viscous(driver, tmp_path):
     """One RK4 step with the D1-based viscous variant (z line march carrying
-    the stage update on an 8 x 12 x 36 box with pieces), against the oracle:
+    the stage update on an 8 x 10 x 24 box with pieces), against the oracle:
     the fields and their change over the step."""
     p = dict(inputs.AIR)
-    shape = (8, 12, 36)
+    shape = (8, 10, 24)
     Q = inputs.rti_state(shape, seed=2, noise_K=1e-3)
     qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
     Q.tofile(qin)
