@@ -13,7 +13,7 @@ namespace {
 
 int pw_blocks(long long N) {
     const long long b = (N + 255) / 256;
-    return (int)(b < 8192 ? b : 8192);
+    return (int)(b < (1 << 30) ? b : (1 << 30));
 }
 
 __global__ void __launch_bounds__(256) k_cv_prims(const double *__restrict__ Q, long long N, long long S, NdConst c,

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kSpecThreads) k_line_spectrum(const double *__
 
 int pointwise_blocks(long long N) {
     const long long b = (N + 255) / 256;
-    return (int)(b < 8192 ? b : 8192);
+    return (int)(b < (1 << 30) ? b : (1 << 30));
 }
 
 }  // namespace
