@@ -191,3 +191,27 @@ def test_pressure_pulses_travel_at_the_local_sound_speed():
     a = amp.cpu().numpy()
     energy = ny * (a[0] ** 2 + 2.0 * np.sum(a[1:-1] ** 2) + a[-1] ** 2)   # even ny
     assert abs(energy / np.sum(lines[-1] ** 2) - 1.0) <= TOL
+
+
+def test_disturbance_pressure_512_sampled_points():
+    """Full size: a smooth 512^3 state against the RTI box it would start from,
+    2000 sampled points (and the eight corners) against the oracle's point-wise
+    formula at those points."""
+    n = 512
+    say("disturbance pressure 512^3")
+    Q = inputs.smooth_state(n, seed=21)
+    Q0 = inputs.rti_state(n, seed=0)
+    g = nopcs.make_grid(n, 4)
+    Qd, Q0d = torch.from_numpy(Q).to(DEV), torch.from_numpy(Q0).to(DEV)
+    out = torch.empty(Q.shape[1:], dtype=torch.float64, device=DEV)
+    nopcs.disturbance_pressure(nopcs.make_params(PARAMS), g, Qd, Q0d, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.integers(0, n ** 3, 2000),
+                          [a + n * (b + n * c) for a in (0, n - 1) for b in (0, n - 1) for c in (0, n - 1)]])
+    got = out.reshape(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    Qs, Q0s = Q.reshape(5, -1)[:, idx][:, None, None, :], Q0.reshape(5, -1)[:, idx][:, None, None, :]
+    want = oracle.disturbance_pressure(PARAMS, Qs, Q0s).reshape(-1)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    say("  sampled err", err)
+    assert err <= TOL
