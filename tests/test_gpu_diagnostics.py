@@ -215,3 +215,25 @@ def test_disturbance_pressure_512_sampled_points():
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
     say("  sampled err", err)
     assert err <= TOL
+
+
+def test_baroclinic_term_dominates_at_the_interface_early_gpu():
+    """Section 5 on the GPU path alone: a 64 x 128 x 64 box of 100 K over 300 K
+    air (h_y = h_x / 2, 2 x 5 x 2 segments) after 100 RK4 steps of the paper's
+    dt; over the two interface planes the baroclinic term's largest amplitude
+    is more than 97 % of the three terms' together."""
+    shape, nseg = (64, 128, 64), (2, 5, 2)
+    dt = 7.69e-8 / (PARAMS["L"] / PARAMS["g"]) ** 0.5
+    say("baroclinic share", shape)
+    g = nopcs.make_grid(shape, nseg)
+    prm = nopcs.make_params(PARAMS)
+    Q = torch.from_numpy(inputs.rti_state(shape, T_upper=100.0, T_lower=300.0, seed=0, noise_K=1e-3)).to(DEV)
+    ws = nopcs.alloc_workspace(g)
+    nopcs.rk_step(prm, g, Q, dt, 100, ws)
+    out = torch.empty((12,) + tuple(Q.shape[1:]), dtype=torch.float64, device=DEV)
+    nopcs.vorticity_budget(prm, g, Q, out)
+    torch.cuda.synchronize()
+    band = slice(shape[1] // 2 - 1, shape[1] // 2 + 1)
+    m = [float(out[k:k + 3][:, :, band, :].abs().max()) for k in (3, 6, 9)]
+    say("  stretching %.3e dilatation %.3e baroclinic %.3e share %.6f" % (m[0], m[1], m[2], m[2] / sum(m)))
+    assert m[2] / sum(m) > 0.97

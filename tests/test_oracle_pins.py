@@ -690,3 +690,19 @@ def test_compact_viscous_stepping_keeps_quiescent_state():
     # at T = rho = 1 the wall conditions also reproduce the stored E' exactly
     Q = inputs.uniform_state((12, 10, 14), T=1.0, rho=1.0, params=p)
     assert np.array_equal(oracle.rk4_compact_viscous(p, Q, 1e-4, 3), Q)
+
+
+def test_baroclinic_term_dominates_at_the_interface_early():
+    """Section 5: at early times the baroclinic term carries more than 97 % of
+    the vorticity production at the interface (by the maximum amplitude of each
+    term).  A 16 x 48 x 16 box of 100 K over 300 K air after 100 steps of the
+    paper's dt: largest |term| over the two interface planes and all
+    components."""
+    p = _params()
+    dt = 7.69e-8 / (p["L"] / p["g"]) ** 0.5
+    shape = (16, 48, 16)
+    Q = oracle.rk4(p, inputs.rti_state(shape, T_upper=100.0, T_lower=300.0, seed=0, noise_K=1e-3, params=p), dt, 100)
+    B = oracle.vorticity_budget(p, Q)
+    band = slice(shape[1] // 2 - 1, shape[1] // 2 + 1)
+    m = [np.max(np.abs(B[k:k + 3][:, :, band, :])) for k in (3, 6, 9)]   # stretching, dilatation, baroclinic
+    assert m[2] / sum(m) > 0.97, m
