@@ -334,6 +334,93 @@ def test_bulk_viscosity_normal_stress():
     assert np.allclose(R[1], (-2 * a * a * x)[None, None, :], rtol=0, atol=1e-10)
 
 
+def test_gravity_source_of_a_uniformly_moving_state():
+    """Source term ge8a: a uniform state in uniform motion has no derivative of
+    any flux, so R is the gravity source alone, S = [0, 0, -rho g, 0, -rho v g]
+    with g L / U_s^2 = 1: gravity pulls the y momentum down and does the work
+    rho g.V = -rho g v on the fluid (positive when it sinks).  The velocity has
+    three different components so that the energy source must pick rho v."""
+    p = _params()
+    shape = (9, 11, 10)
+    rho, vel = 0.83, (0.31, -0.47, 0.19)
+    Q = inputs.uniform_state(shape[::-1], T=1.3, rho=rho, velocity=vel, params=p)
+    R = oracle.rhs(p, Q)
+    expect = [0.0, 0.0, -rho, 0.0, -rho * vel[1]]
+    for c in range(5):
+        assert np.all(R[c] == expect[c]), (c, np.unique(R[c])[:4], expect[c])
+    # the sampled-point evaluation carries its own copy of the source
+    pts = np.array([[0, 0, 0], [4, 5, 3], [9, 10, 8], [1, 10, 2]])
+    Rp = oracle.rhs_points(p, Q, pts)
+    for c in range(5):
+        assert np.all(Rp[c] == expect[c])
+    # without gravity the state is an exact steady solution
+    assert np.all(oracle.rhs(_params(gravity=0), Q) == 0.0)
+
+
+def _fourier_heat_flux_divergence(p, T_dim, h_dim):
+    """Energy right-hand side (non-dimensional) of pure heat conduction along a
+    line of nodes at temperatures T_dim [K], spacing h_dim [m], written from the
+    dimensional Fourier law: q* = -k* dT*/dx* with k* = mu*(T*) c_p / Pr,
+    c_p = gamma R / (gamma - 1) and Sutherland's mu*(T*); the inner gradient and
+    the outer divergence are second-order central differences (Section 4), and
+    the result is scaled by L / (rho_s U_s^3) (ge11, ge20)."""
+    g, R, Pr, L = p["gamma"], p["R_gas"], p["Pr"], p["L"]
+    mu = p["mu_ref"] * (T_dim / p["T_ref"]) ** 1.5 * (p["T_ref"] + p["S_suth"]) / (T_dim + p["S_suth"])
+    k = mu * (g * R / (g - 1.0)) / Pr
+    n = len(T_dim)
+    dT = np.empty(n)
+    dT[1:-1] = (T_dim[2:] - T_dim[:-2]) / (2 * h_dim)
+    dT[0] = (-3 * T_dim[0] + 4 * T_dim[1] - T_dim[2]) / (2 * h_dim)
+    dT[-1] = (3 * T_dim[-1] - 4 * T_dim[-2] + T_dim[-3]) / (2 * h_dim)
+    q = -k * dT
+    div = np.full(n, np.nan)
+    div[1:-1] = (q[2:] - q[:-2]) / (2 * h_dim)
+    Us = math.sqrt(p["g"] * L)
+    return -div * L / (p["rho_s"] * Us ** 3)
+
+
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_heat_conduction_follows_the_dimensional_fourier_law(direction):
+    """ge20 and ge11: a resting gas with a linear temperature profile at uniform
+    pressure (gravity off) has no convective or stress term; its energy RHS is
+    the divergence of the Fourier heat flux.  The oracle's non-dimensional
+    factor 1/((gamma - 1) Pr Re M^2) and mu(T) must reproduce the flux written
+    in SI units from k* = mu* c_p / Pr."""
+    p = _params(gravity=0)
+    n = 13
+    shape = [6, 7, 8]
+    shape[2 - direction] = n
+    Rh = inputs.rh_of(p)
+    s = np.linspace(0.0, 1.0, n)
+    T_nd = 1.0 + 0.6 * s                                 # 300 K .. 480 K across the box
+    pp = 0.35                                            # uniform p' (non-dimensional)
+    rho_line = (pp + Rh) / (Rh * T_nd)                   # p = rho Rh T
+    bshape = [1, 1, 1]
+    bshape[2 - direction] = n
+    Q = np.zeros([5] + shape)
+    Q[0] = rho_line.reshape(bshape)
+    Q[4] = pp / (p["gamma"] - 1.0)                       # E' = p' / (gamma - 1) at rest
+    R = oracle.rhs(p, Q)
+    expect = _fourier_heat_flux_divergence(p, T_nd * p["T_s"], p["L"] / (n - 1))
+    line = [2, 3, 4]
+    line[2 - direction] = slice(None)
+    got = R[4][tuple(line)]
+    inner = slice(1, n - 1)
+    scale = np.max(np.abs(expect[inner]))
+    assert scale > 0
+    assert np.max(np.abs(got[inner] - expect[inner])) <= 1e-11 * scale
+    # nothing else moves: mass and momentum RHS vanish (p' uniform, no velocity)
+    assert np.max(np.abs(R[:4])) <= 1e-12 * scale
+    # the sampled-point evaluation agrees
+    pts = []
+    for i in range(1, n - 1):
+        ijk = [4, 3, 2]
+        ijk[direction] = i
+        pts.append(ijk)
+    Rp = oracle.rhs_points(p, Q, np.array(pts))
+    assert np.max(np.abs(Rp[4] - expect[inner])) <= 1e-11 * scale
+
+
 def test_hydrostatic_column_balance_converges():
     """Isothermal hydrostatic column: dp/dy + rho -> 0 at second order."""
     res = []
