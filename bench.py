@@ -9,8 +9,14 @@ direction, dt = 1e-6.
 
 Prints ONE JSON line:
   metric/value/unit : Mpoint-stage updates/s (points x 4 stages x steps / s / 1e6)
-  roofline          : dominant kernel, algorithmic bytes per launch / its mean
-                      duration (HIP events on its stream, over the timed region)
+  roofline          : dominant kernel: the method's algorithmic bytes of the stage
+                      it completes (170 B per point-stage in FP64: three 5-field
+                      RK4 registers) / its mean launch time (HIP events on its
+                      stream, over the timed region); its own compulsory bytes
+                      under roofline.kernel_compulsory
+  step_counter_frac : counter-measured HBM bytes of the timed region / its time
+  mixed             : a short pass of the same box in mixed precision
+  serving           : p50/p99 latency of a small Poisson stream of RTI boxes
   cpu_baseline      : the FP64 oracle timed on the host cores on a bounded sample
 """
 import argparse
@@ -111,6 +117,32 @@ def cpu_baseline(n=128, steps=1):
             "sample": "RTI box %d^3, %d RK4 step(s) (%d stages), FP64 oracle, %.1f s" % (n, steps, 4 * steps, dt)}
 
 
+def time_steps(nopcs, lib, params, grid, Q, ws, dt, steps, warmup, prec, stream):
+    """warmup untimed steps, then `steps` timed ones (HIP events on the launch
+    stream around the whole region, per-kernel events from the library)."""
+    import ctypes
+    import torch
+    nopcs.rk_step(params, grid, Q, dt, warmup, ws, precision=prec)
+    torch.cuda.synchronize()
+    lib.nopcs_timing_enable(1)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    nopcs.rk_step(params, grid, Q, dt, steps, ws, precision=prec)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.nopcs_timing_enable(0)
+    per = {}
+    for k, name in enumerate(KERNEL_NAMES):
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        nopcs._check(lib.nopcs_timing_read(k, ctypes.byref(tot), ctypes.byref(cnt)))
+        if cnt.value:
+            per[name] = (tot.value, cnt.value)
+    return start.elapsed_time(stop), per, wall
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +153,9 @@ def main():
     ap.add_argument("--dt", type=float, default=1e-6)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the short mixed-precision pass")
+    ap.add_argument("--no-serving", action="store_true", help="skip the small serving sample")
+    ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--cpu-n", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
@@ -132,7 +167,8 @@ def main():
               "--gpus %d is not supported." % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import ctypes
+
     import torch
 
     from paper_2203_00879_amd import inputs, nopcs
@@ -151,39 +187,18 @@ def main():
     params = nopcs.make_params(p)
     Q0 = inputs.rti_state(n, seed=0)
     Q = torch.from_numpy(Q0).to(dev)
-    del Q0
     prec = nopcs.MIXED if args.precision == "mixed" else nopcs.FP64
     ws = nopcs.alloc_workspace(grid, prec)
     stream = torch.cuda.current_stream()
     lib = nopcs.lib()
-
-    nopcs.rk_step(params, grid, Q, args.dt, args.warmup, ws, precision=prec)
-    torch.cuda.synchronize()
-
-    import ctypes
     lib.nopcs_timing_enable.argtypes = [ctypes.c_int]
     lib.nopcs_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]
-    lib.nopcs_timing_enable(1)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    nopcs.rk_step(params, grid, Q, args.dt, args.steps, ws, precision=prec)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lib.nopcs_timing_enable(0)
-    ms = start.elapsed_time(stop)
-    sec = ms / 1e3
 
-    per = {}
-    for k, name in enumerate(KERNEL_NAMES):
-        tot, cnt = ctypes.c_double(), ctypes.c_int64()
-        nopcs._check(lib.nopcs_timing_read(k, ctypes.byref(tot), ctypes.byref(cnt)))
-        if cnt.value:
-            per[name] = (tot.value, cnt.value)
+    ms, per, wall = time_steps(nopcs, lib, params, grid, Q, ws, args.dt, args.steps, args.warmup, prec, stream)
+    sec = ms / 1e3
     finite = bool(torch.isfinite(Q).all().item())
+    del ws
 
     N3 = n ** 3
     pstage = N3 * 4 * args.steps
@@ -194,17 +209,27 @@ def main():
     dom = max((k for k in per if k in KERNEL_SOURCES and bpp(k) > 0), key=lambda k: per[k][0])
     tot_ms, cnt = per[dom]
     avg_s = tot_ms / cnt / 1e3
+    # the method's algorithmic bytes per point-stage: three 5-field RK4 registers
+    # (FP64 170 B; mixed precision with the stage state in FP32, 125 B)
+    alg_pps = 170.0 if pr == "fp64" else 125.0
+    achieved = alg_pps * N3 / avg_s / 1e9
     bpl = bpp(dom) * N3
-    achieved = bpl / avg_s / 1e9
     workload_key = "rti_%d_fp64_seg%d" % (n, args.nseg)
-    traffic = load_traffic(dom, workload_key)
+    traffic = load_traffic(dom, workload_key) if pr == "fp64" else None
     flop = load_counter_record(dom, workload_key, "fp64_flop_per_launch") if pr == "fp64" else None
+    # counter bytes of the whole timed region (per-kernel counter runs x launches)
+    step_bytes = 0.0
+    for k, (t, c) in per.items():
+        tb = load_traffic(k, workload_key) if pr == "fp64" else None
+        if tb is None and k != "wall":
+            step_bytes = None
+            break
+        step_bytes += (tb or 0.0) * c
     kernels = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1],
                    "alg_GBps": (bpp(k) * N3 / (v[0] / v[1] / 1e3) / 1e9) if bpp(k) else None}
                for k, v in per.items()}
     out = {
-        "metric": "Mpoint-stage updates/s (512^3 FP64 RK4 stepping)" if pr == "fp64" else
-                  "Mpoint-stage updates/s (512^3 mixed-precision RK4 stepping)",
+        "metric": "Mpoint-stage updates/s at 512\u00b3 FP64 vs mixed; p50/p99 batched solve latency",
         "value": value,
         "unit": "Mpoint-stage/s",
         "n_gpus": 1,
@@ -220,10 +245,20 @@ def main():
                                "interface noise" % (n, "FP64" if pr == "fp64" else "mixed precision", args.nseg, args.dt),
                    "points": N3, "segments_per_direction": args.nseg, "precision": pr},
         "rk_update_fused_into_sweep_z": fused,
+        # dominant kernel: the method's algorithmic bytes of the stage it completes
+        # (alg_pps per point-stage x points) over its mean launch time
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": bpl, "mean_launch_ms": avg_s * 1e3},
-        "step_algorithmic_frac": 170.0 * pstage / sec / 1e9 / HBM_PEAK_GBS,
+                     "alg_bytes_per_launch": alg_pps * N3, "alg_bytes_per_point_stage": alg_pps,
+                     "mean_launch_ms": avg_s * 1e3,
+                     # the kernel's own compulsory bytes (every operand it reads or writes once)
+                     "kernel_compulsory": {"bytes_per_launch": bpl, "achieved": bpl / avg_s / 1e9,
+                                           "frac": bpl / avg_s / 1e9 / HBM_PEAK_GBS}},
+        "step_algorithmic_frac": alg_pps * pstage / sec / 1e9 / HBM_PEAK_GBS,
+        # counter-measured HBM bytes of every launch in the timed region over its
+        # time (null when a kernel's counters were taken on other sources)
+        "step_counter_frac": None if step_bytes is None else step_bytes / sec / 1e9 / HBM_PEAK_GBS,
+        "step_counter_bytes_per_point_stage": None if step_bytes is None else step_bytes / pstage,
         # FP64 VALU rate of the dominant kernel: counter-measured FP64 flops per
         # launch (64 lanes x (add + mul + trans + 2 fma) instructions) / its mean
         # launch time, against the FP64 vector peak (null if the counters were
@@ -237,9 +272,28 @@ def main():
         "paper_context": {"Mpoint_stage_per_s": 19700.0,
                           "hardware": "19,200 Haswell cores, 4.19e9 points, FP64 (paper, other machine)"},
     }
+    if pr == "fp64" and not args.no_mixed:
+        # the metric's other precision: a short mixed-precision pass on the same box
+        Q.copy_(torch.from_numpy(Q0))
+        wsm = nopcs.alloc_workspace(grid, nopcs.MIXED)
+        msm, _, _ = time_steps(nopcs, lib, params, grid, Q, wsm, args.dt, args.mixed_steps, 1, nopcs.MIXED, stream)
+        del wsm
+        out["mixed"] = {"steps": args.mixed_steps, "ms_per_step": msm / args.mixed_steps,
+                        "Mpoint_stage_per_s": N3 * 4 * args.mixed_steps / (msm / 1e3) / 1e6,
+                        "speedup_vs_fp64": (ms / args.steps) / (msm / args.mixed_steps),
+                        "finite": bool(torch.isfinite(Q).all().item())}
+    del Q
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        # the metric's latency part: a small Poisson stream of RTI boxes through the
+        # serving runtime, mixed precision, at an arrival rate the GPU sustains
+        from paper_2203_00879_amd import serve_bench
+        sv = serve_bench.run(n_req=24, step_scale=0.1, slots=8, budget_gb=60.0, precision="mixed",
+                             mean_gap_s=0.1)
+        out["serving"] = {k: sv[k] for k in ("requests", "all_ok", "Mpoint_stage_per_s", "p50_latency_s",
+                                             "p99_latency_s", "p50_admission_s", "p99_admission_s",
+                                             "offered_Mpoint_stage_per_s", "mean_gap_s", "step_scale", "precision")}
     if not args.no_cpu_baseline:
-        del ws
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

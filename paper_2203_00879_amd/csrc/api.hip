@@ -305,6 +305,7 @@ namespace {
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;   // recorded after the entry's latest replay
 };
 std::mutex g_gmu;
 std::map<std::string, GraphEntry> g_graph_cache;
@@ -316,11 +317,54 @@ void put_bytes(std::string &k, const T &v) {
     k.append(reinterpret_cast<const char *>(&v), sizeof v);
 }
 
+// Destroy an entry once its replays have run (the executable may still be
+// queued on a caller's stream).
 void drop_graph(GraphEntry &e) {
+    if (e.done) {
+        (void)hipEventSynchronize(e.done);
+        (void)hipEventDestroy(e.done);
+    }
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
     if (e.graph) (void)hipGraphDestroy(e.graph);
     e.exec = nullptr;
     e.graph = nullptr;
+    e.done = nullptr;
+}
+
+// Replay a cached executable nsteps times on st and record its completion
+// event; the caller holds g_gmu, so no other thread can evict the entry
+// between the lookup and the launches.
+int replay(GraphEntry &e, int nsteps, hipStream_t st) {
+    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(e.exec, st));
+    NOPCS_HIP_CHECK(hipEventRecord(e.done, st));
+    return NOPCS_OK;
+}
+
+// Make room for one more entry: the oldest goes (after its replays have run).
+void evict_if_full() {
+    if (g_graph_cache.size() >= kMaxGraphs) {
+        drop_graph(g_graph_cache.begin()->second);
+        g_graph_cache.erase(g_graph_cache.begin());
+    }
+}
+
+// Instantiate a captured graph into an entry with its completion event.
+int instantiate(GraphEntry &e) {
+    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(e.graph);
+        e.graph = nullptr;
+        set_error("hipGraphInstantiate failed");
+        return NOPCS_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+        e.exec = nullptr;
+        e.graph = nullptr;
+        set_error("hipEventCreateWithFlags failed");
+        return NOPCS_EDEVICE;
+    }
+    return NOPCS_OK;
 }
 }  // namespace
 
@@ -331,7 +375,7 @@ static void release_graphs() {
 }
 
 static int step_graph(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
-                      const LinePlanDev pl[3], hipGraphExec_t *out) {
+                      const LinePlanDev pl[3], int nsteps, hipStream_t st) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
     std::string key;
@@ -345,14 +389,8 @@ static int step_graph(const nse_params &params, const nopcs_grid *grid, int prec
     for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, grid->n[d]));
     std::lock_guard<std::mutex> lk(g_gmu);
     auto it = g_graph_cache.find(key);
-    if (it != g_graph_cache.end()) {
-        *out = it->second.exec;
-        return NOPCS_OK;
-    }
-    if (g_graph_cache.size() >= kMaxGraphs) {
-        drop_graph(g_graph_cache.begin()->second);
-        g_graph_cache.erase(g_graph_cache.begin());
-    }
+    if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
+    evict_if_full();
     hipStream_t &cs = g_capture_stream[dev];
     if (!cs) NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     GraphEntry e;
@@ -366,14 +404,9 @@ static int step_graph(const nse_params &params, const nopcs_grid *grid, int prec
         return rc;
     }
     NOPCS_HIP_CHECK(ec);
-    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(e.graph);
-        set_error("hipGraphInstantiate failed");
-        return NOPCS_EDEVICE;
-    }
-    g_graph_cache[key] = e;
-    *out = e.exec;
-    return NOPCS_OK;
+    const int ri = instantiate(e);
+    if (ri != NOPCS_OK) return ri;
+    return replay(g_graph_cache[key] = e, nsteps, st);
 }
 
 extern "C" {
@@ -598,11 +631,7 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
         }
         return NOPCS_OK;
     }
-    hipGraphExec_t exec = nullptr;
-    rc = step_graph(*params, grid, precision, Q, dt, ws, pl, &exec);
-    if (rc != NOPCS_OK) return rc;
-    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(exec, st));
-    return NOPCS_OK;
+    return step_graph(*params, grid, precision, Q, dt, ws, pl, nsteps, st);
 }
 
 int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, double *Q, double dt, int32_t nsteps,
@@ -633,7 +662,7 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
 // own branch (a private stream forked from the capture stream and joined back),
 // so one replay runs all boxes and the device overlaps the branches.
 static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
-                       const LinePlanDev (*pl)[3], hipGraphExec_t *out) {
+                       const LinePlanDev (*pl)[3], int nsteps, hipStream_t st) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
     std::string key = "batch";
@@ -649,14 +678,8 @@ static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxe
     }
     std::lock_guard<std::mutex> lk(g_gmu);
     auto it = g_graph_cache.find(key);
-    if (it != g_graph_cache.end()) {
-        *out = it->second.exec;
-        return NOPCS_OK;
-    }
-    if (g_graph_cache.size() >= kMaxGraphs) {
-        drop_graph(g_graph_cache.begin()->second);
-        g_graph_cache.erase(g_graph_cache.begin());
-    }
+    if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
+    evict_if_full();
     hipStream_t &cs = g_capture_stream[dev];
     if (!cs) NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     // branch streams and fork/join events of this device, kept for the process
@@ -695,14 +718,9 @@ static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxe
         set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he != hipSuccess ? he : ec));
         return NOPCS_EDEVICE;
     }
-    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(e.graph);
-        set_error("hipGraphInstantiate failed");
-        return NOPCS_EDEVICE;
-    }
-    g_graph_cache[key] = e;
-    *out = e.exec;
-    return NOPCS_OK;
+    const int ri = instantiate(e);
+    if (ri != NOPCS_OK) return ri;
+    return replay(g_graph_cache[key] = e, nsteps, st);
 }
 
 int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes, int precision, double dt,
@@ -737,11 +755,7 @@ int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes
         if (rc != NOPCS_OK) return rc;
     }
     if (nsteps == 0) return NOPCS_OK;
-    hipGraphExec_t exec = nullptr;
-    const int rc = batch_graph(*params, nbox, boxes, precision, dt, pl, &exec);
-    if (rc != NOPCS_OK) return rc;
-    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(exec, (hipStream_t)hip_stream));
-    return NOPCS_OK;
+    return batch_graph(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream);
 }
 
 int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
 #pragma unroll
         for (int t = MRL - 1; t >= 0; --t) {
             const int k = t + 1;
-            const TC xs = k == m ? d[t] : fma_(-cp[k], xn, d[t]);
+            const TC xs = k == m ? d[t] : fma_(-cp[min(k, m)], xn, d[t]);   // k > m: unused, read in range
             d[t] = t < m ? xs : TC(0);
             xn = d[t];
         }
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
 #pragma unroll
         for (int t = MRL - 1; t >= 0; --t) {
             const int k = t + 1;
-            const TC xs = k == m ? d[t] : fma_(-cp[k], xn, d[t]);
+            const TC xs = k == m ? d[t] : fma_(-cp[min(k, m)], xn, d[t]);   // k > m: unused, read in range
             const TC xk = t < m ? xs : TC(0);
             xn = xk;
             const TR nv = ring[t % RA] - TR(xk);

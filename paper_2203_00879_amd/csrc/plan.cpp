@@ -269,7 +269,7 @@ void build_march_tables(LinePlanHost &P) {
 // ---------------------------------------------------------------------------
 namespace {
 struct PlanEntry {
-    void *buf = nullptr;
+    std::vector<void *> bufs;   // one buffer (tables packed), or one per table in the CPU build
     LinePlanDev dev{};
 };
 std::mutex g_mu;
@@ -351,6 +351,35 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     cpy(o_k1w, P.k1_w.data(), sizeof(double) * P.k1_w.size());
     cpy(o_evr, P.k1_evrow.data(), sizeof(int) * P.k1_evrow.size());
     cpy(o_evm, P.k1_evmask.data(), sizeof(int) * P.k1_evmask.size());
+    // each table's offset in the blob and the bytes the kernels may read
+    const size_t tab_off[] = {o_runs, o_rslot, o_kslot, o_row, o_j0, o_len, o_coefA, o_den, o_cp, o_d32, o_c32b,
+                              o_grp, o_own, o_rec, o_wsum, o_k1w, o_evr, o_evm};
+    const size_t tab_len[] = {sizeof(int2) * nrun, sizeof(int2) * nrun, sizeof(short) * n, sizeof(int) * ncl,
+                              sizeof(int) * ncl, sizeof(int) * ncl, sizeof(double) * coefA.size(),
+                              sizeof(double) * (n + 1), sizeof(double) * (n + 1), sizeof(float) * (n + 1),
+                              sizeof(float) * (n + 1), sizeof(int2) * ngrp, sizeof(int) * nrun,
+                              sizeof(int) * P.k1_rec.size(), sizeof(double) * ncl, sizeof(double) * P.k1_w.size(),
+                              sizeof(int) * P.k1_evrow.size(), sizeof(int) * P.k1_evmask.size()};
+    constexpr int ntab = sizeof(tab_off) / sizeof(tab_off[0]);
+    static_assert(ntab == sizeof(tab_len) / sizeof(tab_len[0]), "one length per table");
+    std::vector<void *> bufs;
+    unsigned char *tab[ntab];
+#ifdef NOPCS_CPU_EMUL
+    // CPU build of the kernels: every table in a guarded allocation of its own,
+    // sized exactly, so that a read past the end of any one table faults
+    for (int t = 0; t < ntab; ++t) {
+        void *b1 = nullptr;
+        if (hipMalloc(&b1, tab_len[t]) != hipSuccess) {
+            for (void *b : bufs) (void)hipFree(b);
+            set_error("hipMalloc of a line plan failed");
+            return NOPCS_ENOMEM;
+        }
+        bufs.push_back(b1);
+        std::memcpy(b1, host.data() + tab_off[t], tab_len[t]);
+        tab[t] = static_cast<unsigned char *>(b1);
+    }
+#else
+    // one device buffer holds every table
     void *buf = nullptr;
     if (hipMalloc(&buf, off) != hipSuccess) {
         set_error("hipMalloc of a line plan failed");
@@ -361,36 +390,38 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
         set_error("hipMemcpy of a line plan failed");
         return NOPCS_EDEVICE;
     }
-    auto *b = static_cast<unsigned char *>(buf);
+    bufs.push_back(buf);
+    for (int t = 0; t < ntab; ++t) tab[t] = static_cast<unsigned char *>(buf) + tab_off[t];
+#endif
     LinePlanDev d;
     d.n = n;
     d.nrun = nrun;
     d.ncl = ncl;
     d.ih = (double)(n - 1) / len;
-    d.runs = reinterpret_cast<const int2 *>(b + o_runs);
-    d.run_slot = reinterpret_cast<const int2 *>(b + o_rslot);
-    d.kslot = reinterpret_cast<const short *>(b + o_kslot);
-    d.cl_row = reinterpret_cast<const int *>(b + o_row);
-    d.cl_j0 = reinterpret_cast<const int *>(b + o_j0);
-    d.cl_len = reinterpret_cast<const int *>(b + o_len);
-    d.rden = reinterpret_cast<const double *>(b + o_den);
-    d.cp = reinterpret_cast<const double *>(b + o_cp);
-    d.rden32 = reinterpret_cast<const float *>(b + o_d32);
-    d.cl_coefA = reinterpret_cast<const double *>(b + o_coefA);
-    d.cp32 = reinterpret_cast<const float *>(b + o_c32b);
+    d.runs = reinterpret_cast<const int2 *>(tab[0]);
+    d.run_slot = reinterpret_cast<const int2 *>(tab[1]);
+    d.kslot = reinterpret_cast<const short *>(tab[2]);
+    d.cl_row = reinterpret_cast<const int *>(tab[3]);
+    d.cl_j0 = reinterpret_cast<const int *>(tab[4]);
+    d.cl_len = reinterpret_cast<const int *>(tab[5]);
+    d.cl_coefA = reinterpret_cast<const double *>(tab[6]);
+    d.rden = reinterpret_cast<const double *>(tab[7]);
+    d.cp = reinterpret_cast<const double *>(tab[8]);
+    d.rden32 = reinterpret_cast<const float *>(tab[9]);
+    d.cp32 = reinterpret_cast<const float *>(tab[10]);
     d.max_m = P.max_m;
     d.ngrp = ngrp;
     d.k1_S = P.k1_S;
-    d.grp = reinterpret_cast<const int2 *>(b + o_grp);
-    d.run_own = reinterpret_cast<const int *>(b + o_own);
-    d.k1_rec = reinterpret_cast<const int *>(b + o_rec);
-    d.cl_wsum = reinterpret_cast<const double *>(b + o_wsum);
-    d.k1_w = reinterpret_cast<const double *>(b + o_k1w);
+    d.grp = reinterpret_cast<const int2 *>(tab[11]);
+    d.run_own = reinterpret_cast<const int *>(tab[12]);
+    d.k1_rec = reinterpret_cast<const int *>(tab[13]);
+    d.cl_wsum = reinterpret_cast<const double *>(tab[14]);
+    d.k1_w = reinterpret_cast<const double *>(tab[15]);
     d.k1_nev = (int)P.k1_evrow.size();
-    d.k1_evrow = reinterpret_cast<const int *>(b + o_evr);
-    d.k1_evmask = reinterpret_cast<const int *>(b + o_evm);
+    d.k1_evrow = reinterpret_cast<const int *>(tab[16]);
+    d.k1_evmask = reinterpret_cast<const int *>(tab[17]);
     PlanEntry e;
-    e.buf = buf;
+    e.bufs = bufs;
     e.dev = d;
     g_plans[key] = e;
     *out = d;
@@ -403,7 +434,7 @@ void release_line_plans() {
     std::lock_guard<std::mutex> lock(g_mu);
     for (auto it = g_plans.begin(); it != g_plans.end();) {
         if (std::get<0>(it->first) == dev) {
-            (void)hipFree(it->second.buf);
+            for (void *b : it->second.bufs) (void)hipFree(b);
             it = g_plans.erase(it);
         } else {
             ++it;

@@ -49,11 +49,12 @@ def request_state(w, seed):
     return inputs.rti_state(w["n"], T_upper=300.0, T_lower=300.0 + w["dT"], seed=seed)
 
 
-def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False, precision="mixed"):
+def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False, precision="mixed",
+        mean_gap_s=0.05):
     import torch
     prec = nopcs.MIXED if precision == "mixed" else nopcs.FP64
     params = nopcs.make_params(inputs.AIR)
-    W = workload(n_req, step_scale=step_scale)
+    W = workload(n_req, mean_gap_s=mean_gap_s, step_scale=step_scale)
     states = [request_state(w, i) for i, w in enumerate(W)]
     grids = [nopcs.make_grid(w["n"], w["nseg"]) for w in W]
     dts = [inputs.stable_dt(w["n"], 300.0 + w["dT"]) for w in W]
@@ -95,7 +96,8 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
         "p50_admission_s": float(np.percentile(adm, 50)), "p99_admission_s": float(np.percentile(adm, 99)),
         "wall_s": wall, "offered_point_stages": pst, "step_scale": step_scale,
-        "arrival_span_s": W[-1]["t"],
+        "arrival_span_s": W[-1]["t"], "mean_gap_s": mean_gap_s,
+        "offered_Mpoint_stage_per_s": pst / W[-1]["t"] / 1e6 if W[-1]["t"] > 0 else None,
     }
     if check:
         # the first `check` requests again, each alone through rk_step: bitwise equal?
@@ -120,8 +122,10 @@ def main():
     ap.add_argument("--check", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
+    ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time in seconds")
     a = ap.parse_args()
-    print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose, a.precision)), flush=True)
+    print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose, a.precision,
+                         a.mean_gap)), flush=True)
 
 
 if __name__ == "__main__":

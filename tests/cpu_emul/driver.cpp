@@ -20,6 +20,40 @@
 #include "../../paper_2203_00879_amd/csrc/plan.hpp"
 #include "hip/hip_runtime.h"
 
+// Context switch of the emulated device threads (x86-64 System V): saves the
+// callee-saved registers, MXCSR and the x87 control word on the current stack,
+// stores the stack pointer in *save_sp and resumes the context saved at new_sp.
+asm(R"(
+    .text
+    .globl emu_ctx_switch
+    .type emu_ctx_switch, @function
+emu_ctx_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    subq $8, %rsp
+    stmxcsr (%rsp)
+    fnstcw 4(%rsp)
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    ldmxcsr (%rsp)
+    fldcw 4(%rsp)
+    addq $8, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+    .size emu_ctx_switch, .-emu_ctx_switch
+    .section .note.GNU-stack,"",@progbits
+    .text
+)");
+
 // device-like buffers: guarded on both sides
 struct Buf {
     double *p;

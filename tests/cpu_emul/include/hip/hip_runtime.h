@@ -1,19 +1,17 @@
 // CPU stand-in for the subset of the HIP runtime that libnopcs uses, so the
 // library's kernels can be compiled with g++ and AddressSanitizer and run on
-// the host: every block runs as blockDim threads that meet at a std::barrier
-// for __syncthreads; __shared__ arrays become function statics (one block runs
-// at a time); device memory is host memory.  Test infrastructure only.
+// the host: every block runs as blockDim fibers that meet at __syncthreads;
+// __shared__ arrays become function statics (one block runs at a time);
+// device memory is host memory.  Test infrastructure only.
 #pragma once
 #include <algorithm>
-#include <barrier>
 #include <chrono>
-#include <condition_variable>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
-#include <thread>
 #include <vector>
 #include <sys/mman.h>
 #include <unistd.h>
@@ -38,8 +36,11 @@ inline void *emu_guarded_alloc(size_t n) {
     if (base == MAP_FAILED) return nullptr;
     mprotect(base, guard, PROT_NONE);
     mprotect(base + guard + body, guard, PROT_NONE);
-    // end of the buffer flush with the trailing guard, start kept 256-byte aligned
-    char *p = base + guard + body - ((n + 255) & ~(size_t)255);
+    // end of the buffer flush with the trailing guard: a read one byte past the
+    // end faults.  The start then has the alignment of n within the page (a
+    // state of an even number of points is 16-byte aligned, a workspace sized
+    // in 256-byte units 256-byte aligned; the library rejects anything less).
+    char *p = base + guard + body - n;
     std::lock_guard<std::mutex> lk(emu_alloc_mu());
     emu_allocs()[p] = {base, total};
     return p;
@@ -82,10 +83,12 @@ struct alignas(8) float2 {
     float x, y;
 };
 
-inline thread_local dim3 threadIdx, blockIdx;
-inline dim3 gridDim, blockDim;   // written by every pool thread of a launch with the same value
-inline thread_local std::barrier<> *emu_bar = nullptr;
-inline void __syncthreads() { emu_bar->arrive_and_wait(); }
+// Device threads are fibers on the launching host thread (see emu_launch):
+// the scheduler sets these before it resumes a fiber.
+inline dim3 threadIdx, blockIdx;
+inline dim3 gridDim, blockDim;
+inline void emu_barrier();
+inline void __syncthreads() { emu_barrier(); }
 
 // Lane exchange inside a 64-wide wavefront: every thread of the block must call
 // it the same number of times (as every lane of a wavefront does on the GPU).
@@ -93,10 +96,10 @@ inline double emu_shfl_buf[1024];
 inline double __shfl_xor(double v, int mask, int width = 64) {
     const unsigned t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
     emu_shfl_buf[t] = v;
-    emu_bar->arrive_and_wait();
+    emu_barrier();
     const unsigned lane = t % (unsigned)width, src = t - lane + ((lane ^ (unsigned)mask) % (unsigned)width);
     const double r = emu_shfl_buf[src];
-    emu_bar->arrive_and_wait();
+    emu_barrier();
     return r;
 }
 
@@ -149,70 +152,137 @@ inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
     return hipSuccess;
 }
 
-// A pool of host threads that play the device threads of one block at a time;
-// created once and reused by every launch (launches from several host threads
-// are serialised).
-struct EmuPool {
-    std::mutex mu, launch_mu;
-    std::condition_variable cv, cv_done;
-    std::vector<std::thread> th;
-    std::function<void(unsigned)> job;
-    unsigned job_nt = 0, active = 0;
-    unsigned long long gen = 0;
-    void loop(unsigned id) {
-        unsigned long long seen = 0;
-        for (;;) {
-            std::function<void(unsigned)> f;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] { return gen != seen; });
-                seen = gen;
-                if (id >= job_nt) continue;
-                f = job;
-            }
-            f(id);
-            std::lock_guard<std::mutex> lk(mu);
-            if (--active == 0) cv_done.notify_all();
-        }
+// Device threads as fibers.  A launch runs its blocks one after the other on
+// the calling host thread; the threads of a block are fibers (own stacks,
+// switched by emu_ctx_switch, defined in driver.cpp) that a scheduler resumes
+// in turn.  __syncthreads() switches back to the scheduler, which resumes a
+// fiber again only after every live fiber of the block has reached the
+// barrier, so block-wide barriers keep their meaning.  Launches from several
+// host threads are serialised (the fibers' globals belong to one launch).
+extern "C" void emu_ctx_switch(void **save_sp, void *new_sp);
+#if defined(__SANITIZE_ADDRESS__)
+extern "C" void __sanitizer_start_switch_fiber(void **fake_stack_save, const void *bottom, size_t size);
+extern "C" void __sanitizer_finish_switch_fiber(void *fake_stack_save, const void **bottom_old, size_t *size_old);
+extern "C" void __asan_unpoison_memory_region(void const volatile *addr, size_t size);
+#endif
+
+struct EmuFiber {
+    void *sp = nullptr;
+    char *stack = nullptr;
+    bool done = false;
+    unsigned long nbar = 0;   // barriers reached
+};
+struct EmuSched {
+    static constexpr size_t kStack = (size_t)512 << 10;
+    std::mutex launch_mu;
+    std::vector<EmuFiber> fib;
+    void *sched_sp = nullptr;
+    unsigned cur = 0;
+    dim3 block;
+    std::function<void()> body;
+    const void *sched_bottom = nullptr;   // the scheduler's own stack (for the sanitizer)
+    size_t sched_size = 0;
+    // switch from the running fiber to the scheduler; dying: the fiber never returns
+    void to_sched(bool dying) {
+#if defined(__SANITIZE_ADDRESS__)
+        void *fake = nullptr;
+        __sanitizer_start_switch_fiber(dying ? nullptr : &fake, sched_bottom, sched_size);
+        emu_ctx_switch(&fib[cur].sp, sched_sp);
+        __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#else
+        (void)dying;
+        emu_ctx_switch(&fib[cur].sp, sched_sp);
+#endif
     }
-    void run(unsigned nt, std::function<void(unsigned)> f) {
-        std::lock_guard<std::mutex> serial(launch_mu);
-        std::unique_lock<std::mutex> lk(mu);
-        while (th.size() < nt) {
-            const unsigned id = (unsigned)th.size();
-            th.emplace_back([this, id] { loop(id); });
-            th.back().detach();
+    // switch from the scheduler to fiber t
+    void to_fiber(unsigned t) {
+        cur = t;
+        threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+#if defined(__SANITIZE_ADDRESS__)
+        void *fake = nullptr;
+        __sanitizer_start_switch_fiber(&fake, fib[t].stack, kStack);
+        emu_ctx_switch(&sched_sp, fib[t].sp);
+        __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#else
+        emu_ctx_switch(&sched_sp, fib[t].sp);
+#endif
+    }
+    static void entry();
+    // a fresh frame at the top of fiber t's stack that emu_ctx_switch "returns" into entry()
+    void reset(unsigned t) {
+        EmuFiber &f = fib[t];
+        if (!f.stack) {
+            f.stack = (char *)mmap(nullptr, kStack, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+            if (f.stack == (char *)MAP_FAILED) std::abort();
+            mprotect(f.stack, (size_t)sysconf(_SC_PAGESIZE), PROT_NONE);   // overflow guard
         }
-        job = std::move(f);
-        job_nt = nt;
-        active = nt;
-        ++gen;
-        cv.notify_all();
-        cv_done.wait(lk, [&] { return active == 0; });
+#if defined(__SANITIZE_ADDRESS__)
+        __asan_unpoison_memory_region(f.stack, kStack);
+#endif
+        uint64_t *top = (uint64_t *)(f.stack + kStack);   // 16-byte aligned
+        top[-1] = 0;                                        // entry() never returns
+        top[-2] = (uint64_t)(uintptr_t)&EmuSched::entry;    // popped by ret
+        for (int r = 3; r <= 8; ++r) top[-r] = 0;           // rbp, rbx, r12-r15
+        top[-9] = 0x037F00001F80ull;                        // MXCSR (low), x87 control word
+        f.sp = top - 9;
+        f.done = false;
+        f.nbar = 0;
+    }
+    void run_block(unsigned nt) {
+        for (unsigned t = 0; t < nt; ++t) reset(t);
+        // rounds: every live fiber runs up to its next barrier (or its end);
+        // the fibers still alive after a round must all wait at the same barrier
+        for (unsigned long round = 1;; ++round) {
+            bool any = false;
+            for (unsigned t = 0; t < nt; ++t) {
+                if (fib[t].done) continue;
+                to_fiber(t);
+                if (fib[t].done) continue;
+                any = true;
+                if (fib[t].nbar != round) {
+                    std::fprintf(stderr, "emulated block: thread %u at barrier %lu in round %lu\n", t, fib[t].nbar,
+                                 round);
+                    std::abort();
+                }
+            }
+            if (!any) break;
+        }
     }
 };
-inline EmuPool &emu_pool() {
-    static EmuPool *p = new EmuPool();   // never destroyed: detached threads outlive main
-    return *p;
+inline EmuSched &emu_sched() {
+    static EmuSched *s = new EmuSched();
+    return *s;
+}
+inline void EmuSched::entry() {
+    EmuSched &s = emu_sched();
+#if defined(__SANITIZE_ADDRESS__)
+    __sanitizer_finish_switch_fiber(nullptr, &s.sched_bottom, &s.sched_size);
+#endif
+    s.body();
+    s.fib[s.cur].done = true;
+    s.to_sched(true);
+    std::abort();   // a finished fiber is never resumed
+}
+inline void emu_barrier() {
+    EmuSched &s = emu_sched();
+    ++s.fib[s.cur].nbar;
+    s.to_sched(false);
 }
 
 template <class K, class... A>
 void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
+    EmuSched &s = emu_sched();
+    std::lock_guard<std::mutex> serial(s.launch_mu);
     const unsigned nt = block.x * block.y * block.z;
     const unsigned nb = grid.x * grid.y * grid.z;
-    // blocks run one after the other, separated by a barrier so that
-    // block-shared (static) arrays are reused safely
-    std::barrier<> bar((std::ptrdiff_t)nt);
-    emu_pool().run(nt, [&](unsigned t) {
-        gridDim = grid;
-        blockDim = block;
-        threadIdx = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-        emu_bar = &bar;
-        for (unsigned b = 0; b < nb; ++b) {
-            blockIdx = dim3(b % grid.x, (b / grid.x) % grid.y, b / (grid.x * grid.y));
-            kernel(args...);
-            bar.arrive_and_wait();
-        }
-    });
+    if (s.fib.size() < nt) s.fib.resize(nt);
+    gridDim = grid;
+    blockDim = block;
+    s.block = block;
+    s.body = [&] { kernel(args...); };
+    for (unsigned b = 0; b < nb; ++b) {
+        blockIdx = dim3(b % grid.x, (b / grid.x) % grid.y, b / (grid.x * grid.y));
+        s.run_block(nt);
+    }
 }
 #define hipLaunchKernelGGL(K, G, B, SHM, ST, ...) emu_launch(K, G, B, __VA_ARGS__)

@@ -107,6 +107,25 @@ def test_emulated_rk_step_matches_oracle(driver, tmp_path):
         assert _rel(G[c], O[c]) <= 1e-12
 
 
+def test_emulated_rk_rti_32_config(driver, tmp_path):
+    """The 32^3 Rayleigh-Taylor configuration exactly as the GPU case would run
+    it: one segment per direction, 20 RK4 steps at dt = 1e-5, every point of all
+    5 fields against the oracle (device buffers end flush with a guard page and
+    every plan table sits in an allocation of its own)."""
+    p = dict(inputs.AIR)
+    Q = inputs.rti_state(32, seed=0)
+    qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
+    Q.tofile(qin)
+    _run(driver, ["rk", 32, 32, 32, 1, 1, 1, 1.0, 1.0, 1.0, 1, 1, 1e-5, 20, qin, qout], tmp_path)
+    G = np.fromfile(qout).reshape(Q.shape)
+    O = oracle.rk4(p, Q, 1e-5, 20)
+    assert np.array_equal(G[0], O[0])
+    for c in range(5):
+        ch = np.max(np.abs(O[c] - Q[c]))
+        assert _rel(G[c], O[c]) <= 1e-12
+        assert np.max(np.abs(G[c] - O[c])) <= 1e-12 * ch
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_emulated_rk_line_march(driver, tmp_path, mixed):
     """One RK4 step of a box whose y and z lines are cut into pieces (line

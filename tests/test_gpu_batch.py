@@ -5,6 +5,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from paper_2203_00879_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -65,3 +66,23 @@ def test_batch_single_box_equals_rk_step():
     nopcs.rk_step_batch(nopcs.make_params(P), [(g, Q, ws)], 1e-5, 3)
     torch.cuda.synchronize()
     assert np.array_equal(Q.cpu().numpy(), lone((40, 36, 44), (2, 3, 2), 7, nopcs.FP64, 1e-5, 3))
+
+
+def test_batch_box_against_oracle():
+    """A box stepped inside a batch against the FP64 oracle: the 48 x 40 x 36
+    box (2 x 1 x 3 segments) of an FP64 batch, 3 steps, every point of all 5
+    fields within 1e-12 of the field's maximum and of its change."""
+    dt, steps = 1e-5, 3
+    boxes = [make(s, n, seed, nopcs.FP64) for s, n, seed in BOXES]
+    nopcs.rk_step_batch(nopcs.make_params(P), boxes, dt, steps)
+    torch.cuda.synchronize()
+    shape, nseg, seed = BOXES[1]
+    Q0 = inputs.rti_state(shape, seed=seed, noise_K=1e-3)
+    O = oracle.rk4(P, Q0, dt, steps)
+    G = boxes[1][1].cpu().numpy()
+    for c in range(5):
+        scale = np.max(np.abs(O[c]))
+        ch = np.max(np.abs(O[c] - Q0[c]))
+        err = float(np.max(np.abs(G[c] - O[c])))
+        say("  field", c, "err %.3e of the field, %.3e of its change" % (err / scale, err / ch))
+        assert err <= 1e-12 * scale and err <= 1e-12 * ch

@@ -36,9 +36,18 @@ def test_rhs_mixed_against_oracle(shape, nseg):
     assert max(errs) <= 1e-6 and max(errs) > 0
 
 
-def test_rk_mixed_against_fp64():
-    """RTI box 64^3, 4 segments, 10 steps: the change of every field over the run
-    in mixed precision against FP64 on the GPU (itself checked against the oracle)."""
+# Per-field bound of mixed-precision RK4 stepping, relative to the largest change
+# of the field over the run: each stage's right-hand side carries about 3e-7
+# of its components' maxima (see the module docstring) and the change over the
+# run is the dt-weighted sum of those right-hand sides, so the change inherits
+# the same relative error; the bound leaves a factor of about 7 over that.
+MIXED_CHANGE_BOUND = 2e-6
+
+
+def test_rk_mixed_against_oracle_and_fp64():
+    """RTI box 64^3, 4 segments, 10 steps: the change of every field over the run,
+    FP64 on the GPU against the oracle (<= 1e-12) and mixed precision against
+    the oracle (<= MIXED_CHANGE_BOUND) and against GPU FP64."""
     import torch
     p = dict(inputs.AIR)
     n, steps, dt = 64, 10, 1e-5
@@ -51,8 +60,14 @@ def test_rk_mixed_against_fp64():
         nopcs.rk_step(nopcs.make_params(p), g, Qd, dt, steps, ws, precision=prec)
         torch.cuda.synchronize()
         out[prec] = Qd.cpu().numpy()
+    O = oracle.rk4(p, Q0, dt, steps)
+    do = O - Q0
     d64, d32 = out[nopcs.FP64] - Q0, out[nopcs.MIXED] - Q0
-    errs = [_rel(d32[c], d64[c]) for c in range(5)]
-    print("mixed vs FP64, change over 10 steps, relative max errors", ["%.2e" % e for e in errs], flush=True)
+    e64 = [_rel(d64[c], do[c]) for c in range(5)]
+    e32 = [_rel(d32[c], do[c]) for c in range(5)]
+    e32_64 = [_rel(d32[c], d64[c]) for c in range(5)]
+    print("change over 10 steps, relative max errors: FP64 vs oracle", ["%.2e" % e for e in e64],
+          "mixed vs oracle", ["%.2e" % e for e in e32], "mixed vs FP64", ["%.2e" % e for e in e32_64], flush=True)
     assert np.isfinite(out[nopcs.MIXED]).all()
-    assert max(errs) <= 1e-4
+    assert max(e64) <= 1e-12
+    assert max(e32) <= MIXED_CHANGE_BOUND and max(e32_64) <= MIXED_CHANGE_BOUND

@@ -6,6 +6,7 @@ mix of boxes must equal the same box advanced alone by rk_step, bit for bit
 import numpy as np
 import pytest
 
+import oracle
 from paper_2203_00879_amd import inputs, nopcs
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +49,14 @@ def test_mix_equals_alone_bitwise():
             assert rc == nopcs.NOPCS_OK and res.steps_done == steps
             assert np.array_equal(Q, ref)
             assert res.t_submit <= res.t_admit <= res.t_done
+            if g.n[0] == 64:
+                # the 64^3 box (2 segments per direction, 9 steps) against the FP64 oracle
+                O = oracle.rk4(inputs.AIR, Q0, dt, steps)
+                for c in range(5):
+                    err = float(np.max(np.abs(Q[c] - O[c])))
+                    print("  oracle field", c, "err %.3e of the field, %.3e of its change"
+                          % (err / np.max(np.abs(O[c])), err / np.max(np.abs(O[c] - Q0[c]))), flush=True)
+                    assert err <= 1e-12 * np.max(np.abs(O[c])) and err <= 1e-12 * np.max(np.abs(O[c] - Q0[c]))
 
 
 def test_mixed_precision_requests_equal_alone_bitwise():
