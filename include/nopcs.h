@@ -213,6 +213,31 @@ int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, con
             size_t ws_bytes, void *hip_stream);
 
 /*
+ * nse_rhs_noalloc -- nse_rhs for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same kernels and the same result as nse_rhs (bit for bit),
+ * with no workspace argument: the only scratch nse_rhs needs, the closure
+ * array of the y and z line marches (5 components x closure rows x lines
+ * doubles of the larger direction), lives in a static device array of
+ * NOPCS_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and never builds a plan: the grid's line plans
+ * must already be cached on the current device by an earlier call with the
+ * same grid and piece lengths (nse_rhs, rk_step, nopcs_derivative, ...),
+ * else NOPCS_EINVAL.  Grids whose closure array exceeds the static array
+ * (about 256^3 with the default pieces) get NOPCS_EINVAL with a message, before
+ * any device work.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (nothing in it needs clearing: each closure
+ * value is written before it is read): calls that overlap on one GPU -- on
+ * different streams or from different threads -- race and must not be
+ * issued.  Q: device state (5 fields, read only); R: device output (5 fields),
+ * not overlapping Q.  Asynchronous on hip_stream.
+ */
+#define NOPCS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nse_rhs_noalloc(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, double *R,
+                    void *hip_stream);
+
+/*
  * nopcs_compact_viscous_workspace_bytes -- bytes of device workspace that
  * nse_rhs_compact_viscous needs: nopcs_workspace_bytes(grid, NOPCS_FP64) plus
  * 28 fields (u, v, w, T, 12 gradients, 12 viscous flux components), each

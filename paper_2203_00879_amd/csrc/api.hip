@@ -65,9 +65,9 @@ static bool check_params(const nse_params *p) {
     return true;
 }
 
-static int get_plans(const nopcs_grid *g, LinePlanDev pl[3]) {
+static int get_plans(const nopcs_grid *g, LinePlanDev pl[3], bool lookup_only = false) {
     for (int d = 0; d < 3; ++d) {
-        const int rc = get_line_plan(g->n[d], g->nseg[d], piece_length(d, g->n[d]), g->len[d], &pl[d]);
+        const int rc = get_line_plan(g->n[d], g->nseg[d], piece_length(d, g->n[d]), g->len[d], &pl[d], lookup_only);
         if (rc != NOPCS_OK) return rc;
         if (4 + pl[d].ncl > sweep_known_rows_max(g->n[d])) {
             set_error("too many segments along direction " + std::to_string(d) + " for " +
@@ -121,9 +121,11 @@ static thread_local bool t_capturing = false;   // inside a graph capture: no ev
 template <class F>
 static hipError_t timed_impl(int id, hipStream_t st, F &&f);
 
+static thread_local bool t_no_alloc = false;    // inside nse_rhs_noalloc: no event objects either
+
 template <class F>
 static hipError_t timed(int id, hipStream_t st, F &&f) {
-    if (t_capturing) return f();
+    if (t_capturing || t_no_alloc) return f();
     return timed_impl(id, st, std::forward<F>(f));
 }
 
@@ -608,6 +610,72 @@ int nse_rhs(const nse_params *params, const nopcs_grid *grid, int precision, con
     if (rc != NOPCS_OK) return rc;
     double *clo = reinterpret_cast<double *>(static_cast<char *>(ws) + 3 * state_bytes(grid));
     return rhs_into(make_nd(*params), grid, pl, Q, R, clo, precision == NOPCS_MIXED, (hipStream_t)hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// nse_rhs without allocation: the closure array of the y and z line marches
+// (the only workspace nse_rhs uses) lives in a static device array of fixed
+// size instead of the caller's workspace.  Each device holds its own copy of
+// the array at its own address, looked up once per device with
+// hipGetSymbolAddress; host code never passes the array's name to a kernel.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocScratchBytes = (size_t)NOPCS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device (null: not looked up yet)
+
+// address of this device's `scratch`, looked up on the first call on the device
+int scratch_address(void **out) {
+    int dev = 0;
+    NOPCS_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal out of range for the static scratch array");
+        return NOPCS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        NOPCS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress gave no address for the scratch array");
+            return NOPCS_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NOPCS_OK;
+}
+}  // namespace
+
+extern "C" int nse_rhs_noalloc(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q,
+                               double *R, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
+    if (precision != NOPCS_FP64 && precision != NOPCS_MIXED) { set_error("unknown precision"); return NOPCS_EINVAL; }
+    if (!Q || !R) { set_error("Q and R must be non-NULL"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_plans(grid, pl, /*lookup_only=*/true);
+    if (rc != NOPCS_OK) return rc;
+    // the closure array of the larger of the y and z sweeps (as in nse_rhs's workspace)
+    size_t need = 0;
+    for (int d = 1; d <= 2; ++d) need = std::max(need, march_closure_elems(grid->n, d, pl[d].ncl) * sizeof(double));
+    if (need > kNoAllocScratchBytes) {
+        set_error("nse_rhs_noalloc: this grid needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                  std::to_string(kNoAllocScratchBytes) + " of the static array");
+        return NOPCS_EINVAL;
+    }
+    void *clo = nullptr;
+    rc = scratch_address(&clo);
+    if (rc != NOPCS_OK) return rc;
+    // every closure value is written by the closure pass before the run march
+    // reads it: nothing in the array needs clearing
+    t_no_alloc = true;
+    rc = rhs_into(make_nd(*params), grid, pl, Q, R, static_cast<double *>(clo), precision == NOPCS_MIXED,
+                  (hipStream_t)hip_stream);
+    t_no_alloc = false;
+    return rc;
 }
 
 int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt, int32_t nsteps,

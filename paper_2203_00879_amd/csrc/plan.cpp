@@ -278,7 +278,7 @@ std::map<std::tuple<int, int, int, int, uint64_t>, PlanEntry> g_plans;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
-int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
     uint64_t lbits;
@@ -289,6 +289,11 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out) {
     if (it != g_plans.end()) {
         *out = it->second.dev;
         return NOPCS_OK;
+    }
+    if (lookup_only) {
+        set_error("no cached line plan for n=" + std::to_string(n) + ", nseg=" + std::to_string(nseg) +
+                  " on this device (an earlier call with this grid builds it)");
+        return NOPCS_EINVAL;
     }
     LinePlanHost P;
     std::string err;

@@ -84,8 +84,10 @@ std::vector<uint8_t> row_kinds(int n, int nseg, int sub_len);
 // Segment starts of an even split (the first n % nseg segments one point longer).
 std::vector<int> even_segments(int n, int nseg);
 
-// Cached device plan for (device, n, nseg, sub_len, len) -> LinePlanDev.
-int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out);
+// Cached device plan for (device, n, nseg, sub_len, len) -> LinePlanDev, built
+// (and its device memory allocated) on first use; lookup_only: never build,
+// NOPCS_EINVAL if the plan is not cached yet.
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only = false);
 
 // Free all cached device plans of the current device.
 void release_line_plans();

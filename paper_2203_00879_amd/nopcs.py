@@ -86,6 +86,7 @@ def lib():
         L.nopcs_workspace_bytes.argtypes = [ctypes.POINTER(Grid), _I]
         L.nopcs_derivative.argtypes = [ctypes.POINTER(Grid), _I, _I, _V, _V, _V, _V]
         L.nse_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V, ctypes.c_size_t, _V]
+        L.nse_rhs_noalloc.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V]
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
         L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
@@ -206,6 +207,16 @@ def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):
     nbytes = ws.numel() * ws.element_size()
     _check(lib().nse_rhs(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(R), _ptr(ws),
                          nbytes, _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # NOPCS_NOALLOC_SCRATCH_BYTES
+
+
+def nse_rhs_noalloc(params, grid, Q, R, precision=FP64, stream=None):
+    """R = right-hand side of ge17 at Q with no allocation: the library's static
+    scratch array replaces the workspace; the grid's plans must be cached."""
+    _check(lib().nse_rhs_noalloc(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(R),
+                                 _stream(stream)))
 
 
 def compact_viscous_workspace_bytes(grid):

@@ -62,6 +62,8 @@ inline void emu_guarded_free(void *p) {
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __restrict__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(X) X
 
 using std::max;
 using std::min;
@@ -128,6 +130,9 @@ enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipErrorNotReady = 6
 inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t) new char; return hipSuccess; }
 inline hipError_t hipStreamDestroy(hipStream_t s) { delete (char *)s; return hipSuccess; }
 inline hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
+// a __device__ variable is a host variable here
+template <class T>
+inline hipError_t hipGetSymbolAddress(void **p, const T &sym) { *p = (void *)&sym; return hipSuccess; }
 // graphs: not available in the host build (capture reports an error; nothing is launched)
 typedef struct emu_graph *hipGraph_t;
 typedef struct emu_graph_exec *hipGraphExec_t;
