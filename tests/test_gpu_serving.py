@@ -49,8 +49,8 @@ def test_mix_equals_alone_bitwise():
             assert rc == nopcs.NOPCS_OK and res.steps_done == steps
             assert np.array_equal(Q, ref)
             assert res.t_submit <= res.t_admit <= res.t_done
-            if g.n[0] == 64:
-                # the 64^3 box (2 segments per direction, 9 steps) against the FP64 oracle
+            if g.n[0] == 72:
+                # the 72^3 box (one segment cut into pieces, 4 steps) against the FP64 oracle
                 O = oracle.rk4(inputs.AIR, Q0, dt, steps)
                 for c in range(5):
                     err = float(np.max(np.abs(Q[c] - O[c])))
