@@ -35,6 +35,9 @@
  *  - Classical four-stage RK4 (Section 4); wall conditions applied after each
  *    stage: zero momentum, adiabatic wall temperature from the one-sided
  *    second-order normal derivative set to zero, density from continuity.
+ *  - The implicit filter of Section 4 (cited, not printed) is read as the
+ *    fourth-order tridiagonal compact filter with the printed coefficient
+ *    0.135, wall rows unfiltered, applied along x, y, z in turn.
  */
 #include <math.h>
 #include <stddef.h>
@@ -765,6 +768,194 @@ void ora_rhs_points(const ora_params *p, const int n[3], const double len[3], co
             for (int comp = 0; comp < 5; ++comp) out[(size_t)comp * npts + q] = r[comp];
         }
         free(F); free(DF); free(work);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Implicit low-pass filter, applied every 50 steps with coefficient 0.135  */
+/* (Section 4; the paper cites the filter without printing it).  Reading:   */
+/* the fourth-order member of the one-parameter family of tridiagonal       */
+/* compact filters,                                                         */
+/*   af fh_{i-1} + fh_i + af fh_{i+1}                                       */
+/*       = a0 f_i + (a1/2)(f_{i+1} + f_{i-1}) + (a2/2)(f_{i+2} + f_{i-2}),  */
+/*   a0 = 5/8 + 3af/4,  a1 = 1/2 + af,  a2 = -1/8 + af/4,                   */
+/* on rows 2..n-3 of a line; rows 0, 1, n-2, n-1 are left unfiltered.  The  */
+/* 3D filter applies it along x, then y, then z.  Its transfer function is  */
+/* (a0 + a1 cos t + a2 cos 2t)/(1 + 2 af cos t): 1 at t = 0, 0 at t = pi.   */
+/* ------------------------------------------------------------------------ */
+static void filter_coefs(double af, double *a0, double *a1, double *a2)
+{
+    *a0 = 5.0 / 8.0 + 0.75 * af;
+    *a1 = 0.5 + af;
+    *a2 = -1.0 / 8.0 + 0.25 * af;
+}
+
+static double filter_rhs(const double *f, ptrdiff_t s, int i, double af)
+{
+    double a0, a1, a2;
+    filter_coefs(af, &a0, &a1, &a2);
+    const double *c = f + (ptrdiff_t)i * s;
+    return a0 * c[0] + 0.5 * a1 * (c[s] + c[-s]) + 0.5 * a2 * (c[2 * s] + c[-2 * s]);
+}
+
+/* Rows lo+1..hi-1 of a filtered line between two known rows (Thomas).      */
+static void filter_run(int lo, int hi, double af, const double *d, double *x, double *work)
+{
+    int m = hi - lo - 1;
+    if (m <= 0) return;
+    double *sub = work, *dia = work + m, *sup = work + 2 * m, *rhs = work + 3 * m, *w = work + 4 * m;
+    for (int k = 0; k < m; ++k) {
+        int i = lo + 1 + k;
+        sub[k] = af;
+        dia[k] = 1.0;
+        sup[k] = af;
+        double r = d[i];
+        if (k == 0) r = r - af * x[lo];
+        if (k == m - 1) r = r - af * x[hi];
+        rhs[k] = r;
+    }
+    ora_thomas(m, sub, dia, sup, rhs, x + lo + 1, w);
+}
+
+/* Filter one line: the global (one-segment) solve.  work: 8n doubles. */
+void ora_filter_line(int n, double af, const double *f, ptrdiff_t sf, double *fh, ptrdiff_t sh, double *work)
+{
+    double *x = work, *d = work + n, *w = work + 2 * n;
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (is_wall_row(i, n)) x[i] = f[(ptrdiff_t)i * sf];
+    for (int i = 2; i <= n - 3; ++i) d[i] = filter_rhs(f, sf, i, af);
+    filter_run(1, n - 2, af, d, x, w);
+    for (int i = 0; i < n; ++i) fh[(ptrdiff_t)i * sh] = x[i];
+}
+
+/* Row e of the filter's equivalent explicit operator C_f = A_f^-1 B_f of the */
+/* global line (as ora_equiv_row for the derivative).  work: 8n doubles.     */
+void ora_filter_equiv_row(int n, double af, int e, double *row, double *work)
+{
+    double a0, a1, a2;
+    filter_coefs(af, &a0, &a1, &a2);
+    double *sub = work, *dia = work + n, *sup = work + 2 * n, *rhs = work + 3 * n,
+           *y = work + 4 * n, *w = work + 5 * n;
+    for (int j = 0; j < n; ++j) {
+        double a_jm1_j = (j - 1 >= 2 && j - 1 <= n - 3) ? af : 0.0;
+        double a_jp1_j = (j + 1 >= 2 && j + 1 <= n - 3) ? af : 0.0;
+        sub[j] = (j > 0) ? a_jm1_j : 0.0;
+        sup[j] = (j < n - 1) ? a_jp1_j : 0.0;
+        dia[j] = 1.0;
+        rhs[j] = (j == e) ? 1.0 : 0.0;
+    }
+    ora_thomas(n, sub, dia, sup, rhs, y, w);
+    for (int j = 0; j < n; ++j) row[j] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double yi = y[i];
+        if (yi == 0.0) continue;
+        if (is_wall_row(i, n)) {
+            row[i] += yi;
+        } else {
+            row[i - 2] += yi * 0.5 * a2; row[i - 1] += yi * 0.5 * a1; row[i] += yi * a0;
+            row[i + 1] += yi * 0.5 * a1; row[i + 2] += yi * 0.5 * a2;
+        }
+    }
+}
+
+/* Segmented NOHAP filter of one line: segment ends take the truncated sum    */
+/* with the row of the global C_f (|j - e| <= 48), the other rows of each    */
+/* segment are solved on their own.  work: 16n doubles.                      */
+void ora_filter_line_seg(int n, double af, int nseg, const int *seg_lo, const double *f, ptrdiff_t sf,
+                         double *fh, ptrdiff_t sh, double *work)
+{
+    double *x = work, *d = work + n, *row = work + 2 * n, *w = work + 3 * n;
+    char *known = (char *)(work + 13 * n);
+    memset(known, 0, (size_t)n);
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (is_wall_row(i, n)) { x[i] = f[(ptrdiff_t)i * sf]; known[i] = 1; }
+    for (int s = 0; s < nseg; ++s) {
+        int lo = seg_lo[s], hi = (s + 1 < nseg) ? seg_lo[s + 1] - 1 : n - 1;
+        int ends[2] = {lo, hi};
+        for (int q = 0; q < 2; ++q) {
+            int e = ends[q];
+            if ((q == 0 && s == 0) || (q == 1 && s == nseg - 1)) continue;
+            if (is_wall_row(e, n)) continue;
+            ora_filter_equiv_row(n, af, e, row, w);
+            int j0 = e - ORA_NB < 0 ? 0 : e - ORA_NB;
+            int j1 = e + ORA_NB > n - 1 ? n - 1 : e + ORA_NB;
+            double acc = 0.0;
+            for (int j = j0; j <= j1; ++j) acc += row[j] * f[(ptrdiff_t)j * sf];
+            x[e] = acc;
+            known[e] = 1;
+        }
+    }
+    for (int i = 2; i <= n - 3; ++i)
+        if (!known[i]) d[i] = filter_rhs(f, sf, i, af);
+    int lo = 1;
+    for (int i = 2; i <= n - 2; ++i) {
+        if (known[i]) { filter_run(lo, i, af, d, x, w); lo = i; }
+    }
+    for (int i = 0; i < n; ++i) fh[(ptrdiff_t)i * sh] = x[i];
+}
+
+/* Filter along dir of a 3D field (global line solves); out may equal f.     */
+void ora_filter_dir(const int n[3], int dir, double af, const double *f, double *out)
+{
+    ptrdiff_t st; long nl;
+    line_geometry(n, dir, &st, &nl);
+    int nd = n[dir];
+    #pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * 9 * (size_t)nd);
+        double *tmp = work + 8 * nd;
+        #pragma omp for schedule(static)
+        for (long l = 0; l < nl; ++l) {
+            ptrdiff_t b = line_base(n, dir, l);
+            ora_filter_line(nd, af, f + b, st, tmp, 1, work);
+            for (int i = 0; i < nd; ++i) out[b + (ptrdiff_t)i * st] = tmp[i];
+        }
+        free(work);
+    }
+}
+
+/* Segmented filter along dir (NOHAP); out may equal f. */
+void ora_filter_dir_seg(const int n[3], int dir, double af, int nseg, const int *seg_lo, const double *f,
+                        double *out)
+{
+    ptrdiff_t st; long nl;
+    line_geometry(n, dir, &st, &nl);
+    int nd = n[dir];
+    #pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * 17 * (size_t)nd);
+        double *tmp = work + 16 * nd;
+        #pragma omp for schedule(static)
+        for (long l = 0; l < nl; ++l) {
+            ptrdiff_t b = line_base(n, dir, l);
+            ora_filter_line_seg(nd, af, nseg, seg_lo, f + b, st, tmp, 1, work);
+            for (int i = 0; i < nd; ++i) out[b + (ptrdiff_t)i * st] = tmp[i];
+        }
+        free(work);
+    }
+}
+
+/* The 3D filter of a state: every conserved field along x, then y, then z,  */
+/* then the wall conditions (the filtered near-wall values set the adiabatic */
+/* wall temperature).  Q in/out. */
+void ora_filter_state(const ora_params *p, const int n[3], double af, double *Q)
+{
+    size_t N = (size_t)n[0] * n[1] * n[2];
+    for (int c = 0; c < 5; ++c)
+        for (int d = 0; d < 3; ++d) ora_filter_dir(n, d, af, Q + c * N, Q + c * N);
+    ora_apply_bc(p, n, Q);
+}
+
+/* RK4 stepping with the 3D filter after every `every`-th step (Section 4:   */
+/* every 50 steps).  every <= 0: never. */
+void ora_rk4_filtered(const ora_params *p, const int n[3], const double len[3], double *Q, double dt, int nsteps,
+                      double af, int every)
+{
+    for (int s = 1; s <= nsteps; ++s) {
+        ora_rk4(p, n, len, Q, dt, 1);
+        if (every > 0 && s % every == 0) ora_filter_state(p, n, af, Q);
     }
 }
 

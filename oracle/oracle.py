@@ -21,7 +21,11 @@ __all__ = [
     "build", "lib", "OraParams", "alpha", "b1", "b2", "nb", "thomas", "d1_line", "equiv_row",
     "d1_line_seg", "d1", "d1_seg", "d2", "rhs", "rhs_points", "apply_bc", "rk4", "rk4_linear",
     "scales", "segment_starts", "num_threads", "vorticity_budget", "disturbance_pressure", "line_spectrum", "rhs_compact_viscous", "rk4_compact_viscous",
+    "filter_line", "filter_line_seg", "filter_equiv_row", "filter_dir", "filter_dir_seg", "filter_state",
+    "rk4_filtered", "FILTER_ALPHA",
 ]
+
+FILTER_ALPHA = 0.135   # filtering coefficient of Section 4
 
 
 def build(force=False):
@@ -77,6 +81,13 @@ def lib():
         L.ora_rk4_linear.restype = _D
         L.ora_scales.argtypes = [ctypes.POINTER(OraParams), _P]
         L.ora_num_threads.restype = _I
+        L.ora_filter_line.argtypes = [_I, _D, _P, _PD, _P, _PD, _P]
+        L.ora_filter_equiv_row.argtypes = [_I, _D, _I, _P, _P]
+        L.ora_filter_line_seg.argtypes = [_I, _D, _I, _P, _P, _PD, _P, _PD, _P]
+        L.ora_filter_dir.argtypes = [_P, _I, _D, _P, _P]
+        L.ora_filter_dir_seg.argtypes = [_P, _I, _D, _I, _P, _P, _P]
+        L.ora_filter_state.argtypes = [ctypes.POINTER(OraParams), _P, _D, _P]
+        L.ora_rk4_filtered.argtypes = [ctypes.POINTER(OraParams), _P, _P, _P, _D, _I, _D, _I]
         _lib = L
     return _lib
 
@@ -312,3 +323,71 @@ def line_spectrum(f):
     for k = 0 .. n // 2, by the library FFT."""
     f = np.asarray(f, dtype=np.float64)
     return np.abs(np.fft.rfft(f)) / f.size
+
+
+# ---------------------------------------------------------------------------
+# Implicit filter of Section 4 (reading: fourth-order tridiagonal compact
+# filter, wall rows unfiltered, applied along x, y, z in turn)
+# ---------------------------------------------------------------------------
+def filter_line(f, af=FILTER_ALPHA):
+    """Filtered line (global solve)."""
+    f = _f64(f)
+    n = len(f)
+    out = np.empty(n)
+    work = np.empty(8 * n)
+    lib().ora_filter_line(n, float(af), _ptr(f), 1, _ptr(out), 1, _ptr(work))
+    return out
+
+
+def filter_equiv_row(n, e, af=FILTER_ALPHA):
+    """Row e of the filter's equivalent explicit operator A_f^-1 B_f on n points."""
+    row = np.empty(n)
+    work = np.empty(8 * n)
+    lib().ora_filter_equiv_row(int(n), float(af), int(e), _ptr(row), _ptr(work))
+    return row
+
+
+def filter_line_seg(f, seg_lo, af=FILTER_ALPHA):
+    """Segmented (NOHAP) filter of one line; seg_lo: segment starts."""
+    f = _f64(f)
+    n = len(f)
+    lo = np.ascontiguousarray(seg_lo, dtype=np.int32)
+    out = np.empty(n)
+    work = np.empty(16 * n + n // 8 + 8)
+    lib().ora_filter_line_seg(n, float(af), len(lo), _ptr(lo), _ptr(f), 1, _ptr(out), 1, _ptr(work))
+    return out
+
+
+def filter_dir(f, direction, af=FILTER_ALPHA):
+    """Filter a 3D field f[nz, ny, nx] along one direction (global line solves)."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().ora_filter_dir(_ptr(_dims(f.shape)), int(direction), float(af), _ptr(f), _ptr(out))
+    return out
+
+
+def filter_dir_seg(f, direction, nseg, af=FILTER_ALPHA):
+    """Segmented (NOHAP) filter along one direction with nseg near-equal segments."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    n = f.shape[2 - direction]
+    lo = np.ascontiguousarray(segment_starts(n, nseg), dtype=np.int32)
+    lib().ora_filter_dir_seg(_ptr(_dims(f.shape)), int(direction), float(af), len(lo), _ptr(lo), _ptr(f), _ptr(out))
+    return out
+
+
+def filter_state(params, Q, af=FILTER_ALPHA):
+    """3D filter of every conserved field (x, then y, then z), then the wall conditions."""
+    Q = _f64(Q).copy()
+    p = OraParams.from_dict(params)
+    lib().ora_filter_state(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), float(af), _ptr(Q))
+    return Q
+
+
+def rk4_filtered(params, Q, dt, nsteps, every=50, af=FILTER_ALPHA, length=1.0):
+    """RK4 steps with the 3D filter after every `every`-th step (Section 4)."""
+    Q = _f64(Q).copy()
+    p = OraParams.from_dict(params)
+    lib().ora_rk4_filtered(ctypes.byref(p), _ptr(_dims(Q.shape[1:])), _ptr(_lens(length)), _ptr(Q), float(dt),
+                           int(nsteps), float(af), int(every))
+    return Q

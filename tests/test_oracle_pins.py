@@ -793,3 +793,108 @@ def test_baroclinic_term_dominates_at_the_interface_early():
     band = slice(shape[1] // 2 - 1, shape[1] // 2 + 1)
     m = [np.max(np.abs(B[k:k + 3][:, :, band, :])) for k in (3, 6, 9)]   # stretching, dilatation, baroclinic
     assert m[2] / sum(m) > 0.97, m
+
+
+# ---------------------------------------------------------------------------
+# Implicit filter (Section 4: coefficient 0.135, every 50 steps).  The paper
+# cites the filter without printing it; the reading is the fourth-order
+# tridiagonal compact filter.  Three properties fix its right-hand side for a
+# given coefficient: constants pass unchanged, polynomials up to degree three
+# pass unchanged (fourth order), and the two-point (Nyquist) mode is removed.
+# ---------------------------------------------------------------------------
+def test_filter_coefficient_as_printed():
+    assert oracle.FILTER_ALPHA == PC["filter_alpha"]
+
+
+@pytest.mark.parametrize("n", [9, 17, 40])
+def test_filter_keeps_cubics_exactly(n):
+    """Interior rows of a fourth-order filter reproduce every cubic; wall rows are unfiltered."""
+    x = np.linspace(-1.0, 2.0, n)
+    for coeffs in ([2.5], [0.3, -1.7], [1.0, 0.5, -2.0], [-0.7, 1.1, 0.4, 3.0]):
+        f = np.polyval(coeffs, x)
+        fh = oracle.filter_line(f)
+        assert np.max(np.abs(fh - f)) <= 4e-15 * max(1.0, np.max(np.abs(f)))
+    # the same holds in 3D along every direction (a cubic in that coordinate)
+    g = np.random.default_rng(2).normal(size=(6, 7, 8))
+    for d in range(3):
+        m = g.shape[2 - d]
+        t = np.linspace(0.0, 1.0, m) ** 3 - 0.5 * np.linspace(0.0, 1.0, m)
+        shape = [1, 1, 1]
+        shape[2 - d] = m
+        f = np.broadcast_to(t.reshape(shape), g.shape).copy()
+        assert np.max(np.abs(oracle.filter_dir(f, d) - f)) <= 4e-15
+
+
+def test_filter_removes_the_two_point_mode():
+    """The (-1)^i mode vanishes on interior rows far enough from the walls that
+    the wall rows' unfiltered values no longer reach them (the filter's
+    equivalent explicit row decays like r^k, r = -0.1376 for 0.135)."""
+    n = 81
+    f = (-1.0) ** np.arange(n)
+    fh = oracle.filter_line(f)
+    assert np.max(np.abs(fh[20:-20])) <= 1e-15
+    # wall rows are left as they are
+    assert np.array_equal(fh[[0, 1, n - 2, n - 1]], f[[0, 1, n - 2, n - 1]])
+
+
+def test_filter_transfer_function_decays_as_its_root():
+    """Interior row of the filter's equivalent explicit operator: symmetric,
+    summing to 1, with taps decaying as r^|k|, r = (-1 + sqrt(1 - 4 af^2)) / (2 af)."""
+    af = oracle.FILTER_ALPHA
+    n, e = 121, 60
+    row = oracle.filter_equiv_row(n, e)
+    assert abs(np.sum(row) - 1.0) <= 1e-14
+    k = np.arange(1, 30)
+    assert np.max(np.abs(row[e + k] - row[e - k])) <= 1e-16
+    r = (-1.0 + math.sqrt(1.0 - 4.0 * af * af)) / (2.0 * af)
+    ratios = row[e + 5:e + 15] / row[e + 4:e + 14]
+    assert np.max(np.abs(ratios - r)) <= 1e-9
+
+
+@pytest.mark.parametrize("nseg", [2, 3, 5, 8])
+def test_filter_segment_invariance_nohap(nseg):
+    """Segmented filter with global-row closures equals the global solve (Section 3's claim for any compact operator)."""
+    n = 200
+    x = np.linspace(0.0, 1.0, n)
+    f = np.sin(23.0 * x) + 0.3 * np.cos(61.0 * x + 0.2) + np.random.default_rng(nseg).normal(scale=0.1, size=n)
+    ref = oracle.filter_line(f)
+    got = oracle.filter_line_seg(f, oracle.segment_starts(n, nseg))
+    assert np.max(np.abs(got - ref)) <= 2e-15 * np.max(np.abs(ref))
+    g3 = np.random.default_rng(5).normal(size=(12, 30, 26))
+    for d in range(3):
+        assert np.max(np.abs(oracle.filter_dir_seg(g3, d, 2) - oracle.filter_dir(g3, d))) <= 2e-15 * np.max(np.abs(g3))
+
+
+def test_filter_directions_commute_and_act_on_separable_modes():
+    """Filters along different axes act on different indices, so they commute;
+    on a separable product mode each acts on its own factor only."""
+    rng = np.random.default_rng(11)
+    f = rng.normal(size=(14, 16, 18))
+    a = oracle.filter_dir(oracle.filter_dir(f, 0), 1)
+    b = oracle.filter_dir(oracle.filter_dir(f, 1), 0)
+    assert np.max(np.abs(a - b)) <= 1e-14
+    z, y, x = (np.linspace(0.0, 1.0, m) for m in (14, 16, 18))
+    fx, fy, fz = np.sin(7.0 * x), np.cos(5.0 * y), np.sin(3.0 * z + 0.4)
+    F = fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+    got = oracle.filter_dir(F, 0)
+    want = fz[:, None, None] * fy[None, :, None] * oracle.filter_line(fx)[None, None, :]
+    assert np.max(np.abs(got - want)) <= 1e-15
+    got = oracle.filter_dir(F, 2)
+    want = oracle.filter_line(fz)[:, None, None] * fy[None, :, None] * fx[None, None, :]
+    assert np.max(np.abs(got - want)) <= 1e-15
+
+
+def test_filtered_stepping():
+    """RK4 with the filter after every 50th step: a quiescent state stays at rest
+    (to rounding), without filtering the stepping is plain RK4, and with it the
+    state after 50 steps is the filtered plain-RK4 state."""
+    p = _params(gravity=0)
+    Q = inputs.uniform_state((10, 9, 11), T=1.2, rho=0.9, params=p)
+    Qf = oracle.rk4_filtered(p, Q, 1e-4, 50, every=50)
+    assert np.max(np.abs(Qf - Q)) <= 1e-13 * np.max(np.abs(Q))
+    p = dict(inputs.AIR)
+    Q = inputs.rti_state((12, 14, 10), seed=1, noise_K=1.0)
+    assert np.array_equal(oracle.rk4_filtered(p, Q, 1e-5, 3, every=0), oracle.rk4(p, Q, 1e-5, 3))
+    a = oracle.rk4_filtered(p, Q, 1e-5, 50, every=50)
+    b = oracle.filter_state(p, oracle.rk4(p, Q, 1e-5, 50))
+    assert np.array_equal(a, b)
