@@ -281,6 +281,35 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
             void *ws, size_t ws_bytes, void *hip_stream);
 
 /*
+ * nopcs_filter -- the implicit 3D filter of Section 4, in place on a state.
+ * The paper applies an implicit filter with filtering coefficient 0.135 every
+ * 50 steps and cites it without printing it; it is read here as the
+ * fourth-order tridiagonal compact filter
+ *   af fh_{i-1} + fh_i + af fh_{i+1}
+ *       = a0 f_i + (a1/2)(f_{i+1} + f_{i-1}) + (a2/2)(f_{i+2} + f_{i-2}),
+ *   a0 = 5/8 + 3 af / 4,  a1 = 1/2 + af,  a2 = -1/8 + af / 4,
+ * on rows 2 .. n-3 of every line (rows 0, 1, n-2, n-1 unfiltered), solved
+ * with the NOHAP closure of Section 3 exactly as nopcs_derivative solves the
+ * derivative: each segment end takes the truncated row (|j - e| <= 48) of the
+ * global A_f^-1 B_f, the rest of each segment is an independent Thomas run;
+ * the result equals the one-segment solve up to round-off.  Every one of the
+ * 5 fields is filtered along x, then y, then z, then the wall conditions of
+ * rk_step are applied.  alpha_f (0.135 in the paper) must lie in (-0.5, 0.5).
+ * Q: device state, 5 fields, in/out.  Asynchronous on hip_stream.
+ */
+int nopcs_filter(const nse_params *params, const nopcs_grid *grid, double alpha_f, double *Q, void *hip_stream);
+
+/*
+ * rk_step_filtered -- rk_step with the implicit filter of nopcs_filter
+ * applied after every filter_every-th step, counting from this call's first
+ * step (Section 4: every 50 steps, alpha_f = 0.135); filter_every = 0 never
+ * filters.  Arguments otherwise as rk_step.
+ */
+int rk_step_filtered(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt,
+                     int32_t nsteps, int32_t filter_every, double alpha_f, void *ws, size_t ws_bytes,
+                     void *hip_stream);
+
+/*
  * rk_step_compact_viscous -- rk_step in FP64 with the right-hand side of
  * nse_rhs_compact_viscous (viscous terms by the compact first derivative):
  * the same four stages, registers and wall conditions.  ws: at least
@@ -292,26 +321,41 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
 
 /*
  * rk_step_batch -- rk_step for a batch of independent boxes of any sizes, all
- * with the same parameters, precision and dt: the RK4 step of every box is
- * captured once as a branch of one HIP graph (cached per batch: boxes, their
- * states and workspaces, parameters, precision, dt and piece lengths), and
- * each of the nsteps steps is one replay of that graph on hip_stream; the
- * device runs the branches concurrently.  Every box gets exactly the result of
- * rk_step on it alone.  1 <= nbox <= NOPCS_MAX_BATCH; each box: a valid grid,
- * Q 16-byte aligned, ws of at least nopcs_workspace_bytes(grid, precision)
- * bytes, 256-byte aligned; no two boxes may share a state or a workspace.
- * NOPCS_EINVAL on argument errors (before any device work).
+ * with the same parameters and precision, each with its own dt (box.dt, or the
+ * call's dt where box.dt is 0).  The RK4 step of all boxes runs as one launch
+ * per stage kernel and configuration over all boxes: the blocks of a launch
+ * take their (box, block) items from a device table of the boxes' arguments,
+ * so a stage has about a dozen launches whatever the number of boxes.  The
+ * step is captured once as a HIP graph (cached per batch: boxes, their states,
+ * workspaces and dt, parameters, precision and piece lengths) and each of the
+ * nsteps steps is one replay on hip_stream.  Every box gets exactly the result
+ * of rk_step on it alone (its blocks run the single-box kernels' arithmetic).
+ * 1 <= nbox <= NOPCS_MAX_BATCH; each box: a valid grid, Q 16-byte aligned, ws
+ * of at least nopcs_workspace_bytes(grid, precision) bytes, 256-byte aligned,
+ * dt >= 0; no two boxes may share a state or a workspace.  NOPCS_EINVAL on
+ * argument errors (before any device work).
  */
-#define NOPCS_MAX_BATCH 16
+#define NOPCS_MAX_BATCH 64
 typedef struct {
     nopcs_grid grid;
     double *Q;               /* device state, in/out */
     void *ws;                /* device workspace of this box */
     size_t ws_bytes;
+    double dt;               /* this box's step; 0: the call's dt */
 } nopcs_box;
 
 int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes, int precision, double dt,
                   int32_t nsteps, void *hip_stream);
+
+/*
+ * nopcs_set_batch_mode -- how rk_step_batch runs a step: 0 (the default) one
+ * launch per kernel and configuration over all boxes, as above, replayed as a
+ * graph; 1 one graph branch per box holding that box's own launches (the
+ * boxes overlap on the device through the branches); 2 the launches of mode 0
+ * issued directly on hip_stream every step, without a graph.  Every mode gives
+ * every box its lone result.  Process-wide; NOPCS_EINVAL for other values.
+ */
+int nopcs_set_batch_mode(int32_t mode);
 
 /* ------------------------------------------------------------------------ */
 /* Tuning.                                                                    */
@@ -425,7 +469,8 @@ enum {
     NOPCS_K_CLOSURE_Z = 8,/* closure rows of the z sweep (line-march pass)         */
     NOPCS_K_VORT = 9,     /* diagnostics: point-wise parts of the vorticity       */
                           /* budget, disturbance pressure, line spectrum          */
-    NOPCS_K_COUNT = 10
+    NOPCS_K_FILTER = 10,  /* implicit filter along one direction (one field)      */
+    NOPCS_K_COUNT = 11
 };
 
 /* on != 0: from now on every kernel launched by this library is bracketed by a

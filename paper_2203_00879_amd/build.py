@@ -48,10 +48,28 @@ def _compile(src, verbose, incremental=False):
     cmd = [hipcc()] + HIP_FLAGS + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
+    before = _snapshot(src)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
+    if _snapshot(src) != before:
+        # hipcc reads the sources once for the device pass and once for the host
+        # pass: an edit in between gives host code that launches kernels the
+        # device code object does not hold
+        os.remove(obj)
+        raise RuntimeError("%s or a header changed while it was compiled; build again" % src)
     return obj
+
+
+def _snapshot(src):
+    """Contents of a source and of every header it may include."""
+    files = [src] + sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h")))
+    files.append(os.path.join(os.path.dirname(HERE), "include", "nopcs.h"))
+    out = []
+    for f in files:
+        with open(f, "rb") as fh:
+            out.append(fh.read())
+    return out
 
 
 def build(verbose=False, jobs=None, incremental=False):

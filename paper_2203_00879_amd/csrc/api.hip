@@ -129,6 +129,13 @@ static hipError_t timed(int id, hipStream_t st, F &&f) {
     return timed_impl(id, st, std::forward<F>(f));
 }
 
+// launches collected into a batch are not timed one by one
+template <class F>
+static hipError_t timed(int id, hipStream_t st, const BatchCollector *col, F &&f) {
+    if (col) return f();
+    return timed(id, st, std::forward<F>(f));
+}
+
 template <class F>
 static hipError_t timed_impl(int id, hipStream_t st, F &&f) {
     bool on;
@@ -173,13 +180,22 @@ static size_t closure_bytes(const nopcs_grid *grid) {
 
 // convective sweep along d: line march (y, z) when the plan allows, LDS pencils
 // otherwise.  c32: the march eliminates in FP32 (mixed precision).
+// Phases of a batched RK4 step (the launches of one stage, in order; see
+// batch.hpp): launches of different boxes in one phase are independent.
+enum : int { PH_VISC = 0, PH_X = 1, PH_Y_CLOSURE = 2, PH_Y = 3, PH_Z_CLOSURE = 4, PH_Z = 5, PH_RK = 6, PH_WALL = 7,
+             PH_PER_STAGE = 16 };
+
 static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, const LinePlanDev &pl, double *clo,
-                      bool c32, hipStream_t st, const RkFuse *rk = nullptr) {
+                      bool c32, hipStream_t st, const RkFuse *rk = nullptr, BatchCollector *col = nullptr,
+                      int phase0 = 0) {
+    const int ph_closure = phase0 + (d == 1 ? PH_Y_CLOSURE : PH_Z_CLOSURE);
+    const int ph_runs = phase0 + (d == 0 ? PH_X : d == 1 ? PH_Y : PH_Z);
     if (clo && march_usable(d, pl)) {
-        NOPCS_HIP_CHECK(timed(NOPCS_K_CLOSURE_Y + (d - 1), st,
-                              [&] { return launch_march_closures(d, a.Qin, clo, grid->n, pl, a.c, st); }));
-        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] {
-            return launch_march_runs(d, a.Qin, a.R, a.r32, c32, clo, grid->n, pl, a.c, st, rk);
+        NOPCS_HIP_CHECK(timed(NOPCS_K_CLOSURE_Y + (d - 1), st, col, [&] {
+            return launch_march_closures(d, a.Qin, clo, grid->n, pl, a.c, st, col, ph_closure);
+        }));
+        NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, col, [&] {
+            return launch_march_runs(d, a.Qin, a.R, a.r32, c32, clo, grid->n, pl, a.c, st, rk, col, ph_runs);
         }));
         return NOPCS_OK;
     }
@@ -187,7 +203,8 @@ static int conv_sweep(int d, const NseSweepArgs &a, const nopcs_grid *grid, cons
         set_error("internal: fused RK update requested on a sweep without the line march");
         return NOPCS_EINVAL;
     }
-    NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl, st); }));
+    NOPCS_HIP_CHECK(timed(NOPCS_K_SWEEP_X + d, st, col,
+                          [&] { return launch_nse_sweep(d, a, sweep_geom(grid->n, d), pl, st, col, ph_runs); }));
     return NOPCS_OK;
 }
 
@@ -231,7 +248,8 @@ static int compact_visc_into(const NdConst &c, const nopcs_grid *grid, const Lin
 }
 
 static int launch_step(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
-                       const LinePlanDev pl[3], hipStream_t st, double *cvx = nullptr) {
+                       const LinePlanDev pl[3], hipStream_t st, double *cvx = nullptr,
+                       BatchCollector *col = nullptr) {
     const NdConst c = make_nd(params);
     const size_t N = field_elems(grid);
     const size_t reg = state_bytes(grid);
@@ -270,29 +288,35 @@ static int launch_step(const nse_params &params, const nopcs_grid *grid, int pre
         a.Qin = Qin;
         a.R = Rs;
         a.stage = stage;
-        if (cvx) {   // D1-based viscous variant (FP64 only)
+        const int ph = stage * PH_PER_STAGE;   // phases of this stage in a batched step
+        if (cvx) {   // D1-based viscous variant (FP64 only; never batched)
+            if (col) {
+                set_error("internal: the D1-based viscous variant is not batched");
+                return NOPCS_EINVAL;
+            }
             const int rc = compact_visc_into(c, grid, pl, Qin, static_cast<double *>(Rs), cvx, st);
             if (rc != NOPCS_OK) return rc;
         } else {
-            NOPCS_HIP_CHECK(
-                timed(NOPCS_K_VISCOUS, st, [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, col,
+                                  [&] { return launch_visc(Qin, Rs, mixed, grid->n, ih, c, st, col, ph + PH_VISC); }));
         }
         if (fuse) {
             const RkFuse F{K, Q, Sout, stage, dt, 0.5 * dt, dt / 6.0};
             for (int d = 0; d < 3; ++d) {
-                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st, d == 2 ? &F : nullptr);
+                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st, d == 2 ? &F : nullptr, col, ph);
                 if (rc != NOPCS_OK) return rc;
             }
         } else {
             for (int d = 0; d < 3; ++d) {
-                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st);
+                const int rc = conv_sweep(d, a, grid, pl[d], clo, mixed, st, nullptr, col, ph);
                 if (rc != NOPCS_OK) return rc;
             }
-            NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, [&] { return launch_rk_update(a, st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_RK, st, col, [&] { return launch_rk_update(a, st, col, ph + PH_RK); }));
         }
         double *Qout = stage == 3 ? Q : Sout;
         for (int d = 0; d < 3; ++d)
-            NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Qout, grid->n, d, c, st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, col,
+                                  [&] { return launch_bc(Qout, grid->n, d, c, st, col, ph + PH_WALL + d); }));
     }
     return NOPCS_OK;
 }
@@ -308,6 +332,8 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;   // recorded after the entry's latest replay
+    void *tables = nullptr;      // device tables of a batched step (owned)
+    std::vector<BatchLaunch> launches;   // a batched step launched directly (no graph)
 };
 std::mutex g_gmu;
 std::map<std::string, GraphEntry> g_graph_cache;
@@ -328,16 +354,25 @@ void drop_graph(GraphEntry &e) {
     }
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
     if (e.graph) (void)hipGraphDestroy(e.graph);
+    if (e.tables) (void)hipFree(e.tables);
     e.exec = nullptr;
     e.graph = nullptr;
     e.done = nullptr;
+    e.tables = nullptr;
 }
 
 // Replay a cached executable nsteps times on st and record its completion
 // event; the caller holds g_gmu, so no other thread can evict the entry
 // between the lookup and the launches.
 int replay(GraphEntry &e, int nsteps, hipStream_t st) {
-    for (int step = 0; step < nsteps; ++step) NOPCS_HIP_CHECK(hipGraphLaunch(e.exec, st));
+    for (int step = 0; step < nsteps; ++step) {
+        if (e.exec) {
+            NOPCS_HIP_CHECK(hipGraphLaunch(e.exec, st));
+        } else {
+            for (const BatchLaunch &L : e.launches)
+                NOPCS_HIP_CHECK(L.launch(static_cast<char *>(e.tables) + L.dev_off, L.ntab, L.total, L.blk, st));
+        }
+    }
     NOPCS_HIP_CHECK(hipEventRecord(e.done, st));
     return NOPCS_OK;
 }
@@ -702,6 +737,79 @@ int rk_step(const nse_params *params, const nopcs_grid *grid, int precision, dou
     return step_graph(*params, grid, precision, Q, dt, ws, pl, nsteps, st);
 }
 
+// Filter plans of a grid (the derivative's segments and pieces, the filter's
+// closure rows and elimination tables).
+static int get_filter_plans(const nopcs_grid *g, double af, LinePlanDev pl[3]) {
+    for (int d = 0; d < 3; ++d) {
+        const int rc = get_line_plan(g->n[d], g->nseg[d], piece_length(d, g->n[d]), g->len[d], &pl[d], false,
+                                     OP_FILTER, af);
+        if (rc != NOPCS_OK) return rc;
+        if (4 + pl[d].ncl > sweep_known_rows_max(g->n[d])) {
+            set_error("too many segments along direction " + std::to_string(d) + " for " +
+                      std::to_string(g->n[d]) + " points");
+            return NOPCS_EINVAL;
+        }
+    }
+    return NOPCS_OK;
+}
+
+static bool check_filter_alpha(double af) {
+    if (!(af > -0.5 && af < 0.5)) {
+        set_error("filter coefficient must lie in (-0.5, 0.5)");
+        return false;
+    }
+    return true;
+}
+
+// The 3D filter of a state in place: every field along x, then y, then z, then
+// the wall conditions.
+static int filter_state(const nse_params &params, const nopcs_grid *grid, const LinePlanDev pl[3], double *Q,
+                        hipStream_t st) {
+    const NdConst c = make_nd(params);
+    const size_t N = field_elems(grid);
+    for (int f = 0; f < 5; ++f)
+        for (int d = 0; d < 3; ++d) {
+            const SweepGeom g = sweep_geom(grid->n, d);
+            double *q = Q + f * N;
+            NOPCS_HIP_CHECK(timed(NOPCS_K_FILTER, st, [&] { return launch_filter(d, q, q, g, pl[d], st); }));
+        }
+    for (int d = 0; d < 3; ++d)
+        NOPCS_HIP_CHECK(timed(NOPCS_K_WALL, st, [&] { return launch_bc(Q, grid->n, d, c, st); }));
+    return NOPCS_OK;
+}
+
+int nopcs_filter(const nse_params *params, const nopcs_grid *grid, double alpha_f, double *Q, void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params) || !check_filter_alpha(alpha_f)) return NOPCS_EINVAL;
+    if (!Q) { set_error("Q must be non-NULL"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    const int rc = get_filter_plans(grid, alpha_f, pl);
+    if (rc != NOPCS_OK) return rc;
+    return filter_state(*params, grid, pl, Q, (hipStream_t)hip_stream);
+}
+
+int rk_step_filtered(const nse_params *params, const nopcs_grid *grid, int precision, double *Q, double dt,
+                     int32_t nsteps, int32_t filter_every, double alpha_f, void *ws, size_t ws_bytes,
+                     void *hip_stream) {
+    if (!check_grid(grid) || !check_params(params) || !check_filter_alpha(alpha_f)) return NOPCS_EINVAL;
+    if (filter_every < 0) { set_error("filter_every must be >= 0"); return NOPCS_EINVAL; }
+    if (nsteps < 0) { set_error("nsteps must be >= 0"); return NOPCS_EINVAL; }
+    LinePlanDev pl[3];
+    int rc = get_filter_plans(grid, alpha_f, pl);
+    if (rc != NOPCS_OK) return rc;
+    int done = 0;
+    while (done < nsteps) {
+        const int chunk = filter_every > 0 ? std::min(nsteps - done, filter_every) : nsteps - done;
+        rc = rk_step(params, grid, precision, Q, dt, chunk, ws, ws_bytes, hip_stream);
+        if (rc != NOPCS_OK) return rc;
+        done += chunk;
+        if (filter_every > 0 && chunk == filter_every) {
+            rc = filter_state(*params, grid, pl, Q, (hipStream_t)hip_stream);
+            if (rc != NOPCS_OK) return rc;
+        }
+    }
+    return NOPCS_OK;
+}
+
 int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, double *Q, double dt, int32_t nsteps,
                             void *ws, size_t ws_bytes, void *hip_stream) {
     if (!check_grid(grid) || !check_params(params)) return NOPCS_EINVAL;
@@ -729,11 +837,11 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
 // One graph for a batch of boxes: the RK4 step of every box is captured as its
 // own branch (a private stream forked from the capture stream and joined back),
 // so one replay runs all boxes and the device overlaps the branches.
-static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
-                       const LinePlanDev (*pl)[3], int nsteps, hipStream_t st) {
+static int batch_graph_branches(const nse_params &params, int nbox, const nopcs_box *boxes, int precision,
+                                double dt, const LinePlanDev (*pl)[3], int nsteps, hipStream_t st) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
-    std::string key = "batch";
+    std::string key = "batch-branches";
     put_bytes(key, dev);
     put_bytes(key, params);
     put_bytes(key, precision);
@@ -742,6 +850,7 @@ static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxe
         put_bytes(key, boxes[b].grid);
         put_bytes(key, boxes[b].Q);
         put_bytes(key, boxes[b].ws);
+        put_bytes(key, boxes[b].dt);
         for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, boxes[b].grid.n[d]));
     }
     std::lock_guard<std::mutex> lk(g_gmu);
@@ -773,7 +882,8 @@ static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxe
     for (int b = 0; b < nbox && rc == NOPCS_OK && he == hipSuccess; ++b) {
         he = hipStreamWaitEvent(bs[b], ev[nbox], 0);
         if (he != hipSuccess) break;
-        rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dt, boxes[b].ws, pl[b], bs[b]);
+        const double dtb = boxes[b].dt > 0.0 ? boxes[b].dt : dt;
+        rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dtb, boxes[b].ws, pl[b], bs[b]);
         if (rc != NOPCS_OK) break;
         he = hipEventRecord(ev[b], bs[b]);
         if (he == hipSuccess) he = hipStreamWaitEvent(cs, ev[b], 0);
@@ -789,6 +899,114 @@ static int batch_graph(const nse_params &params, int nbox, const nopcs_box *boxe
     const int ri = instantiate(e);
     if (ri != NOPCS_OK) return ri;
     return replay(g_graph_cache[key] = e, nsteps, st);
+}
+
+// How a batch of boxes is stepped: 0 (default) one launch per kernel and
+// configuration over all boxes (batch.hpp), captured as a graph; 1 one graph
+// branch per box, each box's launches as rk_step makes them (kept for
+// comparison); 2 the launches of mode 0 issued directly, without a graph.
+static std::atomic<int> g_batch_mode{0};
+
+// The batched RK4 step of a set of boxes: every box's launches are collected
+// by phase (launch_step with a collector), each (phase, kernel) becomes one
+// launch over a device table of the boxes' arguments, and the sequence is
+// captured once as a graph (cached per batch: boxes, states, workspaces, dt,
+// parameters, precision, piece lengths) and replayed nsteps times.
+static int batch_graph_launches(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
+                                const LinePlanDev (*pl)[3], int nsteps, hipStream_t st, bool graph) {
+    int dev = 0;
+    NOPCS_HIP_CHECK(hipGetDevice(&dev));
+    std::string key = graph ? "batch-launches" : "batch-direct";
+    put_bytes(key, dev);
+    put_bytes(key, params);
+    put_bytes(key, precision);
+    put_bytes(key, dt);
+    for (int b = 0; b < nbox; ++b) {
+        put_bytes(key, boxes[b].grid);
+        put_bytes(key, boxes[b].Q);
+        put_bytes(key, boxes[b].ws);
+        put_bytes(key, boxes[b].dt);
+        for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, boxes[b].grid.n[d]));
+    }
+    std::lock_guard<std::mutex> lk(g_gmu);
+    auto it = g_graph_cache.find(key);
+    if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
+    evict_if_full();
+    // collect every box's launches (nothing is launched), phase by phase
+    BatchCollector col;
+    for (int b = 0; b < nbox; ++b) {
+        const double dtb = boxes[b].dt > 0.0 ? boxes[b].dt : dt;
+        const int rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dtb, boxes[b].ws, pl[b], nullptr,
+                                   nullptr, &col);
+        if (rc != NOPCS_OK) return rc;
+    }
+    // one device buffer holds every table, each 256-byte aligned
+    size_t bytes = 0;
+    for (auto &ph : col.phases)
+        for (BatchLaunch &L : ph.second) {
+            L.dev_off = bytes;
+            bytes = (bytes + L.items.size() + 255) & ~(size_t)255;
+        }
+    std::vector<unsigned char> host(bytes, 0);
+    for (auto &ph : col.phases)
+        for (BatchLaunch &L : ph.second) std::memcpy(host.data() + L.dev_off, L.items.data(), L.items.size());
+    GraphEntry e;
+    NOPCS_HIP_CHECK(hipMalloc(&e.tables, bytes));
+    if (hipMemcpy(e.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(e.tables);
+        set_error("upload of the batch tables failed");
+        return NOPCS_EDEVICE;
+    }
+    if (!graph) {
+        for (auto &ph : col.phases)
+            for (BatchLaunch &L : ph.second) {
+                e.launches.push_back(L);
+                e.launches.back().items.clear();
+            }
+        if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipFree(e.tables);
+            set_error("hipEventCreateWithFlags failed");
+            return NOPCS_EDEVICE;
+        }
+        return replay(g_graph_cache[key] = e, nsteps, st);
+    }
+    hipStream_t &cs = g_capture_stream[dev];
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(e.tables);
+        set_error("hipStreamCreateWithFlags failed");
+        return NOPCS_EDEVICE;
+    }
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+        for (auto &ph : col.phases) {
+            for (BatchLaunch &L : ph.second) {
+                he = L.launch(static_cast<char *>(e.tables) + L.dev_off, L.ntab, L.total, L.blk, cs);
+                if (he != hipSuccess) break;
+            }
+            if (he != hipSuccess) break;
+        }
+        const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
+        if (he == hipSuccess) he = ec;
+    }
+    if (he != hipSuccess) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        (void)hipFree(e.tables);
+        set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he));
+        return NOPCS_EDEVICE;
+    }
+    void *tables = e.tables;
+    const int ri = instantiate(e);
+    if (ri != NOPCS_OK) {
+        (void)hipFree(tables);
+        return ri;
+    }
+    return replay(g_graph_cache[key] = e, nsteps, st);
+}
+
+int nopcs_set_batch_mode(int32_t mode) {
+    if (mode < 0 || mode > 2) { set_error("batch mode must be 0, 1 or 2"); return NOPCS_EINVAL; }
+    g_batch_mode.store(mode);
+    return NOPCS_OK;
 }
 
 int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes, int precision, double dt,
@@ -810,6 +1028,10 @@ int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes
             return NOPCS_EINVAL;
         }
         if (!check_ws(&x.grid, precision, x.ws, x.ws_bytes)) return NOPCS_EINVAL;
+        if (!(x.dt >= 0.0) || !std::isfinite(x.dt)) {
+            set_error("box " + std::to_string(b) + ": dt must be finite and >= 0 (0: the call's dt)");
+            return NOPCS_EINVAL;
+        }
         for (int c = 0; c < b; ++c)
             if (boxes[c].Q == x.Q || boxes[c].ws == x.ws) {
                 set_error("boxes " + std::to_string(c) + " and " + std::to_string(b) + " share a state or workspace");
@@ -823,7 +1045,10 @@ int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes
         if (rc != NOPCS_OK) return rc;
     }
     if (nsteps == 0) return NOPCS_OK;
-    return batch_graph(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream);
+    const int mode = g_batch_mode.load();
+    if (mode == 1)
+        return batch_graph_branches(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream);
+    return batch_graph_launches(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream, mode == 0);
 }
 
 int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,

@@ -1,6 +1,7 @@
 // kernels.hpp -- kernel argument blocks and host launchers of libnopcs.
 #pragma once
 
+#include "batch.hpp"
 #include "common.hpp"
 #include "plan.hpp"
 #include "sweep.hpp"
@@ -38,14 +39,19 @@ int sweep_lines_per_block(int dir, int n);
 int sweep_threads_per_block(int dir, int n);
 int sweep_known_rows_max(int n);
 
+// Every stepping launcher below either launches for one box or, given a
+// collector, adds its box to phase `phase` of a batched step (batch.hpp).
 hipError_t launch_deriv(int dir, const double *f, double *d1, double *d2, const SweepGeom &g, const LinePlanDev &pl,
                         hipStream_t st);
+// implicit filter of one field along dir with a filter plan (out may equal f)
+hipError_t launch_filter(int dir, const double *f, double *out, const SweepGeom &g, const LinePlanDev &pl,
+                         hipStream_t st);
 // R <- R - D_dir(convective flux) for the 5 components (one launch per direction)
 hipError_t launch_nse_sweep(int dir, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
-                            hipStream_t st);
+                            hipStream_t st, BatchCollector *col = nullptr, int phase = 0);
 
 // RK4 register update of stage a.stage from R (point-wise over 5 fields)
-hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st);
+hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st, BatchCollector *col = nullptr, int phase = 0);
 
 // Line-march sweeps along y (dir 1) and z (dir 2): geometry of the lines.
 struct MarchGeom {
@@ -56,20 +62,39 @@ struct MarchGeom {
 bool march_usable(int dir, const LinePlanDev &pl);
 // doubles of the closure array of one march sweep
 size_t march_closure_elems(const int n[3], int dir, int ncl);
+// Arguments of the line-march kernels (one box).
+struct ClosureArgs {
+    const double *Q;
+    double *clo;
+    MarchGeom g;
+    LinePlanDev pl;
+    NdConst c;
+};
+struct MarchArgs {
+    const double *Q;
+    void *R;          // FP64 or FP32, as the kernel instantiation says
+    const double *clo;
+    MarchGeom g;
+    LinePlanDev pl;
+    NdConst c;
+    RkFuse F;
+};
 // closure rows of the 5 convective flux components along dir into clo
 // (march_closure_elems doubles); nothing to do without closure rows
 hipError_t launch_march_closures(int dir, const double *Q, double *clo, const int n[3], const LinePlanDev &pl,
-                                 const NdConst &c, hipStream_t st);
+                                 const NdConst &c, hipStream_t st, BatchCollector *col = nullptr, int phase = 0);
 // R <- R - D_dir(convective flux) for the 5 components, closures from clo;
 // r32: R is stored in FP32; c32: the elimination runs in FP32
 hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
-                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk = nullptr);
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk = nullptr,
+                             BatchCollector *col = nullptr, int phase = 0);
 
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
-                       hipStream_t st);
+                       hipStream_t st, BatchCollector *col = nullptr, int phase = 0);
 
 // Wall conditions on one face pair (dir 0, 1, 2) of state Q.
-hipError_t launch_bc(double *Q, const int n[3], int dir, const NdConst &c, hipStream_t st);
+hipError_t launch_bc(double *Q, const int n[3], int dir, const NdConst &c, hipStream_t st,
+                     BatchCollector *col = nullptr, int phase = 0);
 
 }  // namespace nopcs

@@ -62,8 +62,10 @@ __device__ inline double flux_row(const double (*L)[MW], int lane, int comp, con
 }
 
 // Rows [row0, rowN] of the block's MW lines pass through a two-chunk LDS ring
-// and are read strictly in order through next().
-template <int CH>
+// and are read strictly in order through next().  PF chunks are in flight in
+// registers while the block works on the chunk in LDS (PF = 2 measured slower
+// than 1 for both marches).
+template <int CH, int PF = 1>
 struct RowPipe {
     double (*L)[CH][NCOMP][MW];   // [2][CH][field][lane]
     const double *src;            // this thread's field at row 0 of its line (a valid
@@ -71,46 +73,52 @@ struct RowPipe {
     long long sD;
     int row0, rowN, lane, field;
     int u, k;                     // next row to read: slot u of chunk k
-    double pre[CH];               // next chunk, in flight
+    double pre[PF][CH];           // the next PF chunks, in flight
     // unconditional loads (no branches: the compiler's memory waits stay
     // precise); rows past rowN repeat row rowN and are never used.  The row
     // offset steps by sD (a uniform select stops it at rowN).
-    __device__ void fetch(int rb) {
+    __device__ void fetch(int rb, double (&dst)[CH]) {
         long long off = sD * min(rb, rowN);
 #pragma unroll
         for (int v = 0; v < CH; ++v) {
-            pre[v] = src[off];
+            dst[v] = src[off];
             off += rb + v < rowN ? sD : 0;
         }
     }
     // field 0 (density) is published as 1/rho, the only form flux_row uses
-    __device__ void publish(int buf) {
+    __device__ void publish(double (&val)[CH], int buf) {
         if (field == 0) {
 #pragma unroll
-            for (int v = 0; v < CH; ++v) pre[v] = 1.0 / pre[v];
+            for (int v = 0; v < CH; ++v) val[v] = 1.0 / val[v];
         }
 #pragma unroll
-        for (int v = 0; v < CH; ++v) L[buf][v][field][lane] = pre[v];
+        for (int v = 0; v < CH; ++v) L[buf][v][field][lane] = val[v];
     }
-    // before the first read: chunk 0 in LDS, chunk 1 in flight
+    // before the first read: chunk 0 in LDS, chunks 1 .. PF in flight
     __device__ void start() {
-        fetch(row0);
-        publish(0);
-        fetch(row0 + CH);
+        double c0[CH];
+        fetch(row0, c0);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) fetch(row0 + (p + 1) * CH, pre[p]);
+        publish(c0, 0);
         u = 0;
         k = 0;
         __syncthreads();
     }
     // staged fields of the next row; the first read of chunk k >= 1 publishes
-    // it and starts fetching chunk k + 1 (uniform: every wavefront of the
+    // it and starts fetching chunk k + PF (uniform: every wavefront of the
     // block reads the same rows)
     __device__ const double (*next())[MW] {
         if (u == CH) {
             u = 0;
             ++k;
-            publish(k & 1);
+            publish(pre[0], k & 1);
             __syncthreads();
-            fetch(row0 + (k + 1) * CH);
+#pragma unroll
+            for (int p = 0; p + 1 < PF; ++p)
+#pragma unroll
+                for (int v = 0; v < CH; ++v) pre[p][v] = pre[p + 1][v];
+            fetch(row0 + (k + PF) * CH, pre[PF - 1]);
         }
         NOPCS_LDS_BOUND(u, CH);
         NOPCS_LDS_BOUND(k * CH + u, rowN - row0 + 1 + CH);
@@ -122,10 +130,9 @@ struct RowPipe {
 // Closure pass
 // ---------------------------------------------------------------------------
 template <int DIR, int S>
-__global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__restrict__ Q, double *__restrict__ clo,
-                                                              MarchGeom g, LinePlanDev pl, NdConst c) {
+__device__ inline void closure_march_body(const double *__restrict__ Q, double *__restrict__ clo, const MarchGeom &g,
+                                          const LinePlanDev &pl, const NdConst &c, int b) {
     __shared__ double L[2][CHC][NCOMP][MW];
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int xc = b % g.nxc, o = b / g.nxc;
     const int lane = threadIdx.x;
     const int x = xc * MW + lane;
@@ -197,6 +204,125 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
     }
 }
 
+// Closure pass with one thread per line: each thread streams its own line,
+// loads the 5 state fields of a row itself, forms the 5 flux components and
+// accumulates every slot of every component in registers -- no LDS, no
+// barriers; the fields of the next CPL rows are in flight in registers.  The
+// arithmetic (1/rho, the flux products, each slot's sum in row order) is that
+// of k_closure_march, so the closure values are the same bit for bit.  Used for
+// plans of at most 8 slots (5 x 8 accumulators).
+constexpr int CLW = 128;   // lines per block
+constexpr int CPL = 4;     // rows in flight per thread
+
+template <int DIR>
+__device__ inline void closure_line_body(const double *__restrict__ Q, double *__restrict__ clo, const MarchGeom &g,
+                                         const LinePlanDev &pl, const NdConst &c, int b) {
+    constexpr int S = 8;
+    const int nxb = (g.nx + CLW - 1) / CLW;
+    const int xc = b % nxb, o = b / nxb;
+    const int x = xc * CLW + (int)threadIdx.x;
+    const bool ok = x < g.nx;
+    const long long base = (ok ? x : 0) + g.sO * o;
+    const long long nlines = (long long)g.nx * g.no;
+    const long long line = x + (long long)g.nx * o;
+    const auto cl_j0 = NOPCS_SCALAR_PTR(int, pl.cl_j0);
+    const auto cl_len = NOPCS_SCALAR_PTR(int, pl.cl_len);
+    const auto k1_rec = NOPCS_SCALAR_PTR(int, pl.k1_rec);
+    const auto k1_w = NOPCS_SCALAR_PTR(double, pl.k1_w);
+    const auto cl_wsum = NOPCS_SCALAR_PTR(double, pl.cl_wsum);
+    const auto ev_row = NOPCS_SCALAR_PTR(int, pl.k1_evrow);
+    const auto ev_msk = NOPCS_SCALAR_PTR(int, pl.k1_evmask);
+    const int jlo = cl_j0[0];
+    const int jhi = cl_j0[pl.ncl - 1] + cl_len[pl.ncl - 1] - 1;
+    const long long sD = g.sD, N3 = g.N3;
+    // the 5 fields of row j (rows past jhi repeat jhi; unconditional loads)
+    auto load = [&](int j, double (&q)[NCOMP]) {
+        const long long off = base + sD * min(j, jhi);
+#pragma unroll
+        for (int f = 0; f < NCOMP; ++f) q[f] = Q[f * N3 + off];
+    };
+    // the 5 flux components of a row (the products of flux_row)
+    auto fluxes = [&](const double (&q)[NCOMP], double (&fx)[NCOMP]) {
+        const double ri = 1.0 / q[0];
+        const double mx = q[1], my = q[2], mz = q[3], Ep = q[4];
+        const double md = DIR == 1 ? my : mz;
+        const double u = mx * ri, v = my * ri, w = mz * ri;
+        const double ke = 0.5 * (mx * u + my * v + mz * w);
+        const double pp = (c.gamma - 1.0) * (Ep - ke);
+        const double ud = DIR == 1 ? v : w;
+        const double uo = md * ri;   // the form flux_row uses for the passive components
+        fx[0] = md;
+        fx[1] = mx * uo;
+        fx[2] = DIR == 1 ? md * ud + pp : my * uo;
+        fx[3] = DIR == 2 ? md * ud + pp : mz * uo;
+        fx[4] = ((Ep + pp) + c.H) * ud;
+    };
+    double acc[NCOMP][S];
+#pragma unroll
+    for (int k = 0; k < NCOMP; ++k)
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[k][s] = 0.0;
+    double fref[NCOMP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double ring[CPL][NCOMP];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) load(jlo + u, ring[u]);
+    int e = 0;
+    int jev = ev_row[0];   // the first event row is jlo (a slot opens there)
+    for (int j0 = jlo; j0 <= jhi; j0 += CPL) {
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int j = j0 + u;
+            double q[NCOMP];
+#pragma unroll
+            for (int f = 0; f < NCOMP; ++f) q[f] = ring[u][f];
+            load(j + CPL, ring[u]);
+            if (j > jhi) continue;   // uniform
+            double fx[NCOMP];
+            fluxes(q, fx);
+            const auto wj = k1_w + (size_t)j * S;
+            if (j != jev) {
+#pragma unroll
+                for (int k = 0; k < NCOMP; ++k) {
+                    const double gk = fx[k] - fref[k];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) acc[k][s] = fma_(wj[s], gk, acc[k][s]);
+                }
+                continue;
+            }
+            // event row: slots open, meet their closure row or close here
+            if (e == 0) {
+#pragma unroll
+                for (int k = 0; k < NCOMP; ++k) fref[k] = fx[k];
+            }
+            const int open = ev_msk[3 * e], erow = ev_msk[3 * e + 1], close = ev_msk[3 * e + 2];
+            const auto rec = k1_rec + (size_t)j * S;
+#pragma unroll
+            for (int k = 0; k < NCOMP; ++k) {
+                const double gk = fx[k] - fref[k];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (open & (1 << s)) acc[k][s] = 0.0;
+                    acc[k][s] = fma_(wj[s], gk, acc[k][s]);
+                    if (erow & (1 << s)) acc[k][s] = acc[k][s] - gk * cl_wsum[rec[s] & 0xfff];
+                }
+            }
+            if (close) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (close & (1 << s)) {
+                        const int qi = rec[s] & 0xfff;
+#pragma unroll
+                        for (int k = 0; k < NCOMP; ++k)
+                            if (ok) clo[((long long)k * pl.ncl + qi) * nlines + line] = acc[k][s] * pl.ih;
+                    }
+                }
+            }
+            ++e;
+            jev = e < pl.k1_nev ? ev_row[e] : -1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Run march
 // ---------------------------------------------------------------------------
@@ -205,13 +331,12 @@ __global__ __launch_bounds__(MW *NCOMP) void k_closure_march(const double *__res
 // RKS >= 0: RK4 stage RKS fused into the epilogue, see RkFuse (R and the
 // elimination both FP64, or both FP32).
 template <int DIR, bool FULL, class TR, class TC, int RKS>
-__global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restrict__ Q, TR *R,
-                                                            const double *__restrict__ clo, MarchGeom g,
-                                                            LinePlanDev pl, NdConst c, RkFuse F) {
+__device__ inline void march_sweep_body(const double *__restrict__ Q, TR *R, const double *__restrict__ clo,
+                                        const MarchGeom &g, const LinePlanDev &pl, const NdConst &c, const RkFuse &F,
+                                        int b) {
     static_assert(RKS < 0 || sizeof(TR) == sizeof(TC), "the fused RK update: FP64 or mixed precision");
     __shared__ double L[2][CHM][NCOMP][MW];
     __shared__ double KV[2 * kGroupRuns][NCOMP][MW];   // closure values bounding the group's runs
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int xc = b % g.nxc, rest = b / g.nxc, o = rest % g.no, grp = rest / g.no;
     const int lane = threadIdx.x;
     const int x = xc * MW + lane;
@@ -313,6 +438,24 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
         }
         constexpr int RB = 4;
         auto rrow = [&](int t) { return sD * (lo + 1 + (t < m ? t : m - 1)); };
+        // the known rows this run may update (rows outside lo+1 .. hi-1)
+        const long long klo = sD * lo, khi = sD * hi, kn = sD * (n - 1);
+        auto known_rows = [&]() {
+            const double rlo = double(Rc[klo]), rhi = double(Rc[khi]), r0 = double(Rc[0]), rn = double(Rc[kn]);
+            const double klo_k = RKS > 0 ? Kc[klo] : 0.0, khi_k = RKS > 0 ? Kc[khi] : 0.0;
+            const double k0_k = RKS > 0 ? Kc[0] : 0.0, kn_k = RKS > 0 ? Kc[kn] : 0.0;
+            const double qlo = Nc[klo], qhi = Nc[khi], q0 = Nc[0], qnn = Nc[kn];
+            if (ok) {
+                if (own & 1) rk_point(klo, rlo, klo_k, qlo, xlo);
+                if (own & 2) rk_point(khi, rhi, khi_k, qhi, xhi);
+                if (own & 4) rk_point(0, r0, k0_k, q0, v0);
+                if (own & 8) rk_point(kn, rn, kn_k, qnn, vn);
+            }
+        };
+        // the known rows first, so that their operands do not stay live through
+        // the row loop (each row is read and written by this thread only; this
+        // keeps the FP64 stage kernels within their registers, without spills)
+        known_rows();
         double fr[RB], fk[RB], fq[RB];
 #pragma unroll
         for (int t = 0; t < RB; ++t) {
@@ -320,12 +463,6 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
             fk[t] = RKS > 0 ? Kc[rrow(t)] : 0.0;
             fq[t] = Nc[rrow(t)];
         }
-        // the known rows this run may update (rows outside lo+1 .. hi-1)
-        const long long klo = sD * lo, khi = sD * hi, kn = sD * (n - 1);
-        const double rlo = double(Rc[klo]), rhi = double(Rc[khi]), r0 = double(Rc[0]), rn = double(Rc[kn]);
-        const double klo_k = RKS > 0 ? Kc[klo] : 0.0, khi_k = RKS > 0 ? Kc[khi] : 0.0;
-        const double k0_k = RKS > 0 ? Kc[0] : 0.0, kn_k = RKS > 0 ? Kc[kn] : 0.0;
-        const double qlo = Nc[klo], qhi = Nc[khi], q0 = Nc[0], qnn = Nc[kn];
 #pragma unroll
         for (int t = 0; t < MRL; ++t) {
             const double rv = fr[t % RB], kk = fk[t % RB], qn = fq[t % RB];
@@ -335,12 +472,6 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
                 fq[t % RB] = Nc[rrow(t + RB)];
             }
             if (ok && t < m) rk_point(rrow(t), rv, kk, qn, double(d[t]));
-        }
-        if (ok) {
-            if (own & 1) rk_point(klo, rlo, klo_k, qlo, xlo);
-            if (own & 2) rk_point(khi, rhi, khi_k, qhi, xhi);
-            if (own & 4) rk_point(0, r0, k0_k, q0, v0);
-            if (own & 8) rk_point(kn, rn, kn_k, qnn, vn);
         }
     };
 
@@ -421,6 +552,28 @@ __global__ __launch_bounds__(MW *NCOMP) void k_march_sweep(const double *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Kernels: one box (block b of its own grid) or a batch of boxes (a walk over
+// a table of boxes, see batch.hpp); both run the bodies above.
+// ---------------------------------------------------------------------------
+template <int DIR, int S>
+struct ClosureMarchBody {
+    using Args = ClosureArgs;
+    __device__ static void run(const Args &a, int b, int) { closure_march_body<DIR, S>(a.Q, a.clo, a.g, a.pl, a.c, b); }
+};
+template <int DIR>
+struct ClosureLineBody {
+    using Args = ClosureArgs;
+    __device__ static void run(const Args &a, int b, int) { closure_line_body<DIR>(a.Q, a.clo, a.g, a.pl, a.c, b); }
+};
+template <int DIR, bool FULL, class TR, class TC, int RKS>
+struct MarchBody {
+    using Args = MarchArgs;
+    __device__ static void run(const Args &a, int b, int) {
+        march_sweep_body<DIR, FULL, TR, TC, RKS>(a.Q, static_cast<TR *>(a.R), a.clo, a.g, a.pl, a.c, a.F, b);
+    }
+};
+
 }  // namespace
 
 bool march_usable(int dir, const LinePlanDev &pl) {
@@ -454,71 +607,66 @@ MarchGeom march_geom(const int n[3], int dir) {
 }
 
 hipError_t launch_march_closures(int dir, const double *Q, double *clo, const int n[3], const LinePlanDev &pl,
-                                 const NdConst &c, hipStream_t st) {
+                                 const NdConst &c, hipStream_t st, BatchCollector *col, int phase) {
     if (pl.ncl == 0) return hipSuccess;
-    const MarchGeom g = march_geom(n, dir);
-    const dim3 blk(MW, NCOMP), grd((unsigned)(g.nxc * g.no));
-    if (dir == 1 && pl.k1_S == 8) hipLaunchKernelGGL((k_closure_march<1, 8>), grd, blk, 0, st, Q, clo, g, pl, c);
-    else if (dir == 1) hipLaunchKernelGGL((k_closure_march<1, kMaxSlots>), grd, blk, 0, st, Q, clo, g, pl, c);
-    else if (dir == 2 && pl.k1_S == 8) hipLaunchKernelGGL((k_closure_march<2, 8>), grd, blk, 0, st, Q, clo, g, pl, c);
-    else if (dir == 2) hipLaunchKernelGGL((k_closure_march<2, kMaxSlots>), grd, blk, 0, st, Q, clo, g, pl, c);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    const ClosureArgs a{Q, clo, march_geom(n, dir), pl, c};
+    // at most 8 slots: one thread per line; 16 slots: the LDS ring pass
+    if (pl.k1_S == 8) {
+        const int blocks = ((a.g.nx + CLW - 1) / CLW) * a.g.no;
+        if (dir == 1) return run_body<ClosureLineBody<1>, CLW>(a, blocks, dim3(CLW), st, col, phase);
+        if (dir == 2) return run_body<ClosureLineBody<2>, CLW>(a, blocks, dim3(CLW), st, col, phase);
+        return hipErrorInvalidValue;
+    }
+    const int blocks = a.g.nxc * a.g.no;
+    const dim3 blk(MW, NCOMP);
+    if (dir == 1) return run_body<ClosureMarchBody<1, kMaxSlots>, MW * NCOMP>(a, blocks, blk, st, col, phase);
+    if (dir == 2) return run_body<ClosureMarchBody<2, kMaxSlots>, MW * NCOMP>(a, blocks, blk, st, col, phase);
+    return hipErrorInvalidValue;
 }
 
-template <class TR, class TC>
-static hipError_t launch_runs_t(int dir, const double *Q, TR *R, const double *clo, const MarchGeom &g,
-                                const LinePlanDev &pl, const NdConst &c, hipStream_t st) {
-    const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
-    const bool full = g.nx % MW == 0;
-    const RkFuse F{};
-    if (dir == 1 && full) hipLaunchKernelGGL((k_march_sweep<1, true, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    else if (dir == 1) hipLaunchKernelGGL((k_march_sweep<1, false, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    else if (dir == 2 && full) hipLaunchKernelGGL((k_march_sweep<2, true, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    else if (dir == 2) hipLaunchKernelGGL((k_march_sweep<2, false, TR, TC, -1>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+// the run march of one instantiation for one box (or added to a batch)
+template <int DIR, class TR, class TC, int RKS>
+static hipError_t march_go(const MarchArgs &a, hipStream_t st, BatchCollector *col, int phase) {
+    const int blocks = (int)((long long)a.g.nxc * a.g.no * a.pl.ngrp);
+    const dim3 blk(MW, NCOMP);
+    if (a.g.nx % MW == 0)   // FULL: every lane holds a line
+        return run_body<MarchBody<DIR, true, TR, TC, RKS>, MW * NCOMP>(a, blocks, blk, st, col, phase);
+    return run_body<MarchBody<DIR, false, TR, TC, RKS>, MW * NCOMP>(a, blocks, blk, st, col, phase);
 }
 
-// z sweep with the RK4 stage update fused (T: R and the elimination, FP64 or FP32)
-template <int S, class T>
-static hipError_t launch_runs_rk(const double *Q, T *R, const double *clo, const MarchGeom &g,
-                                 const LinePlanDev &pl, const NdConst &c, const RkFuse &F, hipStream_t st) {
-    const dim3 blk(MW, NCOMP), grd((unsigned)((long long)g.nxc * g.no * pl.ngrp));
-    if (g.nx % MW == 0)
-        hipLaunchKernelGGL((k_march_sweep<2, true, T, T, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    else
-        hipLaunchKernelGGL((k_march_sweep<2, false, T, T, S>), grd, blk, 0, st, Q, R, clo, g, pl, c, F);
-    return hipGetLastError();
+template <class T>
+static hipError_t march_rk_go(const MarchArgs &a, int stage, hipStream_t st, BatchCollector *col, int phase) {
+    switch (stage) {
+        case 0: return march_go<2, T, T, 0>(a, st, col, phase);
+        case 1: return march_go<2, T, T, 1>(a, st, col, phase);
+        case 2: return march_go<2, T, T, 2>(a, st, col, phase);
+        case 3: return march_go<2, T, T, 3>(a, st, col, phase);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c32, const double *clo, const int n[3],
-                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk) {
-    const MarchGeom g = march_geom(n, dir);
+                             const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk,
+                             BatchCollector *col, int phase) {
+    MarchArgs a{Q, R, clo, march_geom(n, dir), pl, c, RkFuse{}};
     if (rk) {
+        // z sweep with the RK4 stage update fused (R and the elimination both
+        // FP64 or both FP32)
         if (dir != 2 || r32 != c32) return hipErrorInvalidValue;
-        if (r32) {
-            float *Rf = static_cast<float *>(R);
-            switch (rk->stage) {
-                case 0: return launch_runs_rk<0, float>(Q, Rf, clo, g, pl, c, *rk, st);
-                case 1: return launch_runs_rk<1, float>(Q, Rf, clo, g, pl, c, *rk, st);
-                case 2: return launch_runs_rk<2, float>(Q, Rf, clo, g, pl, c, *rk, st);
-                case 3: return launch_runs_rk<3, float>(Q, Rf, clo, g, pl, c, *rk, st);
-                default: return hipErrorInvalidValue;
-            }
-        }
-        double *Rd = static_cast<double *>(R);
-        switch (rk->stage) {
-            case 0: return launch_runs_rk<0, double>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 1: return launch_runs_rk<1, double>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 2: return launch_runs_rk<2, double>(Q, Rd, clo, g, pl, c, *rk, st);
-            case 3: return launch_runs_rk<3, double>(Q, Rd, clo, g, pl, c, *rk, st);
-            default: return hipErrorInvalidValue;
-        }
+        a.F = *rk;
+        return r32 ? march_rk_go<float>(a, rk->stage, st, col, phase) : march_rk_go<double>(a, rk->stage, st, col, phase);
     }
-    if (!c32) return launch_runs_t<double, double>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
-    if (!r32) return launch_runs_t<double, float>(dir, Q, static_cast<double *>(R), clo, g, pl, c, st);
-    return launch_runs_t<float, float>(dir, Q, static_cast<float *>(R), clo, g, pl, c, st);
+    if (dir == 1) {
+        if (!c32) return march_go<1, double, double, -1>(a, st, col, phase);
+        if (!r32) return march_go<1, double, float, -1>(a, st, col, phase);
+        return march_go<1, float, float, -1>(a, st, col, phase);
+    }
+    if (dir == 2) {
+        if (!c32) return march_go<2, double, double, -1>(a, st, col, phase);
+        if (!r32) return march_go<2, double, float, -1>(a, st, col, phase);
+        return march_go<2, float, float, -1>(a, st, col, phase);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nopcs

@@ -28,32 +28,48 @@ std::vector<int> even_segments(int n, int nseg) {
     return lo;
 }
 
-// Column j of the global C = A^-1 B (h = 1), in long double: solve A x = B e_j.
-static void global_column(int n, int j, std::vector<long double> &x, std::vector<long double> &work) {
-    const long double a = kAlpha, b1 = kB1, b2 = kB2;
+// Column j of the global C = A^-1 B (h = 1) of operator op, in long double:
+// solve A x = B e_j.
+static void global_column(int n, int j, int op, double alpha_f, std::vector<long double> &x,
+                          std::vector<long double> &work) {
+    const long double a = op == OP_FILTER ? (long double)alpha_f : (long double)kAlpha;
     std::vector<long double> &rhs = x;
     std::fill(rhs.begin(), rhs.end(), 0.0L);
     auto put = [&](int row, long double v) {
         if (row >= 0 && row < n) rhs[row] += v;
     };
     // B e_j: entries B_{i,j} of every row i that touches column j
-    if (j <= 2) {  // row 0: (-3/2, 2, -1/2) on columns 0..2
-        const long double w0[3] = {-1.5L, 2.0L, -0.5L};
-        put(0, w0[j]);
-    }
-    if (j == 0) put(1, -0.5L);
-    if (j == 2) put(1, 0.5L);
-    for (int i = j - 2; i <= j + 2; ++i) {
-        if (i < 2 || i > n - 3) continue;
-        const int k = j - i;
-        const long double v = k == -2 ? -b2 : k == -1 ? -b1 : k == 1 ? b1 : k == 2 ? b2 : 0.0L;
-        put(i, v);
-    }
-    if (j == n - 3) put(n - 2, -0.5L);
-    if (j == n - 1) put(n - 2, 0.5L);
-    if (j >= n - 3) {  // row n-1: (1/2, -2, 3/2) on columns n-3..n-1
-        const long double w1[3] = {0.5L, -2.0L, 1.5L};
-        put(n - 1, w1[j - (n - 3)]);
+    if (op == OP_FILTER) {
+        // wall rows 0, 1, n-2, n-1 are the identity (left unfiltered); interior
+        // rows a0 f_i + a1/2 (f_{i+1} + f_{i-1}) + a2/2 (f_{i+2} + f_{i-2})
+        const long double af = alpha_f;
+        const long double a0 = 5.0L / 8.0L + 0.75L * af, a1h = 0.5L * (0.5L + af), a2h = 0.5L * (-0.125L + 0.25L * af);
+        if (j <= 1 || j >= n - 2) put(j, 1.0L);
+        for (int i = j - 2; i <= j + 2; ++i) {
+            if (i < 2 || i > n - 3) continue;
+            const int k = j - i < 0 ? i - j : j - i;
+            put(i, k == 0 ? a0 : k == 1 ? a1h : a2h);
+        }
+    } else {
+        const long double b1 = kB1, b2 = kB2;
+        if (j <= 2) {  // row 0: (-3/2, 2, -1/2) on columns 0..2
+            const long double w0[3] = {-1.5L, 2.0L, -0.5L};
+            put(0, w0[j]);
+        }
+        if (j == 0) put(1, -0.5L);
+        if (j == 2) put(1, 0.5L);
+        for (int i = j - 2; i <= j + 2; ++i) {
+            if (i < 2 || i > n - 3) continue;
+            const int k = j - i;
+            const long double v = k == -2 ? -b2 : k == -1 ? -b1 : k == 1 ? b1 : k == 2 ? b2 : 0.0L;
+            put(i, v);
+        }
+        if (j == n - 3) put(n - 2, -0.5L);
+        if (j == n - 1) put(n - 2, 0.5L);
+        if (j >= n - 3) {  // row n-1: (1/2, -2, 3/2) on columns n-3..n-1
+            const long double w1[3] = {0.5L, -2.0L, 1.5L};
+            put(n - 1, w1[j - (n - 3)]);
+        }
     }
     // rows 0, 1, n-2, n-1 are explicit: x equals rhs there.  Rows 2..n-3:
     // a x_{i-1} + x_i + a x_{i+1} = rhs_i with x_1 and x_{n-2} known.
@@ -104,7 +120,7 @@ std::vector<uint8_t> row_kinds(int n, int nseg, int sub_len) {
     return kind;
 }
 
-bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string &err) {
+bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string &err, int op, double alpha_f) {
     if (n < 8) {
         err = "line length must be >= 8 (got " + std::to_string(n) + ")";
         return false;
@@ -114,7 +130,13 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
               ", nseg=" + std::to_string(nseg) + ")";
         return false;
     }
+    if (op == OP_FILTER && !(alpha_f > -0.5 && alpha_f < 0.5)) {
+        err = "filter coefficient must lie in (-0.5, 0.5) (diagonally dominant system)";
+        return false;
+    }
     P = LinePlanHost();
+    P.op = op;
+    P.alpha = op == OP_FILTER ? alpha_f : kAlpha;
     P.n = n;
     P.nseg = nseg;
     P.sub_len = sub_len;
@@ -143,7 +165,7 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
             for (int e : rows)
                 if (j >= e - kNb && j <= e + kNb) { needed = true; break; }
             if (!needed) continue;
-            global_column(n, j, col, work);
+            global_column(n, j, op, alpha_f, col, work);
             for (int q = 0; q < ncl; ++q) {
                 const int e = rows[q];
                 if (j < e - kNb || j > e + kNb) continue;
@@ -174,11 +196,11 @@ bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &P, std::string 
     P.cp.assign(n + 1, 0.0);
     double cprev = 0.0;
     for (int k = 1; k <= n; ++k) {
-        const double s = (k > 1) ? kAlpha : 0.0;
+        const double s = (k > 1) ? P.alpha : 0.0;
         const double den = 1.0 - s * cprev;
         P.den[k] = den;
         P.rden[k] = 1.0 / den;
-        P.cp[k] = kAlpha / den;
+        P.cp[k] = P.alpha / den;
         cprev = P.cp[k];
     }
     build_march_tables(P);
@@ -273,17 +295,19 @@ struct PlanEntry {
     LinePlanDev dev{};
 };
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, uint64_t>, PlanEntry> g_plans;
+std::map<std::tuple<int, int, int, int, uint64_t, int, uint64_t>, PlanEntry> g_plans;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
-int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only) {
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only, int op,
+                  double alpha_f) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
-    uint64_t lbits;
+    uint64_t lbits, abits = 0;
     std::memcpy(&lbits, &len, sizeof lbits);
-    const auto key = std::make_tuple(dev, n, nseg, sub_len, lbits);
+    if (op == OP_FILTER) std::memcpy(&abits, &alpha_f, sizeof abits);
+    const auto key = std::make_tuple(dev, n, nseg, sub_len, lbits, op, abits);
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
@@ -297,7 +321,7 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bo
     }
     LinePlanHost P;
     std::string err;
-    if (!build_line_plan(n, nseg, sub_len, P, err)) {
+    if (!build_line_plan(n, nseg, sub_len, P, err, op, alpha_f)) {
         set_error(err);
         return NOPCS_EINVAL;
     }
@@ -399,6 +423,9 @@ int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bo
     for (int t = 0; t < ntab; ++t) tab[t] = static_cast<unsigned char *>(buf) + tab_off[t];
 #endif
     LinePlanDev d;
+    d.op = op;
+    d.alpha = P.alpha;
+    d.fc = filter_coefs(op == OP_FILTER ? alpha_f : 0.0);
     d.n = n;
     d.nrun = nrun;
     d.ncl = ncl;

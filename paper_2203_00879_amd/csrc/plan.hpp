@@ -11,8 +11,29 @@ namespace nopcs {
 // Row kinds of one line.
 enum : uint8_t { ROW_COMPACT = 0, ROW_WALL = 1, ROW_CLOSURE = 2 };
 
+// Line operators with a plan: the OUCS3 first derivative (Section 3) and the
+// implicit low-pass filter (Section 4; fourth-order tridiagonal compact filter
+// with coefficient alpha_f, wall rows unfiltered).
+enum : int { OP_D1 = 0, OP_FILTER = 1 };
+
+// Right-hand side of the filter: af fh_{i-1} + fh_i + af fh_{i+1} =
+// a0 f_i + (a1/2)(f_{i+1} + f_{i-1}) + (a2/2)(f_{i+2} + f_{i-2}), fourth order.
+struct FilterCoefs {
+    double a0, a1h, a2h;   // a0, a1 / 2, a2 / 2
+};
+inline FilterCoefs filter_coefs(double af) {
+    FilterCoefs c;
+    c.a0 = 5.0 / 8.0 + 0.75 * af;
+    c.a1h = 0.5 * (0.5 + af);
+    c.a2h = 0.5 * (-1.0 / 8.0 + 0.25 * af);
+    return c;
+}
+
 // Device view of a line plan (passed by value to kernels).
 struct LinePlanDev {
+    int op;                // OP_D1 or OP_FILTER
+    double alpha;          // off-diagonal of A (kAlpha, or the filter's alpha_f)
+    FilterCoefs fc;        // OP_FILTER: right-hand side coefficients
     int n;                 // points on the line
     int nrun;              // Thomas runs (maximal sets of compact rows between known rows)
     int ncl;               // closure rows
@@ -53,6 +74,8 @@ constexpr int kMaxSlots = 16;
 
 // Host description (kept for tests and for building the device copy).
 struct LinePlanHost {
+    int op = OP_D1;
+    double alpha = kAlpha;
     int n = 0, nseg = 0, sub_len = 0;
     std::vector<int> seg_lo;          // user segment starts
     std::vector<int2> runs, run_slot;
@@ -75,7 +98,8 @@ constexpr int kGroupRuns = 4;
 // Build the plan of a line of n points cut into nseg user segments; each user
 // segment is further cut into pieces of at most sub_len points (0 = no extra cuts).
 // Returns false with an error message on invalid input.
-bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &out, std::string &err);
+bool build_line_plan(int n, int nseg, int sub_len, LinePlanHost &out, std::string &err, int op = OP_D1,
+                     double alpha_f = 0.0);
 
 // Kind of every row of a line of n points cut into nseg user segments and
 // pieces of at most sub_len points (host only; valid n, nseg assumed).
@@ -87,7 +111,8 @@ std::vector<int> even_segments(int n, int nseg);
 // Cached device plan for (device, n, nseg, sub_len, len) -> LinePlanDev, built
 // (and its device memory allocated) on first use; lookup_only: never build,
 // NOPCS_EINVAL if the plan is not cached yet.
-int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only = false);
+int get_line_plan(int n, int nseg, int sub_len, double len, LinePlanDev *out, bool lookup_only = false,
+                  int op = OP_D1, double alpha_f = 0.0);
 
 // Free all cached device plans of the current device.
 void release_line_plans();

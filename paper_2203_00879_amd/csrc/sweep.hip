@@ -6,15 +6,20 @@ namespace nopcs {
 
 namespace {
 
-// pencil of this block: first line, valid lines, base element offset
+// pencil `pencil` of a sweep: first line, valid lines, base element offset
 template <class C>
-__device__ inline void pencil_of(const SweepGeom &g, int &np, long long &base) {
+__device__ inline void pencil_at(const SweepGeom &g, int pencil, int &np, long long &base) {
     const int npa = (g.nA + C::P - 1) / C::P;
-    const int pencil = xcd_swizzle(blockIdx.x, gridDim.x);
     const int pa = pencil % npa, pb = pencil / npa;
     const int l0 = pa * C::P;
     np = min(C::P, g.nA - l0);
     base = (long long)l0 * g.sA + (long long)pb * g.sB;
+}
+
+// pencil of this block (single-box launches)
+template <class C>
+__device__ inline void pencil_of(const SweepGeom &g, int &np, long long &base) {
+    pencil_at<C>(g, xcd_swizzle(blockIdx.x, gridDim.x), np, base);
 }
 
 template <class C>
@@ -87,6 +92,38 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
 }
 
 // ---------------------------------------------------------------------------
+// Implicit filter along DIR of one field, in place (out may equal f: a block
+// reads its whole pencil before it writes any of it, and pencils are disjoint).
+// ---------------------------------------------------------------------------
+template <int DIR, int NMAX>
+__global__ __launch_bounds__(256) void k_filter(const double *f, double *out, SweepGeom g, LinePlanDev pl) {
+    constexpr int PW = deriv_pencil_width<DIR, NMAX>();
+    using C = SweepCfg<DIR, NMAX, PW>;
+    __shared__ double F[C::FSZ];
+    __shared__ double KN[C::P * C::KMAX];
+    int np;
+    long long base;
+    pencil_of<C>(g, np, base);
+    const int n = g.n;
+    int ks[C::PTS];
+    owned_slots<DIR, NMAX, PW>(pl, ks);
+#pragma unroll
+    for (int s = 0; s < C::PTS; ++s) {
+        int l, i;
+        C::owned(threadIdx.x + s * C::NT, l, i);
+        if (l < np && i < n) F[C::fidx(l, i)] = f[base + l * g.sA + i * g.sD];
+    }
+    __syncthreads();
+    lds_line_solve<DIR, NMAX, 1, PW, OP_FILTER>(F, KN, pl, np);
+#pragma unroll
+    for (int s = 0; s < C::PTS; ++s) {
+        int l, i;
+        C::owned(threadIdx.x + s * C::NT, l, i);
+        if (l < np && i < n) out[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Convective sweep along DIR: R_c <- R_c - D_DIR(flux_c) for the 5 flux
 // components of ge3-ge5, staged C::G components at a time.
 // ---------------------------------------------------------------------------
@@ -137,13 +174,13 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
 }  // namespace
 
 template <int DIR, int NMAX, class TR>
-__global__ __launch_bounds__(256) void k_nse_sweep(NseSweepArgs a, SweepGeom g, LinePlanDev pl) {
+__device__ inline void nse_sweep_body(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, int b) {
     using C = SweepCfg<DIR, NMAX>;
     __shared__ double F[C::G * C::FSZ];
     __shared__ double KN[C::G * C::P * C::KMAX];
     int np;
     long long base;
-    pencil_of<C>(g, np, base);
+    pencil_at<C>(g, b, np, base);
     const int n = g.n;
     const long long N3 = a.N3;
     const NdConst &c = a.c;
@@ -204,15 +241,15 @@ template <> struct Pair<double> { using T = double2; };
 template <> struct Pair<float> { using T = float2; };
 
 template <int STAGE, class TR>
-__global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long total) {
+__device__ inline void rk_update_body(const NseSweepArgs &a, long long total, int b, int nb) {
     const long long npair = total >> 1;
-    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long stride = (long long)nb * 256;
     const TR *const R = static_cast<const TR *>(a.R);
     const auto *R2 = reinterpret_cast<const typename Pair<TR>::T *>(R);
     double2 *K2 = reinterpret_cast<double2 *>(a.K);
     double2 *S2 = reinterpret_cast<double2 *>(a.Qs);
     double2 *N2 = reinterpret_cast<double2 *>(a.Qn);
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += stride) {
+    for (long long p = (long long)b * 256 + threadIdx.x; p < npair; p += stride) {
         const auto kr = R2[p];
         const double2 kv = make_double2(double(kr.x), double(kr.y));
         double2 kk = STAGE == 0 ? make_double2(0.0, 0.0) : K2[p];
@@ -227,7 +264,7 @@ __global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long tot
             N2[p] = qn;
         }
     }
-    if ((total & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((total & 1) && b == 0 && threadIdx.x == 0) {
         const long long o = total - 1;
         double kk = STAGE == 0 ? 0.0 : a.K[o], qs = 0.0, qn = a.Qn[o];
         rk_elem<STAGE>(double(R[o]), kk, qs, qn, a);
@@ -241,11 +278,31 @@ __global__ __launch_bounds__(256) void k_rk_update(NseSweepArgs a, long long tot
 }
 }  // namespace
 
+struct SweepArgs {
+    NseSweepArgs a;
+    SweepGeom g;
+    LinePlanDev pl;
+};
+template <int DIR, int NMAX, class TR>
+struct SweepBody {
+    using Args = SweepArgs;
+    __device__ static void run(const Args &x, int b, int) { nse_sweep_body<DIR, NMAX, TR>(x.a, x.g, x.pl, b); }
+};
+struct RkUpdArgs {
+    NseSweepArgs a;
+    long long total;
+};
+template <int STAGE, class TR>
+struct RkUpdBody {
+    using Args = RkUpdArgs;
+    __device__ static void run(const Args &x, int b, int nb) { rk_update_body<STAGE, TR>(x.a, x.total, b, nb); }
+};
+
 // Classical RK4 register update of one stage (Section 4), point-wise over the
 // 5 fields:  k = R;  stage 0: K = k, Qs = Qn + dt/2 k;  stage 1: K += 2k,
 // Qs = Qn + dt/2 k;  stage 2: K += 2k, Qs = Qn + dt k;  stage 3:
 // Qn = Qn + dt/6 (K + k).
-hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st) {
+hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st, BatchCollector *col, int phase) {
     const long long total = 5 * a.N3;
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.R) | reinterpret_cast<uintptr_t>(a.K) |
                            reinterpret_cast<uintptr_t>(a.Qs) | reinterpret_cast<uintptr_t>(a.Qn)) & 15) == 0;
@@ -253,23 +310,23 @@ hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st) {
     long long blocks = ((total >> 1) + 255) / 256;
     if (blocks > 256 * 32) blocks = 256 * 32;
     if (blocks < 1) blocks = 1;
-    const dim3 g((unsigned)blocks), b(256);
+    const RkUpdArgs x{a, total};
+    const int nb = (int)blocks;
+    const dim3 blk(256);
     if (a.r32) {
         switch (a.stage) {
-            case 0: hipLaunchKernelGGL((k_rk_update<0, float>), g, b, 0, st, a, total); break;
-            case 1: hipLaunchKernelGGL((k_rk_update<1, float>), g, b, 0, st, a, total); break;
-            case 2: hipLaunchKernelGGL((k_rk_update<2, float>), g, b, 0, st, a, total); break;
-            default: hipLaunchKernelGGL((k_rk_update<3, float>), g, b, 0, st, a, total); break;
-        }
-    } else {
-        switch (a.stage) {
-            case 0: hipLaunchKernelGGL((k_rk_update<0, double>), g, b, 0, st, a, total); break;
-            case 1: hipLaunchKernelGGL((k_rk_update<1, double>), g, b, 0, st, a, total); break;
-            case 2: hipLaunchKernelGGL((k_rk_update<2, double>), g, b, 0, st, a, total); break;
-            default: hipLaunchKernelGGL((k_rk_update<3, double>), g, b, 0, st, a, total); break;
+            case 0: return run_body<RkUpdBody<0, float>, 256>(x, nb, blk, st, col, phase);
+            case 1: return run_body<RkUpdBody<1, float>, 256>(x, nb, blk, st, col, phase);
+            case 2: return run_body<RkUpdBody<2, float>, 256>(x, nb, blk, st, col, phase);
+            default: return run_body<RkUpdBody<3, float>, 256>(x, nb, blk, st, col, phase);
         }
     }
-    return hipGetLastError();
+    switch (a.stage) {
+        case 0: return run_body<RkUpdBody<0, double>, 256>(x, nb, blk, st, col, phase);
+        case 1: return run_body<RkUpdBody<1, double>, 256>(x, nb, blk, st, col, phase);
+        case 2: return run_body<RkUpdBody<2, double>, 256>(x, nb, blk, st, col, phase);
+        default: return run_body<RkUpdBody<3, double>, 256>(x, nb, blk, st, col, phase);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -286,15 +343,24 @@ static hipError_t launch_deriv_t(const double *f, double *d1, double *d2, const 
 }
 
 template <int DIR, int NMAX>
-static hipError_t launch_sweep_t(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, hipStream_t st) {
-    using C = SweepCfg<DIR, NMAX>;
+static hipError_t launch_filter_t(const double *f, double *out, const SweepGeom &g, const LinePlanDev &pl,
+                                  hipStream_t st) {
+    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>()>;
     const int npa = (g.nA + C::P - 1) / C::P;
     const long long blocks = (long long)npa * g.nB;
-    if (a.r32)
-        hipLaunchKernelGGL((k_nse_sweep<DIR, NMAX, float>), dim3((unsigned)blocks), dim3(C::NT), 0, st, a, g, pl);
-    else
-        hipLaunchKernelGGL((k_nse_sweep<DIR, NMAX, double>), dim3((unsigned)blocks), dim3(C::NT), 0, st, a, g, pl);
+    hipLaunchKernelGGL((k_filter<DIR, NMAX>), dim3((unsigned)blocks), dim3(C::NT), 0, st, f, out, g, pl);
     return hipGetLastError();
+}
+
+template <int DIR, int NMAX>
+static hipError_t launch_sweep_t(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, hipStream_t st,
+                                 BatchCollector *col, int phase) {
+    using C = SweepCfg<DIR, NMAX>;
+    const int npa = (g.nA + C::P - 1) / C::P;
+    const int blocks = (int)((long long)npa * g.nB);
+    const SweepArgs x{a, g, pl};
+    if (a.r32) return run_body<SweepBody<DIR, NMAX, float>, C::NT>(x, blocks, dim3(C::NT), st, col, phase);
+    return run_body<SweepBody<DIR, NMAX, double>, C::NT>(x, blocks, dim3(C::NT), st, col, phase);
 }
 
 int nmax_class(int n) {
@@ -342,12 +408,22 @@ hipError_t launch_deriv(int dir, const double *f, double *d1, double *d2, const 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_nse_sweep(int dir, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
-                            hipStream_t st) {
+hipError_t launch_filter(int dir, const double *f, double *out, const SweepGeom &g, const LinePlanDev &pl,
+                         hipStream_t st) {
+    if (pl.op != OP_FILTER) return hipErrorInvalidValue;
     const int nm = nmax_class(g.n);
-    if (dir == 0) { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<0, NMX>(a, g, pl, st))); }
-    else if (dir == 1) { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<1, NMX>(a, g, pl, st))); }
-    else { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<2, NMX>(a, g, pl, st))); }
+    if (dir == 0) { NOPCS_NMAX_SWITCH(nm, return (launch_filter_t<0, NMX>(f, out, g, pl, st))); }
+    else if (dir == 1) { NOPCS_NMAX_SWITCH(nm, return (launch_filter_t<1, NMX>(f, out, g, pl, st))); }
+    else { NOPCS_NMAX_SWITCH(nm, return (launch_filter_t<2, NMX>(f, out, g, pl, st))); }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_nse_sweep(int dir, const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl,
+                            hipStream_t st, BatchCollector *col, int phase) {
+    const int nm = nmax_class(g.n);
+    if (dir == 0) { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<0, NMX>(a, g, pl, st, col, phase))); }
+    else if (dir == 1) { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<1, NMX>(a, g, pl, st, col, phase))); }
+    else { NOPCS_NMAX_SWITCH(nm, return (launch_sweep_t<2, NMX>(a, g, pl, st, col, phase))); }
     return hipErrorInvalidValue;
 }
 

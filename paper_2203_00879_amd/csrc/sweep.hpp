@@ -80,15 +80,27 @@ inline SweepGeom sweep_geom(const int n[3], int dir) {
 // Phases A and C for NC components staged in F[c] (FP64).  Known-row values
 // land in KN(c)[slot * P + l].  All threads of the block call it; it ends with
 // a barrier; f' is then in F (compact rows) and KN (known rows).
-template <int DIR, int NMAX, int NC, int PW = 0>
+// OP = OP_FILTER applies the plan's implicit filter instead of the first
+// derivative: closure rows f_e + sum_j C_ej (f_j - f_e) (the filter's rows sum
+// to 1), wall rows unfiltered, interior right-hand side
+// a0 f_i + a1/2 (f_{i+1} + f_{i-1}) + a2/2 (f_{i+2} + f_{i-2}), A = (af, 1, af).
+template <int DIR, int NMAX, int NC, int PW = 0, int OP = OP_D1>
 __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev &pl, int np) {
     using C = SweepCfg<DIR, NMAX, PW>;
     constexpr int KS = C::P * C::KMAX;
     auto F = [&](int c) -> double * { return Fb + c * C::FSZ; };
     auto KN = [&](int c) -> double * { return KNb + c * KS; };
+    constexpr bool FILT = OP == OP_FILTER;
     const int tid = threadIdx.x;
     const int n = pl.n;
     const double ih = pl.ih;
+    const double alpha = FILT ? pl.alpha : kAlpha;
+    const double fa0 = pl.fc.a0, fa1 = pl.fc.a1h, fa2 = pl.fc.a2h;
+    // interior right-hand side of row i from the window f_{i-2} .. f_{i+2}
+    auto rhs5 = [&](double w0, double w1, double w2, double w3, double w4) {
+        if constexpr (FILT) return fa0 * w2 + fa1 * (w1 + w3) + fa2 * (w0 + w4);
+        else return ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+    };
     // plan tables through the scalar path where the index is wave-uniform
     const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
     const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
@@ -152,7 +164,9 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
                     }
                 }
             }
-            v = (a0 + a1) * ih;
+            v = FILT ? fe + (a0 + a1) : (a0 + a1) * ih;
+        } else if (FILT) {
+            v = f[C::fidx(l, s == 0 ? 0 : s == 1 ? 1 : s == 2 ? n - 2 : n - 1)];
         } else if (s == 0) {
             const double f0 = f[C::fidx(l, 0)];
             v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
@@ -195,8 +209,8 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         double dprev;
         {
             const double fn = f[C::fidx(l, min(lo + 4, hi + 1))];
-            double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
-            rr = rr - kAlpha * xlo;
+            double rr = rhs5(w0, w1, w2, w3, w4);
+            rr = rr - alpha * xlo;
             dprev = rr * rden[1];
             f[C::fidx(l, lo + 1)] = dprev;
             w0 = w1;
@@ -211,7 +225,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             const int i = lo + k;
             const double fn = f[C::fidx(l, min(i + 3, hi + 1))];
             const double cpn = cp[k + 1], rdn = rden[k + 1];
-            const double rr = ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+            const double rr = rhs5(w0, w1, w2, w3, w4);
             const double dp = fma_(-cpk, dprev, rr * rdk);
             f[C::fidx(l, i)] = dp;
             dprev = dp;
@@ -223,7 +237,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             w3 = w4;
             w4 = fn;
         }
-        dprev = fma_(-kAlpha * xhi, pl.rden[m], dprev);
+        dprev = fma_(-alpha * xhi, pl.rden[m], dprev);
         f[C::fidx(l, lo + m)] = dprev;
         // backward: x_m = d_m, x_k = d_k - c'_k x_{k+1}; k runs from the plan's
         // longest run down, lanes of shorter runs wait until k < m

@@ -261,8 +261,7 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
 }
 
 template <class TR>
-__global__ __launch_bounds__(CNT) void k_visc(VArgs A) {
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+__device__ inline void visc_body(const VArgs &A, int b) {
     const int tt = b % A.ntx, rest = b / A.ntx, ty = rest % A.nty, tz = rest / A.nty;
     const int own_i = tt * CTX, own_j = ty * CTY;
     const int i0 = min(own_i, max(0, A.nx - CTX));
@@ -292,10 +291,16 @@ __global__ __launch_bounds__(CNT) void k_visc(VArgs A) {
     if (interior) visc_march<false, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
     else visc_march<true, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
 }
+
+template <class TR>
+struct ViscBody {
+    using Args = VArgs;
+    __device__ static void run(const Args &a, int b, int) { visc_body<TR>(a, b); }
+};
 }  // namespace
 
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
-                       hipStream_t st) {
+                       hipStream_t st, BatchCollector *col, int phase) {
     VArgs A;
     A.Q = Q;
     A.R = R;
@@ -311,22 +316,31 @@ hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const
     A.ihz = ih[2];
     A.c = c;
     const int ntz = (n[2] + A.zc - 1) / A.zc;
-    const long long blocks = (long long)A.ntx * A.nty * ntz;
-    if (r32) hipLaunchKernelGGL(k_visc<float>, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
-    else hipLaunchKernelGGL(k_visc<double>, dim3((unsigned)blocks), dim3(CNT), 0, st, A);
-    return hipGetLastError();
+    const int blocks = (int)((long long)A.ntx * A.nty * ntz);
+    if (r32) return run_body<ViscBody<float>, CNT>(A, blocks, dim3(CNT), st, col, phase);
+    return run_body<ViscBody<double>, CNT>(A, blocks, dim3(CNT), st, col, phase);
 }
 
 // ---------------------------------------------------------------------------
 // Wall conditions of the closed adiabatic box (Section 2), one face pair.
 // ---------------------------------------------------------------------------
 namespace {
-__global__ void k_bc(double *Q, int nx, int ny, int nz, int dir, long long N3, NdConst c) {
+struct BcArgs {
+    double *Q;
+    int nx, ny, nz, dir;
+    long long N3;
+    NdConst c;
+};
+__device__ inline void bc_body(const BcArgs &A, int blk) {
+    double *const Q = A.Q;
+    const int nx = A.nx, ny = A.ny, nz = A.nz, dir = A.dir;
+    const long long N3 = A.N3;
+    const NdConst &c = A.c;
     const int n[3] = {nx, ny, nz};
     const long long st[3] = {1, nx, (long long)nx * ny};
     const int a = dir == 0 ? 1 : 0, bb = dir == 2 ? 1 : 2;
     const long long nface = (long long)n[a] * n[bb];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blk * 256 + threadIdx.x;
     if (t >= 2 * nface) return;
     const int side = t >= nface ? 1 : 0;
     const long long l = t - side * nface;
@@ -345,15 +359,19 @@ __global__ void k_bc(double *Q, int nx, int ny, int nz, int dir, long long N3, N
     Q[3 * N3 + o] = 0.0;
     Q[4 * N3 + o] = (rho * c.Rh * Tw - c.Rh) / (c.gamma - 1.0);
 }
+struct BcBody {
+    using Args = BcArgs;
+    // every node of the face pair is independent: block b takes nodes 256 b ..
+    __device__ static void run(const Args &a, int b, int) { bc_body(a, b); }
+};
 }  // namespace
 
-hipError_t launch_bc(double *Q, const int n[3], int dir, const NdConst &c, hipStream_t st) {
+hipError_t launch_bc(double *Q, const int n[3], int dir, const NdConst &c, hipStream_t st, BatchCollector *col,
+                     int phase) {
     const int a = dir == 0 ? 1 : 0, b = dir == 2 ? 1 : 2;
     const long long tot = 2LL * n[a] * n[b];
-    const int nt = 256;
-    hipLaunchKernelGGL(k_bc, dim3((unsigned)((tot + nt - 1) / nt)), dim3(nt), 0, st, Q, n[0], n[1], n[2], dir,
-                       (long long)n[0] * n[1] * n[2], c);
-    return hipGetLastError();
+    const BcArgs x{Q, n[0], n[1], n[2], dir, (long long)n[0] * n[1] * n[2], c};
+    return run_body<BcBody, 256>(x, (int)((tot + 255) / 256), dim3(256), st, col, phase);
 }
 
 }  // namespace nopcs

@@ -42,10 +42,11 @@ class Params(ctypes.Structure):
 
 
 class Box(ctypes.Structure):
-    _fields_ = [("grid", Grid), ("Q", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
+    _fields_ = [("grid", Grid), ("Q", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("dt", ctypes.c_double)]
 
 
-MAX_BATCH = 16
+MAX_BATCH = 64
 
 
 class SolverConfig(ctypes.Structure):
@@ -87,6 +88,9 @@ def lib():
         L.nopcs_derivative.argtypes = [ctypes.POINTER(Grid), _I, _I, _V, _V, _V, _V]
         L.nse_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V, ctypes.c_size_t, _V]
         L.nse_rhs_noalloc.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, _V]
+        L.nopcs_filter.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), ctypes.c_double, _V, _V]
+        L.rk_step_filtered.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _V, ctypes.c_size_t, _V]
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
         L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
@@ -101,6 +105,7 @@ def lib():
                                               ctypes.c_size_t, _V]
         L.rk_step_batch.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(Box), _I, ctypes.c_double,
                                     ctypes.c_int32, _V]
+        L.nopcs_set_batch_mode.argtypes = [ctypes.c_int32]
         L.rk_step_compact_viscous.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, ctypes.c_double,
                                               ctypes.c_int32, _V, ctypes.c_size_t, _V]
         L.nopcs_vorticity_workspace_bytes.restype = ctypes.c_size_t
@@ -209,6 +214,22 @@ def nse_rhs(params, grid, Q, R, precision=FP64, ws=None, stream=None):
                          nbytes, _stream(stream)))
 
 
+FILTER_ALPHA = 0.135   # filtering coefficient of Section 4
+
+
+def nopcs_filter(params, grid, Q, alpha_f=FILTER_ALPHA, stream=None):
+    """The implicit 3D filter of a device state Q, in place."""
+    _check(lib().nopcs_filter(ctypes.byref(params), ctypes.byref(grid), float(alpha_f), _ptr(Q), _stream(stream)))
+
+
+def rk_step_filtered(params, grid, Q, dt, nsteps, ws, filter_every=50, alpha_f=FILTER_ALPHA, precision=FP64,
+                     stream=None):
+    """rk_step with the implicit filter after every filter_every-th step."""
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().rk_step_filtered(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), float(dt),
+                                  int(nsteps), int(filter_every), float(alpha_f), _ptr(ws), nbytes, _stream(stream)))
+
+
 NOALLOC_SCRATCH_BYTES = 64 << 20   # NOPCS_NOALLOC_SCRATCH_BYTES
 
 
@@ -238,16 +259,24 @@ def nse_rhs_compact_viscous(params, grid, Q, R, ws=None, stream=None):
 
 
 def rk_step_batch(params, boxes, dt, nsteps, precision=FP64, stream=None):
-    """rk_step for a batch of boxes [(grid, Q, ws), ...] replayed as one graph
-    with a branch per box."""
+    """rk_step for a batch of boxes [(grid, Q, ws) or (grid, Q, ws, dt_box), ...]
+    (one launch per stage kernel over all boxes, replayed as one graph)."""
     arr = (Box * len(boxes))()
-    for i, (grid, Q, ws) in enumerate(boxes):
+    for i, box in enumerate(boxes):
+        grid, Q, ws = box[:3]
         arr[i].grid = grid
         arr[i].Q = Q.data_ptr()
         arr[i].ws = ws.data_ptr()
         arr[i].ws_bytes = ws.numel() * ws.element_size()
+        arr[i].dt = float(box[3]) if len(box) > 3 else 0.0
     _check(lib().rk_step_batch(ctypes.byref(params), len(boxes), arr, int(precision), float(dt), int(nsteps),
                                _stream(stream)))
+
+
+def set_batch_mode(mode):
+    """0: one launch per stage kernel over all boxes, as a graph (default); 1: one graph
+    branch per box; 2: the launches of 0 issued directly (no graph)."""
+    _check(lib().nopcs_set_batch_mode(int(mode)))
 
 
 def rk_step_compact_viscous(params, grid, Q, dt, nsteps, ws, stream=None):

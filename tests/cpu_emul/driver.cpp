@@ -3,8 +3,11 @@
 //   driver deriv nx ny nz sx sy sz lx ly lz dir  in out        (in: N, out: d1 then d2)
 //   driver rhs   nx ny nz sx sy sz lx ly lz viscous gravity in out   (in/out: 5N)
 //   driver rk    nx ny nz sx sy sz lx ly lz viscous gravity dt nsteps in out
+//   driver filter nx ny nz sx sy sz lx ly lz af every dt nsteps in out  (nopcs_filter if nsteps is 0,
+//                                                              else rk_step_filtered; in/out: 5N)
 //   driver plan  n nseg piece_len                            (prints the line-march tables)
 //   driver serve                                              (scripted checks of the serving runtime)
+//   driver batch                       (batched stepping of uneven boxes against each box's lone step)
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction;
 // NOPCS_EMUL_PRECISION=1 runs rhs and rk in mixed precision.
 #include <chrono>
@@ -204,6 +207,100 @@ static int serve_checks() {
     return 0;
 }
 
+// a smooth state on an nx x ny x nz box (as test_state, any shape)
+static std::vector<double> box_state(const int n[3], int seed) {
+    const size_t N = (size_t)n[0] * n[1] * n[2];
+    std::vector<double> q(5 * N);
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                const size_t o = i + (size_t)n[0] * (j + (size_t)n[1] * k);
+                const double a = 0.3 * (seed + 1), x = (double)i / (n[0] - 1), y = (double)j / (n[1] - 1),
+                             z = (double)k / (n[2] - 1);
+                q[o] = 1.0 + 0.05 * std::sin(6.0 * x + a) * std::cos(5.0 * y - a) * std::sin(4.0 * z + 1.0);
+                q[N + o] = 0.01 * std::sin(3.0 * y + a) * x * (1 - x);
+                q[2 * N + o] = 0.01 * std::cos(2.0 * z - a) * y * (1 - y);
+                q[3 * N + o] = 0.01 * std::sin(4.0 * x + 2 * a) * z * (1 - z);
+                q[4 * N + o] = 50.0 * std::cos(3.0 * x - a) * std::sin(2.0 * y + z);
+            }
+    return q;
+}
+
+// Batched stepping (rk_step_batch, direct launches) of uneven boxes against
+// rk_step on each box alone: every box bit for bit.
+static int batch_checks(int prec) {
+    struct Shape { int n[3], s[3]; double dt; };
+    const Shape shapes[] = {{{8, 8, 8}, {1, 1, 1}, 1e-5},
+                            {{16, 12, 10}, {2, 1, 1}, 2e-5},
+                            {{16, 12, 10}, {2, 1, 1}, 0.0},   // the call's dt
+                            {{40, 33, 37}, {1, 2, 3}, 1e-5},
+                            {{9, 70, 11}, {1, 2, 1}, 3e-5}};
+    const int nb = sizeof shapes / sizeof shapes[0], nsteps = 2;
+    const double dt_call = 1.5e-5;
+    nse_params p = air_params();
+    std::vector<nopcs_grid> g(nb);
+    std::vector<std::vector<double>> q0(nb), ref(nb);
+    std::vector<Buf *> Q(nb), W(nb);
+    std::vector<size_t> wsb(nb), n5(nb);
+    for (int b = 0; b < nb; ++b) {
+        for (int d = 0; d < 3; ++d) {
+            g[b].n[d] = shapes[b].n[d];
+            g[b].nseg[d] = shapes[b].s[d];
+            g[b].len[d] = 1.0 + 0.25 * d;
+        }
+        n5[b] = 5 * (size_t)g[b].n[0] * g[b].n[1] * g[b].n[2];
+        wsb[b] = nopcs_workspace_bytes(&g[b], prec);
+        q0[b] = box_state(g[b].n, b);
+        Q[b] = new Buf(n5[b]);
+        W[b] = new Buf((wsb[b] + 7) / 8);
+        std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+        const double dt = shapes[b].dt > 0 ? shapes[b].dt : dt_call;
+        if (rk_step(&p, &g[b], prec, Q[b]->p, dt, nsteps, W[b]->p, wsb[b], nullptr) != NOPCS_OK) {
+            std::fprintf(stderr, "lone rk_step failed: %s\n", nopcs_last_error());
+            return 1;
+        }
+        ref[b].assign(Q[b]->p, Q[b]->p + n5[b]);
+        std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+    }
+    std::vector<nopcs_box> boxes(nb);
+    for (int b = 0; b < nb; ++b) boxes[b] = nopcs_box{g[b], Q[b]->p, W[b]->p, wsb[b], shapes[b].dt};
+    int rc = nopcs_set_batch_mode(2);
+    for (int rep = 0; rep < 2 && rc == NOPCS_OK; ++rep) {   // the second call replays the cached launches
+        if (rep) for (int b = 0; b < nb; ++b) std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+        rc = rk_step_batch(&p, nb, boxes.data(), prec, dt_call, nsteps, nullptr);
+        for (int b = 0; b < nb && rc == NOPCS_OK; ++b) {
+            if (std::memcmp(Q[b]->p, ref[b].data(), n5[b] * sizeof(double)) != 0) {
+                size_t bad = 0;
+                while (Q[b]->p[bad] == ref[b][bad]) ++bad;
+                std::fprintf(stderr, "box %d differs from its lone step at %zu: %.17g vs %.17g\n", b, bad, Q[b]->p[bad],
+                             ref[b][bad]);
+                rc = 1;
+            }
+        }
+        if (rc == NOPCS_OK) std::printf("ok batch call %d: %d boxes bit-identical to their lone steps\n", rep, nb);
+    }
+    if (rc > 1) std::fprintf(stderr, "rk_step_batch failed: %d %s\n", rc, nopcs_last_error());
+    // errors: duplicate state, misaligned workspace, negative dt
+    if (rc == NOPCS_OK) {
+        std::vector<nopcs_box> bad = boxes;
+        bad[1].Q = bad[0].Q;
+        bad[1].grid = bad[0].grid;
+        if (rk_step_batch(&p, 2, bad.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
+        bad = boxes;
+        bad[0].ws = static_cast<char *>(bad[0].ws) + 8;
+        if (rk_step_batch(&p, 1, bad.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
+        bad = boxes;
+        bad[0].dt = -1.0;
+        if (rk_step_batch(&p, 1, bad.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
+        if (rk_step_batch(&p, 0, boxes.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
+        if (nopcs_set_batch_mode(3) != NOPCS_EINVAL) rc = 1;
+        std::printf(rc == NOPCS_OK ? "ok batch argument errors\n" : "batch argument errors not reported\n");
+    }
+    for (int b = 0; b < nb; ++b) { delete Q[b]; delete W[b]; }
+    nopcs_release_plans();
+    return rc == NOPCS_OK ? 0 : 1;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
@@ -216,6 +313,10 @@ int main(int argc, char **argv) {
         return 0;
     }
     if (mode == "serve") return serve_checks();
+    if (mode == "batch") {
+        const char *pe = std::getenv("NOPCS_EMUL_PRECISION");
+        return batch_checks(pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64);
+    }
     if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
     // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)
     if (const char *pc = std::getenv("NOPCS_EMUL_PIECE"))
@@ -287,6 +388,25 @@ int main(int argc, char **argv) {
             rc = nse_rhs_compact_viscous(&p, &g, Q.p, R.p, ws.p, wsb, nullptr);
             if (rc == 0) write_raw(argv[14], R.p, 5 * N);
         }
+    } else if (mode == "filter") {   // driver filter ... af every dt nsteps in out: nopcs_filter (nsteps 0) or
+                                     // rk_step_filtered
+        p.viscous = 1;
+        p.gravity = 1;
+        const double af = std::atof(argv[11]);
+        const int every = std::atoi(argv[12]);
+        const double dt = std::atof(argv[13]);
+        const int nsteps = std::atoi(argv[14]);
+        std::vector<double> Qh = read_raw(argv[15], 5 * N);
+        Buf Q(5 * N);
+        std::memcpy(Q.p, Qh.data(), 5 * N * sizeof(double));
+        if (nsteps == 0) {
+            rc = nopcs_filter(&p, &g, af, Q.p, nullptr);
+        } else {
+            const size_t wsb = nopcs_workspace_bytes(&g, prec);
+            Buf ws((wsb + 7) / 8);
+            rc = rk_step_filtered(&p, &g, prec, Q.p, dt, nsteps, every, af, ws.p, wsb, nullptr);
+        }
+        if (rc == 0) write_raw(argv[16], Q.p, 5 * N);
     } else if (mode == "vort") {
         std::vector<double> Qh = read_raw(argv[11], 5 * N);
         Buf Q(5 * N), out(12 * N);

@@ -62,7 +62,7 @@ inline void emu_guarded_free(void *p) {
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __restrict__
-#define __align__(n) alignas(n)
+#define __align__(n) __attribute__((aligned(n)))
 #define HIP_SYMBOL(X) X
 
 using std::max;

@@ -194,6 +194,22 @@ def test_emulated_serving_runtime(driver, tmp_path):
     assert "ok mix equals alone bit for bit" in r.stdout
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_emulated_batch_step(driver, tmp_path, mixed):
+    """rk_step_batch over five uneven boxes (one launch per stage kernel over all
+    boxes, issued directly; two boxes of one shape share every launch, one box
+    takes the call's dt, the others their own): each box bit-identical to
+    rk_step on it alone, on the first call and on the cached second; duplicate
+    states, misaligned workspaces, negative dt and an empty batch rejected."""
+    env = dict(os.environ)
+    if mixed:
+        env["NOPCS_EMUL_PRECISION"] = "1"
+    r = subprocess.run([driver, "batch"], capture_output=True, text=True, timeout=900, env=env)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "ok batch call 1: 5 boxes bit-identical to their lone steps" in r.stdout
+    assert "ok batch argument errors" in r.stdout
+
+
 def test_emulated_rhs_mixed_precision(driver, tmp_path):
     """Mixed precision (FP32 elimination along y and z, FP64 everything else)
     against the oracle's FP64 right-hand side.  Error budget: the FP32 runs see
@@ -279,3 +295,47 @@ def test_emulated_rk_step_compact_viscous(driver, tmp_path):
     for c in range(5):
         assert _rel(G[c], O[c]) <= 1e-12, c
         assert _rel(G[c] - Q[c], O[c] - Q[c]) <= 1e-9, c
+
+
+@pytest.mark.parametrize("shape, nseg, piece", [((27, 19, 22), (3, 2, 4), None), ((9, 130, 10), (1, 3, 1), None),
+                                                ((72, 20, 16), (2, 1, 2), 16)])
+def test_emulated_filter(driver, tmp_path, shape, nseg, piece):
+    """The implicit 3D filter (nopcs_filter) against the oracle's global line
+    solves, segmented lines (the second case's 130-point y lines are cut into
+    pieces), every point of all 5 fields."""
+    p = dict(inputs.AIR)
+    Q = inputs.smooth_state(shape, seed=13)
+    Q[1:4] += np.random.default_rng(2).normal(scale=1e-3, size=Q[1:4].shape)
+    qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
+    Q.tofile(qin)
+    _run(driver, ["filter", *shape, *nseg, 1.0, 1.0, 1.0, oracle.FILTER_ALPHA, 0, 0.0, 0, qin, qout], tmp_path,
+         piece=piece)
+    G = np.fromfile(qout).reshape(Q.shape)
+    O = oracle.filter_state(p, Q)
+    for c in range(5):
+        assert _rel(G[c], O[c]) <= 1e-12
+
+
+def test_emulated_filtered_stepping(driver, tmp_path):
+    """RK4 with the filter after every 2nd step (5 steps: filtered twice) on a
+    segmented box in motion, against the oracle, every point of all 5 fields.
+    (On a resting RTI box the momentum after a few steps is so small that the
+    filter's rounding of rho, ~1e-16 of rho, is 1e-12 of the momentum's
+    maximum: that case is checked on rho and E' only.)"""
+    p = dict(inputs.AIR)
+    shape = (20, 24, 18)
+    Q = inputs.smooth_state(shape, seed=6, amp_u=0.02)
+    qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
+    Q.tofile(qin)
+    _run(driver, ["filter", *shape, 2, 2, 1, 1.0, 1.0, 1.0, oracle.FILTER_ALPHA, 2, 2e-6, 5, qin, qout], tmp_path)
+    G = np.fromfile(qout).reshape(Q.shape)
+    O = oracle.rk4_filtered(p, Q, 2e-6, 5, every=2)
+    for c in range(5):
+        assert _rel(G[c], O[c]) <= 1e-12
+    Q = inputs.rti_state(shape, seed=6, noise_K=1.0)
+    Q.tofile(qin)
+    _run(driver, ["filter", *shape, 2, 2, 1, 1.0, 1.0, 1.0, oracle.FILTER_ALPHA, 2, 1e-5, 5, qin, qout], tmp_path)
+    G = np.fromfile(qout).reshape(Q.shape)
+    O = oracle.rk4_filtered(p, Q, 1e-5, 5, every=2)
+    for c in (0, 4):
+        assert _rel(G[c], O[c]) <= 1e-12

@@ -1,5 +1,6 @@
-"""GPU: RK4 stepping of a batch of uneven boxes replayed as one graph
-(rk_step_batch) gives every box exactly the result of rk_step on it alone."""
+"""GPU: RK4 stepping of a batch of uneven boxes (rk_step_batch: one launch per
+stage kernel over all boxes, as a graph or issued directly, or one graph
+branch per box) gives every box exactly the result of rk_step on it alone."""
 import sys
 
 import numpy as np
@@ -40,23 +41,35 @@ def lone(shape, nseg, seed, prec, dt, nsteps):
     return Q.cpu().numpy()
 
 
+@pytest.fixture
+def batch_mode(request):
+    nopcs.set_batch_mode(request.param)
+    yield request.param
+    nopcs.set_batch_mode(0)
+
+
+@pytest.mark.parametrize("batch_mode", [0, 1, 2], indirect=True)
 @pytest.mark.parametrize("prec", [nopcs.FP64, nopcs.MIXED])
-def test_batch_equals_lone_runs_bitwise_over_replays(prec):
-    """Four uneven boxes, 2 + 1 + 1 steps in three calls (the graph is captured
-    on the first and replayed after), with unrelated eager work in between."""
-    say("batch of", len(BOXES), "precision", prec)
-    dt = 1e-5
+def test_batch_equals_lone_runs_bitwise_over_replays(prec, batch_mode):
+    """Four uneven boxes plus a fifth of the second's shape (so launches hold
+    several boxes of one configuration), 2 + 1 + 1 steps in three calls (the
+    step is captured or collected on the first and replayed after), with
+    unrelated eager work in between; the fifth box takes its own dt."""
+    say("batch of", len(BOXES) + 1, "precision", prec, "mode", batch_mode)
+    dt, dt5 = 1e-5, 2.5e-5
     nopcs.lib().nopcs_set_graphs(0)
-    want = [lone(s, n, seed, prec, dt, 4) for s, n, seed in BOXES]
-    boxes = [make(s, n, seed, prec) for s, n, seed in BOXES]
+    specs = BOXES + [(BOXES[1][0], BOXES[1][1], 9)]
+    want = [lone(s, n, seed, prec, dt, 4) for s, n, seed in BOXES] + [lone(*specs[4], prec, dt5, 4)]
+    boxes = [make(s, n, seed, prec) for s, n, seed in specs]
+    boxes[4] = boxes[4] + (dt5,)
     prm = nopcs.make_params(P)
     junk = torch.ones(1 << 20, dtype=torch.float64, device=DEV)
     for k in (2, 1, 1):
         nopcs.rk_step_batch(prm, boxes, dt, k, precision=prec)
         junk.mul_(1.5).add_(1.0)
         torch.cuda.synchronize()
-    for (g, Q, ws), w, (shape, _, _) in zip(boxes, want, BOXES):
-        got = Q.cpu().numpy()
+    for box, w, (shape, _, _) in zip(boxes, want, specs):
+        got = box[1].cpu().numpy()
         say("  box", shape, "max diff", float(np.max(np.abs(got - w))))
         assert np.array_equal(got, w)
 
