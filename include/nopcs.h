@@ -322,18 +322,20 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
 /*
  * rk_step_batch -- rk_step for a batch of independent boxes of any sizes, all
  * with the same parameters and precision, each with its own dt (box.dt, or the
- * call's dt where box.dt is 0).  The RK4 step of all boxes runs as one launch
- * per stage kernel and configuration over all boxes: the blocks of a launch
- * take their (box, block) items from a device table of the boxes' arguments,
- * so a stage has about a dozen launches whatever the number of boxes.  The
- * step is captured once as a HIP graph (cached per batch: boxes, their states,
- * workspaces and dt, parameters, precision and piece lengths) and each of the
- * nsteps steps is one replay on hip_stream.  Every box gets exactly the result
- * of rk_step on it alone (its blocks run the single-box kernels' arithmetic).
- * 1 <= nbox <= NOPCS_MAX_BATCH; each box: a valid grid, Q 16-byte aligned, ws
- * of at least nopcs_workspace_bytes(grid, precision) bytes, 256-byte aligned,
- * dt >= 0; no two boxes may share a state or a workspace.  NOPCS_EINVAL on
- * argument errors (before any device work).
+ * call's dt where box.dt is 0).  Boxes too small to fill the device alone
+ * (under 2^21 points) share their launches: one launch per stage kernel and
+ * configuration covers all of them, its blocks taking their (box, block)
+ * items from a device table of the boxes' arguments; each larger box runs its
+ * own launches.  The step is captured once as a HIP graph holding one branch
+ * per large box and one for the shared launches (cached per batch: boxes,
+ * their states, workspaces and dt, parameters, precision, piece lengths and
+ * mode) and each of the nsteps steps is one replay on hip_stream
+ * (nopcs_set_batch_mode selects other arrangements).  Every box gets exactly
+ * the result of rk_step on it alone (its blocks run the single-box kernels'
+ * arithmetic).  1 <= nbox <= NOPCS_MAX_BATCH; each box: a valid grid, Q
+ * 16-byte aligned, ws of at least nopcs_workspace_bytes(grid, precision)
+ * bytes, 256-byte aligned, dt >= 0; no two boxes may share a state or a
+ * workspace.  NOPCS_EINVAL on argument errors (before any device work).
  */
 #define NOPCS_MAX_BATCH 64
 typedef struct {
@@ -348,11 +350,12 @@ int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes
                   int32_t nsteps, void *hip_stream);
 
 /*
- * nopcs_set_batch_mode -- how rk_step_batch runs a step: 0 (the default) one
- * launch per kernel and configuration over all boxes, as above, replayed as a
- * graph; 1 one graph branch per box holding that box's own launches (the
- * boxes overlap on the device through the branches); 2 the launches of mode 0
- * issued directly on hip_stream every step, without a graph.  Every mode gives
+ * nopcs_set_batch_mode -- how rk_step_batch runs a step: 0 every box in the
+ * shared launches, replayed as a graph; 1 one graph branch per box holding
+ * that box's own launches (the boxes overlap on the device through the
+ * branches); 2 every box in the shared launches, issued directly on
+ * hip_stream every step without a graph; 3 (the default) shared launches for
+ * the small boxes and a branch for each large one, as above.  Every mode gives
  * every box its lone result.  Process-wide; NOPCS_EINVAL for other values.
  */
 int nopcs_set_batch_mode(int32_t mode);

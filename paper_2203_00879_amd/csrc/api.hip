@@ -834,14 +834,36 @@ int rk_step_compact_viscous(const nse_params *params, const nopcs_grid *grid, do
     return NOPCS_OK;
 }
 
-// One graph for a batch of boxes: the RK4 step of every box is captured as its
-// own branch (a private stream forked from the capture stream and joined back),
-// so one replay runs all boxes and the device overlaps the branches.
-static int batch_graph_branches(const nse_params &params, int nbox, const nopcs_box *boxes, int precision,
-                                double dt, const LinePlanDev (*pl)[3], int nsteps, hipStream_t st) {
+// How a batch of boxes is stepped (nopcs_set_batch_mode):
+//   0 merged:   one launch per kernel and configuration over all boxes
+//               (batch.hpp), captured as a graph;
+//   1 branches: one graph branch per box, each box's launches as rk_step makes
+//               them (the device overlaps the branches);
+//   2 direct:   the launches of mode 0 issued on the stream, without a graph;
+//   3 hybrid:   a branch of its own for every box whose stage kernels fill the
+//               device alone (at least kOwnBranchPoints points), the others
+//               merged in one more branch (the default).
+// Merged launches run phase by phase, so every box of a merged launch waits
+// for the largest at each of the step's phase boundaries; branches let boxes
+// advance independently but cost a launch per kernel and box.  Many small
+// boxes favour merging, a few large ones branches.
+enum { BATCH_MERGED = 0, BATCH_BRANCHES = 1, BATCH_DIRECT = 2, BATCH_HYBRID = 3 };
+static std::atomic<int> g_batch_mode{BATCH_HYBRID};
+constexpr long long kOwnBranchPoints = 1LL << 21;   // 128^3
+
+// The batched RK4 step of a set of boxes.  Boxes that share launches have
+// their launches collected by phase (launch_step with a collector); each
+// (phase, kernel) becomes one launch over a device table of the boxes'
+// arguments.  The step is captured once as a graph -- one branch per group of
+// boxes, forked from the capture stream and joined back -- cached per batch
+// (mode, boxes, states, workspaces, dt, parameters, precision, piece lengths)
+// and replayed nsteps times.
+static int batch_step(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
+                      const LinePlanDev (*pl)[3], int nsteps, hipStream_t st, int mode) {
     int dev = 0;
     NOPCS_HIP_CHECK(hipGetDevice(&dev));
-    std::string key = "batch-branches";
+    std::string key = "batch";
+    put_bytes(key, mode);
     put_bytes(key, dev);
     put_bytes(key, params);
     put_bytes(key, precision);
@@ -857,107 +879,60 @@ static int batch_graph_branches(const nse_params &params, int nbox, const nopcs_
     auto it = g_graph_cache.find(key);
     if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
     evict_if_full();
-    hipStream_t &cs = g_capture_stream[dev];
-    if (!cs) NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    // branch streams and fork/join events of this device, kept for the process
-    static std::map<int, std::vector<hipStream_t>> branch;
-    static std::map<int, std::vector<hipEvent_t>> events;
-    std::vector<hipStream_t> &bs = branch[dev];
-    std::vector<hipEvent_t> &ev = events[dev];
-    while ((int)bs.size() < nbox) {
-        hipStream_t s = nullptr;
-        NOPCS_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        bs.push_back(s);
+    auto dt_of = [&](int b) { return boxes[b].dt > 0.0 ? boxes[b].dt : dt; };
+    // groups: boxes with a branch of their own, and the boxes that share launches
+    std::vector<int> own, merged;
+    for (int b = 0; b < nbox; ++b) {
+        const long long pts = (long long)boxes[b].grid.n[0] * boxes[b].grid.n[1] * boxes[b].grid.n[2];
+        const bool alone = mode == BATCH_BRANCHES || (mode == BATCH_HYBRID && pts >= kOwnBranchPoints);
+        (alone ? own : merged).push_back(b);
     }
-    while ((int)ev.size() < nbox + 1) {
-        hipEvent_t e = nullptr;
-        NOPCS_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        ev.push_back(e);
+    if (merged.size() == 1) {   // one box needs no table: its own launches
+        own.push_back(merged[0]);
+        merged.clear();
     }
     GraphEntry e;
-    NOPCS_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    t_capturing = true;
-    int rc = NOPCS_OK;
-    hipError_t he = hipEventRecord(ev[nbox], cs);
-    for (int b = 0; b < nbox && rc == NOPCS_OK && he == hipSuccess; ++b) {
-        he = hipStreamWaitEvent(bs[b], ev[nbox], 0);
-        if (he != hipSuccess) break;
-        const double dtb = boxes[b].dt > 0.0 ? boxes[b].dt : dt;
-        rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dtb, boxes[b].ws, pl[b], bs[b]);
-        if (rc != NOPCS_OK) break;
-        he = hipEventRecord(ev[b], bs[b]);
-        if (he == hipSuccess) he = hipStreamWaitEvent(cs, ev[b], 0);
-    }
-    t_capturing = false;
-    const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
-    if (rc != NOPCS_OK || he != hipSuccess || ec != hipSuccess) {
-        if (e.graph) (void)hipGraphDestroy(e.graph);
-        if (rc != NOPCS_OK) return rc;
-        set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he != hipSuccess ? he : ec));
-        return NOPCS_EDEVICE;
-    }
-    const int ri = instantiate(e);
-    if (ri != NOPCS_OK) return ri;
-    return replay(g_graph_cache[key] = e, nsteps, st);
-}
-
-// How a batch of boxes is stepped: 0 (default) one launch per kernel and
-// configuration over all boxes (batch.hpp), captured as a graph; 1 one graph
-// branch per box, each box's launches as rk_step makes them (kept for
-// comparison); 2 the launches of mode 0 issued directly, without a graph.
-static std::atomic<int> g_batch_mode{0};
-
-// The batched RK4 step of a set of boxes: every box's launches are collected
-// by phase (launch_step with a collector), each (phase, kernel) becomes one
-// launch over a device table of the boxes' arguments, and the sequence is
-// captured once as a graph (cached per batch: boxes, states, workspaces, dt,
-// parameters, precision, piece lengths) and replayed nsteps times.
-static int batch_graph_launches(const nse_params &params, int nbox, const nopcs_box *boxes, int precision, double dt,
-                                const LinePlanDev (*pl)[3], int nsteps, hipStream_t st, bool graph) {
-    int dev = 0;
-    NOPCS_HIP_CHECK(hipGetDevice(&dev));
-    std::string key = graph ? "batch-launches" : "batch-direct";
-    put_bytes(key, dev);
-    put_bytes(key, params);
-    put_bytes(key, precision);
-    put_bytes(key, dt);
-    for (int b = 0; b < nbox; ++b) {
-        put_bytes(key, boxes[b].grid);
-        put_bytes(key, boxes[b].Q);
-        put_bytes(key, boxes[b].ws);
-        put_bytes(key, boxes[b].dt);
-        for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, boxes[b].grid.n[d]));
-    }
-    std::lock_guard<std::mutex> lk(g_gmu);
-    auto it = g_graph_cache.find(key);
-    if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
-    evict_if_full();
-    // collect every box's launches (nothing is launched), phase by phase
     BatchCollector col;
-    for (int b = 0; b < nbox; ++b) {
-        const double dtb = boxes[b].dt > 0.0 ? boxes[b].dt : dt;
-        const int rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dtb, boxes[b].ws, pl[b], nullptr,
-                                   nullptr, &col);
-        if (rc != NOPCS_OK) return rc;
-    }
-    // one device buffer holds every table, each 256-byte aligned
-    size_t bytes = 0;
-    for (auto &ph : col.phases)
-        for (BatchLaunch &L : ph.second) {
-            L.dev_off = bytes;
-            bytes = (bytes + L.items.size() + 255) & ~(size_t)255;
+    if (!merged.empty()) {
+        for (int b : merged) {
+            const int rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dt_of(b), boxes[b].ws, pl[b],
+                                       nullptr, nullptr, &col);
+            if (rc != NOPCS_OK) return rc;
         }
-    std::vector<unsigned char> host(bytes, 0);
-    for (auto &ph : col.phases)
-        for (BatchLaunch &L : ph.second) std::memcpy(host.data() + L.dev_off, L.items.data(), L.items.size());
-    GraphEntry e;
-    NOPCS_HIP_CHECK(hipMalloc(&e.tables, bytes));
-    if (hipMemcpy(e.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(e.tables);
-        set_error("upload of the batch tables failed");
-        return NOPCS_EDEVICE;
+        // one device buffer holds every table, each 256-byte aligned
+        size_t bytes = 0;
+        for (auto &ph : col.phases)
+            for (BatchLaunch &L : ph.second) {
+                L.dev_off = bytes;
+                bytes = (bytes + L.items.size() + 255) & ~(size_t)255;
+            }
+        std::vector<unsigned char> host(bytes, 0);
+        for (auto &ph : col.phases)
+            for (BatchLaunch &L : ph.second) std::memcpy(host.data() + L.dev_off, L.items.data(), L.items.size());
+        NOPCS_HIP_CHECK(hipMalloc(&e.tables, bytes));
+        if (hipMemcpy(e.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(e.tables);
+            set_error("upload of the batch tables failed");
+            return NOPCS_EDEVICE;
+        }
     }
-    if (!graph) {
+    auto launch_merged = [&](hipStream_t s) -> hipError_t {
+        for (auto &ph : col.phases)
+            for (BatchLaunch &L : ph.second) {
+                const hipError_t he = L.launch(static_cast<char *>(e.tables) + L.dev_off, L.ntab, L.total, L.blk, s);
+                if (he != hipSuccess) return he;
+            }
+        return hipSuccess;
+    };
+    if (mode == BATCH_DIRECT) {   // every box merged (own is empty: nbox >= 2) or the lone box's launches
+        if (merged.empty()) {
+            for (int step = 0; step < nsteps; ++step) {
+                const int rc = launch_step(params, &boxes[0].grid, precision, boxes[0].Q, dt_of(0), boxes[0].ws, pl[0],
+                                           st);
+                if (rc != NOPCS_OK) return rc;
+            }
+            return NOPCS_OK;
+        }
         for (auto &ph : col.phases)
             for (BatchLaunch &L : ph.second) {
                 e.launches.push_back(L);
@@ -970,41 +945,73 @@ static int batch_graph_launches(const nse_params &params, int nbox, const nopcs_
         }
         return replay(g_graph_cache[key] = e, nsteps, st);
     }
+    auto fail = [&](int rc, hipError_t he) {
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+        if (e.tables) (void)hipFree(e.tables);
+        if (rc != NOPCS_OK) return rc;
+        set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he));
+        return (int)NOPCS_EDEVICE;
+    };
     hipStream_t &cs = g_capture_stream[dev];
-    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipFree(e.tables);
-        set_error("hipStreamCreateWithFlags failed");
-        return NOPCS_EDEVICE;
+    if (!cs) {
+        const hipError_t r = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (r != hipSuccess) return fail(NOPCS_OK, r);
+    }
+    // branch streams and fork/join events of this device, kept for the process
+    static std::map<int, std::vector<hipStream_t>> branch;
+    static std::map<int, std::vector<hipEvent_t>> events;
+    const int ngroups = (int)own.size() + (merged.empty() ? 0 : 1);
+    std::vector<hipStream_t> &bs = branch[dev];
+    std::vector<hipEvent_t> &ev = events[dev];
+    while ((int)bs.size() < ngroups) {
+        hipStream_t s = nullptr;
+        const hipError_t r = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (r != hipSuccess) return fail(NOPCS_OK, r);
+        bs.push_back(s);
+    }
+    while ((int)ev.size() < ngroups + 1) {
+        hipEvent_t x = nullptr;
+        const hipError_t r = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+        if (r != hipSuccess) return fail(NOPCS_OK, r);
+        ev.push_back(x);
     }
     hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
-        for (auto &ph : col.phases) {
-            for (BatchLaunch &L : ph.second) {
-                he = L.launch(static_cast<char *>(e.tables) + L.dev_off, L.ntab, L.total, L.blk, cs);
+    if (he != hipSuccess) return fail(NOPCS_OK, he);
+    t_capturing = true;
+    int rc = NOPCS_OK;
+    if (ngroups == 1 && !merged.empty()) {
+        he = launch_merged(cs);
+    } else {
+        he = hipEventRecord(ev[ngroups], cs);
+        for (int gi = 0; gi < ngroups && rc == NOPCS_OK && he == hipSuccess; ++gi) {
+            he = hipStreamWaitEvent(bs[gi], ev[ngroups], 0);
+            if (he != hipSuccess) break;
+            if (gi < (int)own.size()) {
+                const int b = own[gi];
+                rc = launch_step(params, &boxes[b].grid, precision, boxes[b].Q, dt_of(b), boxes[b].ws, pl[b], bs[gi]);
+                if (rc != NOPCS_OK) break;
+            } else {
+                he = launch_merged(bs[gi]);
                 if (he != hipSuccess) break;
             }
-            if (he != hipSuccess) break;
+            he = hipEventRecord(ev[gi], bs[gi]);
+            if (he == hipSuccess) he = hipStreamWaitEvent(cs, ev[gi], 0);
         }
-        const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
-        if (he == hipSuccess) he = ec;
     }
-    if (he != hipSuccess) {
-        if (e.graph) (void)hipGraphDestroy(e.graph);
-        (void)hipFree(e.tables);
-        set_error(std::string("batch graph capture failed: ") + hipGetErrorString(he));
-        return NOPCS_EDEVICE;
-    }
+    t_capturing = false;
+    const hipError_t ec = hipStreamEndCapture(cs, &e.graph);
+    if (rc != NOPCS_OK || he != hipSuccess || ec != hipSuccess) return fail(rc, he != hipSuccess ? he : ec);
     void *tables = e.tables;
     const int ri = instantiate(e);
     if (ri != NOPCS_OK) {
-        (void)hipFree(tables);
+        if (tables) (void)hipFree(tables);
         return ri;
     }
     return replay(g_graph_cache[key] = e, nsteps, st);
 }
 
 int nopcs_set_batch_mode(int32_t mode) {
-    if (mode < 0 || mode > 2) { set_error("batch mode must be 0, 1 or 2"); return NOPCS_EINVAL; }
+    if (mode < BATCH_MERGED || mode > BATCH_HYBRID) { set_error("batch mode must be 0, 1, 2 or 3"); return NOPCS_EINVAL; }
     g_batch_mode.store(mode);
     return NOPCS_OK;
 }
@@ -1045,10 +1052,7 @@ int rk_step_batch(const nse_params *params, int32_t nbox, const nopcs_box *boxes
         if (rc != NOPCS_OK) return rc;
     }
     if (nsteps == 0) return NOPCS_OK;
-    const int mode = g_batch_mode.load();
-    if (mode == 1)
-        return batch_graph_branches(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream);
-    return batch_graph_launches(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream, mode == 0);
+    return batch_step(*params, nbox, boxes, precision, dt, pl, nsteps, (hipStream_t)hip_stream, g_batch_mode.load());
 }
 
 int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,

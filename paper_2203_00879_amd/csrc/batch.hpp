@@ -17,6 +17,7 @@
 
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -49,13 +50,25 @@ __device__ inline void batch_walk(const BatchItem<typename Body::Args> *__restri
     }
 }
 
+// Wavefronts per SIMD a body's kernels are compiled for (Body::kMinWaves, else
+// 1): the register budget of each thread is the SIMD's file divided by it.
+template <class B, class = void>
+struct body_min_waves {
+    static constexpr int value = 1;
+};
+template <class B>
+struct body_min_waves<B, std::void_t<decltype(B::kMinWaves)>> {
+    static constexpr int value = B::kMinWaves;
+};
+
 // Kernels running a body: one box (block b of its own grid), or a batch.
 template <class Body, int NT>
-__global__ __launch_bounds__(NT) void k_one(typename Body::Args a) {
+__global__ __launch_bounds__(NT, body_min_waves<Body>::value) void k_one(typename Body::Args a) {
     Body::run(a, xcd_swizzle(blockIdx.x, gridDim.x), gridDim.x);
 }
 template <class Body, int NT>
-__global__ __launch_bounds__(NT) void k_many(const BatchItem<typename Body::Args> *__restrict__ tab, int ntab) {
+__global__ __launch_bounds__(NT, body_min_waves<Body>::value) void k_many(
+    const BatchItem<typename Body::Args> *__restrict__ tab, int ntab) {
     batch_walk<Body>(tab, ntab);
 }
 

@@ -260,7 +260,8 @@ def nse_rhs_compact_viscous(params, grid, Q, R, ws=None, stream=None):
 
 def rk_step_batch(params, boxes, dt, nsteps, precision=FP64, stream=None):
     """rk_step for a batch of boxes [(grid, Q, ws) or (grid, Q, ws, dt_box), ...]
-    (one launch per stage kernel over all boxes, replayed as one graph)."""
+    (small boxes share one launch per stage kernel, large ones run their own;
+    one graph replay per step)."""
     arr = (Box * len(boxes))()
     for i, box in enumerate(boxes):
         grid, Q, ws = box[:3]
@@ -274,8 +275,9 @@ def rk_step_batch(params, boxes, dt, nsteps, precision=FP64, stream=None):
 
 
 def set_batch_mode(mode):
-    """0: one launch per stage kernel over all boxes, as a graph (default); 1: one graph
-    branch per box; 2: the launches of 0 issued directly (no graph)."""
+    """0: every box in shared launches, as a graph; 1: one graph branch per box;
+    2: shared launches issued directly (no graph); 3 (default): shared launches
+    for boxes under 2^21 points and a branch for each larger one."""
     _check(lib().nopcs_set_batch_mode(int(mode)))
 
 

@@ -2,6 +2,13 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Parallel test workers (pytest -n) split the cores among the C oracle's
+# OpenMP loops: more spinning threads than cores slow those loops down by
+# orders of magnitude.
+if os.environ.get("PYTEST_XDIST_WORKER_COUNT"):
+    os.environ.setdefault("OMP_NUM_THREADS",
+                          str(max(1, (os.cpu_count() or 1) // int(os.environ["PYTEST_XDIST_WORKER_COUNT"]))))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

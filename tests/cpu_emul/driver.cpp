@@ -293,7 +293,7 @@ static int batch_checks(int prec) {
         bad[0].dt = -1.0;
         if (rk_step_batch(&p, 1, bad.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
         if (rk_step_batch(&p, 0, boxes.data(), prec, dt_call, 1, nullptr) != NOPCS_EINVAL) rc = 1;
-        if (nopcs_set_batch_mode(3) != NOPCS_EINVAL) rc = 1;
+        if (nopcs_set_batch_mode(4) != NOPCS_EINVAL) rc = 1;
         std::printf(rc == NOPCS_OK ? "ok batch argument errors\n" : "batch argument errors not reported\n");
     }
     for (int b = 0; b < nb; ++b) { delete Q[b]; delete W[b]; }

@@ -36,11 +36,13 @@ def driver():
                  "-I", os.path.join(EMU, "include")]
         # one compiler per translation unit, in parallel, then one link
         srcs = _sources() + [os.path.join(EMU, "driver.cpp")]
-        objs = [BIN + ".%d.o" % k for k in range(len(srcs))]
+        # per-process object and binary names: parallel workers may build at once
+        objs = [BIN + ".%d.%d.o" % (os.getpid(), k) for k in range(len(srcs))]
         procs = [subprocess.Popen(["g++"] + flags + ["-x", "c++", "-c", src, "-o", obj]) for src, obj in zip(srcs, objs)]
         assert all(p.wait() == 0 for p in procs), "CPU build of the kernels failed"
-        subprocess.check_call(["g++"] + flags + objs + ["-o", BIN + ".tmp"])
-        os.replace(BIN + ".tmp", BIN)
+        tmp = BIN + ".%d.tmp" % os.getpid()
+        subprocess.check_call(["g++"] + flags + objs + ["-o", tmp])
+        os.replace(tmp, BIN)
         for obj in objs:
             os.remove(obj)
     return BIN

@@ -1,6 +1,7 @@
 """GPU: RK4 stepping of a batch of uneven boxes (rk_step_batch: one launch per
-stage kernel over all boxes, as a graph or issued directly, or one graph
-branch per box) gives every box exactly the result of rk_step on it alone."""
+stage kernel over all boxes, as a graph or issued directly, one graph branch
+per box, or branches for large boxes beside shared launches for small ones)
+gives every box exactly the result of rk_step on it alone."""
 import sys
 
 import numpy as np
@@ -21,6 +22,7 @@ DEV = "cuda:0"
 P = dict(inputs.AIR)
 BOXES = [((32, 32, 32), (1, 1, 1), 0), ((48, 40, 36), (2, 1, 3), 1), ((24, 64, 28), (1, 2, 1), 2),
          ((80, 20, 72), (2, 1, 2), 3)]
+BIG = ((132, 128, 128), (2, 2, 2), 5)   # 2^21 points or more: a branch of its own in the default mode
 
 
 def say(*a):
@@ -45,21 +47,22 @@ def lone(shape, nseg, seed, prec, dt, nsteps):
 def batch_mode(request):
     nopcs.set_batch_mode(request.param)
     yield request.param
-    nopcs.set_batch_mode(0)
+    nopcs.set_batch_mode(3)
 
 
-@pytest.mark.parametrize("batch_mode", [0, 1, 2], indirect=True)
+@pytest.mark.parametrize("batch_mode", [0, 1, 2, 3], indirect=True)
 @pytest.mark.parametrize("prec", [nopcs.FP64, nopcs.MIXED])
 def test_batch_equals_lone_runs_bitwise_over_replays(prec, batch_mode):
-    """Four uneven boxes plus a fifth of the second's shape (so launches hold
-    several boxes of one configuration), 2 + 1 + 1 steps in three calls (the
-    step is captured or collected on the first and replayed after), with
-    unrelated eager work in between; the fifth box takes its own dt."""
-    say("batch of", len(BOXES) + 1, "precision", prec, "mode", batch_mode)
+    """Four uneven boxes, a fifth of the second's shape (so launches hold
+    several boxes of one configuration) with its own dt, and a large sixth,
+    2 + 1 + 1 steps in three calls (the step is captured or collected on the
+    first and replayed after), with unrelated eager work in between."""
+    say("batch of", len(BOXES) + 2, "precision", prec, "mode", batch_mode)
     dt, dt5 = 1e-5, 2.5e-5
     nopcs.lib().nopcs_set_graphs(0)
-    specs = BOXES + [(BOXES[1][0], BOXES[1][1], 9)]
-    want = [lone(s, n, seed, prec, dt, 4) for s, n, seed in BOXES] + [lone(*specs[4], prec, dt5, 4)]
+    specs = BOXES + [(BOXES[1][0], BOXES[1][1], 9), BIG]
+    dts = [dt] * len(BOXES) + [dt5, dt]
+    want = [lone(s, n, seed, prec, d, 4) for (s, n, seed), d in zip(specs, dts)]
     boxes = [make(s, n, seed, prec) for s, n, seed in specs]
     boxes[4] = boxes[4] + (dt5,)
     prm = nopcs.make_params(P)
