@@ -398,11 +398,24 @@ int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precisi
  * (device, state pointer, workspace pointer, box, parameters, precision, dt,
  * piece lengths), and replays that graph nsteps times on the caller's stream;
  * results are bit for bit those of the launches themselves.  Graphs are cached
- * (at most 64) and freed by nopcs_release_plans.  Kernel timing
+ * (at most 64 by default, nopcs_set_graph_cache_limit) and freed by
+ * nopcs_release_plans.  Kernel timing
  * (nopcs_timing_*) does not see launches inside graphs.  on == 0 (the default)
  * launches every kernel directly.  Process-wide; returns NOPCS_OK.
  */
 int nopcs_set_graphs(int32_t on);
+
+/*
+ * nopcs_set_graph_cache_limit -- the number of cached steps (graphs of
+ * rk_step and rk_step_batch, and the collected launches of batch mode 2) the
+ * library keeps, 1..4096 (default 64).  When a new step would exceed it, the
+ * least recently replayed entries are freed, each after its replays have run;
+ * lowering the limit frees entries at once the same way.  A serving loop whose
+ * batches change often holds one entry per batch it has seen, each with its
+ * device tables (a few KB) and graph.  Process-wide; NOPCS_EINVAL outside the
+ * range.
+ */
+int nopcs_set_graph_cache_limit(int32_t n);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of many boxes on one GPU.                    */
@@ -414,6 +427,9 @@ typedef struct {
     int32_t max_slots;       /* maximum requests resident on the device at once */
     int32_t max_queue;       /* maximum requests waiting for admission */
     int32_t device;          /* HIP device ordinal */
+    int32_t batched;         /* 0: each resident request steps on its own stream;
+                                1: all resident requests step together through
+                                rk_step_batch, one batch in flight at a time */
 } solver_config;
 
 typedef struct {
@@ -434,10 +450,13 @@ typedef struct {
 /* Create a solver: one stream per slot (default priority) and a worker thread that
  * admits queued requests in arrival order while a slot is free and their device
  * footprint (state + nopcs_workspace_bytes) fits hbm_budget_bytes, and keeps every
- * resident request advancing in chunks of RK4 steps on its own stream (continuous
- * batching; a request's arithmetic is that of rk_step on its box alone, in the
- * request's precision, NOPCS_FP64 or NOPCS_MIXED).  *out is owned by the caller
- * until solver_destroy. */
+ * resident request advancing in chunks of RK4 steps (continuous batching): on the
+ * request's own stream (batched = 0), or, with batched = 1, in batched steps over
+ * every resident request (rk_step_batch per group of requests with the same
+ * parameters and precision; a chunk advances every member by the steps the
+ * member closest to its end has left, at most 8).  Either way a request's
+ * arithmetic is that of rk_step on its box alone, in the request's precision,
+ * NOPCS_FP64 or NOPCS_MIXED.  *out is owned by the caller until solver_destroy. */
 int solver_create(const solver_config *cfg, nopcs_solver **out);
 
 /* Queue a request (non-blocking; the initial state is copied).  NOPCS_EBUSY if the

@@ -334,11 +334,16 @@ struct GraphEntry {
     hipEvent_t done = nullptr;   // recorded after the entry's latest replay
     void *tables = nullptr;      // device tables of a batched step (owned)
     std::vector<BatchLaunch> launches;   // a batched step launched directly (no graph)
+    uint64_t last_use = 0;               // g_graph_clock at the latest replay
 };
 std::mutex g_gmu;
 std::map<std::string, GraphEntry> g_graph_cache;
 std::map<int, hipStream_t> g_capture_stream;
-constexpr size_t kMaxGraphs = 64;
+// branch streams and fork/join events of batched steps, per device
+std::map<int, std::vector<hipStream_t>> g_branch_streams;
+std::map<int, std::vector<hipEvent_t>> g_branch_events;
+std::atomic<int> g_max_graphs{64};   // entries the cache holds (nopcs_set_graph_cache_limit)
+uint64_t g_graph_clock = 0;          // use counter for least-recently-used eviction (under g_gmu)
 
 template <class T>
 void put_bytes(std::string &k, const T &v) {
@@ -365,6 +370,7 @@ void drop_graph(GraphEntry &e) {
 // event; the caller holds g_gmu, so no other thread can evict the entry
 // between the lookup and the launches.
 int replay(GraphEntry &e, int nsteps, hipStream_t st) {
+    e.last_use = ++g_graph_clock;
     for (int step = 0; step < nsteps; ++step) {
         if (e.exec) {
             NOPCS_HIP_CHECK(hipGraphLaunch(e.exec, st));
@@ -377,11 +383,16 @@ int replay(GraphEntry &e, int nsteps, hipStream_t st) {
     return NOPCS_OK;
 }
 
-// Make room for one more entry: the oldest goes (after its replays have run).
-void evict_if_full() {
-    if (g_graph_cache.size() >= kMaxGraphs) {
-        drop_graph(g_graph_cache.begin()->second);
-        g_graph_cache.erase(g_graph_cache.begin());
+// Make room for `room` more entries: the least recently used go (each after
+// its replays have run).
+void evict_if_full(size_t room = 1) {
+    const size_t cap = (size_t)g_max_graphs.load();
+    while (!g_graph_cache.empty() && g_graph_cache.size() + room > cap) {
+        auto lru = g_graph_cache.begin();
+        for (auto it = g_graph_cache.begin(); it != g_graph_cache.end(); ++it)
+            if (it->second.last_use < lru->second.last_use) lru = it;
+        drop_graph(lru->second);
+        g_graph_cache.erase(lru);
     }
 }
 
@@ -409,6 +420,15 @@ static void release_graphs() {
     std::lock_guard<std::mutex> lk(g_gmu);
     for (auto &kv : g_graph_cache) drop_graph(kv.second);
     g_graph_cache.clear();
+    for (auto &kv : g_branch_streams)
+        for (hipStream_t x : kv.second) (void)hipStreamDestroy(x);
+    for (auto &kv : g_branch_events)
+        for (hipEvent_t x : kv.second) (void)hipEventDestroy(x);
+    for (auto &kv : g_capture_stream)
+        if (kv.second) (void)hipStreamDestroy(kv.second);
+    g_branch_streams.clear();
+    g_branch_events.clear();
+    g_capture_stream.clear();
 }
 
 static int step_graph(const nse_params &params, const nopcs_grid *grid, int precision, double *Q, double dt, void *ws,
@@ -957,12 +977,10 @@ static int batch_step(const nse_params &params, int nbox, const nopcs_box *boxes
         const hipError_t r = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (r != hipSuccess) return fail(NOPCS_OK, r);
     }
-    // branch streams and fork/join events of this device, kept for the process
-    static std::map<int, std::vector<hipStream_t>> branch;
-    static std::map<int, std::vector<hipEvent_t>> events;
+    // branch streams and fork/join events of this device (kept until nopcs_release_plans)
     const int ngroups = (int)own.size() + (merged.empty() ? 0 : 1);
-    std::vector<hipStream_t> &bs = branch[dev];
-    std::vector<hipEvent_t> &ev = events[dev];
+    std::vector<hipStream_t> &bs = g_branch_streams[dev];
+    std::vector<hipEvent_t> &ev = g_branch_events[dev];
     while ((int)bs.size() < ngroups) {
         hipStream_t s = nullptr;
         const hipError_t r = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -1122,6 +1140,14 @@ int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precisi
 
 int nopcs_set_graphs(int32_t on) {
     g_graphs.store(on ? 1 : 0);
+    return NOPCS_OK;
+}
+
+int nopcs_set_graph_cache_limit(int32_t n) {
+    if (n < 1 || n > 4096) { set_error("graph cache limit must be in [1, 4096]"); return NOPCS_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_gmu);
+    g_max_graphs.store(n);
+    evict_if_full(0);
     return NOPCS_OK;
 }
 

@@ -3,12 +3,15 @@
 // Requests (initial state on the host, box, parameters, steps) are queued by
 // solver_submit and admitted in arrival order while a slot is free and their
 // device footprint (state + workspace) fits the HBM budget.  Every resident
-// request owns a HIP stream (default priority) and advances in chunks of RK4
-// steps; a worker thread keeps one chunk in flight per resident request, so
-// the GPU interleaves all of them (continuous batching: a finished request
-// frees its slot and memory at once and the next queued request is admitted).
-// Each request runs exactly the kernels and launch shapes rk_step uses for
-// its box alone, so its result does not depend on what else is resident.
+// request owns a HIP stream (default priority, for its copies) and advances in
+// chunks of RK4 steps (continuous batching: a finished request frees its slot
+// and memory at once and the next queued request is admitted).  Two ways of
+// stepping: a worker thread keeps one chunk in flight per resident request on
+// the request's stream, so the GPU interleaves all of them; or (batched) it
+// keeps one batched chunk in flight over all resident requests, rk_step_batch
+// per group with the same parameters and precision, so that small boxes share
+// launches.  Each request runs exactly the arithmetic of rk_step on its box
+// alone, so its result does not depend on what else is resident.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,8 +47,9 @@ struct Request {
     double *dQ = nullptr;          // device state
     void *dws = nullptr;           // device workspace
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;       // end of the chunk in flight
+    hipEvent_t ev = nullptr;       // end of the chunk (batched: of the upload) in flight
     bool in_flight = false;
+    int32_t chunk = 0;             // batched: steps of the batched chunk in flight
     int32_t steps_done = 0;
     int32_t status = NOPCS_EAGAIN;
     double t_submit = 0, t_admit = -1, t_done = -1;
@@ -71,7 +75,9 @@ struct nopcs_solver {
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
+    void run_batched();
     bool admit_one(std::unique_lock<std::mutex> &lk);
+    bool copy_out(std::unique_lock<std::mutex> &lk, Request &r);
     void finish(Request &r, int status);
 };
 
@@ -109,6 +115,10 @@ bool nopcs_solver::admit_one(std::unique_lock<std::mutex> &lk) {
                hipMemcpyAsync(r.dQ, r.q0.data(), r.n_elems * sizeof(double), hipMemcpyHostToDevice, r.stream) !=
                    hipSuccess) {
         status = NOPCS_EDEVICE;
+    } else if (cfg.batched) {
+        // batched chunks run on the worker's stream: a request joins them once its upload is done
+        if (hipEventRecord(r.ev, r.stream) != hipSuccess) status = NOPCS_EDEVICE;
+        r.in_flight = true;
     }
     lk.lock();
     r.t_admit = now();
@@ -140,6 +150,133 @@ void nopcs_solver::finish(Request &r, int status) {
     cv.notify_all();
 }
 
+// Result back to the host, non-finite check, release (called with the lock
+// held; the request's device work has ended).
+bool nopcs_solver::copy_out(std::unique_lock<std::mutex> &lk, Request &r) {
+    r.qout.resize(r.n_elems);
+    lk.unlock();
+    const bool ok = hipMemcpyAsync(r.qout.data(), r.dQ, r.n_elems * sizeof(double), hipMemcpyDeviceToHost,
+                                   r.stream) == hipSuccess &&
+                    hipStreamSynchronize(r.stream) == hipSuccess;
+    bool finite = ok;
+    if (ok)
+        for (double v : r.qout)
+            if (!std::isfinite(v)) {
+                finite = false;
+                break;
+            }
+    lk.lock();
+    finish(r, !ok ? NOPCS_EDEVICE : finite ? NOPCS_OK : NOPCS_ENONFINITE);
+    return true;
+}
+
+// Batched stepping: one batched chunk in flight on the worker's own stream.
+// When it ends, finished requests are copied back after the next chunk has
+// been launched (their memory is no longer touched by it).
+void nopcs_solver::run_batched() {
+    (void)hipSetDevice(cfg.device);
+    hipStream_t bst = nullptr;
+    hipEvent_t bev = nullptr;
+    const bool dev_ok = hipStreamCreateWithFlags(&bst, hipStreamNonBlocking) == hipSuccess &&
+                        hipEventCreateWithFlags(&bev, hipEventDisableTiming) == hipSuccess;
+    std::vector<Request *> members;   // the requests of the chunk in flight
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop) {
+        while (admit_one(lk)) {
+        }
+        bool progressed = false;
+        if (!members.empty()) {
+            const hipError_t q = hipEventQuery(bev);
+            if (q == hipErrorNotReady) {
+                cv.wait_for(lk, std::chrono::microseconds(100));
+                continue;
+            }
+            for (Request *r : members) {
+                if (r->done) continue;
+                if (q != hipSuccess) finish(*r, NOPCS_EDEVICE);
+                else r->steps_done += r->chunk;
+            }
+            members.clear();
+            progressed = true;
+        }
+        // requests ready for a chunk (upload done, steps left), grouped by parameters and precision
+        std::vector<Request *> finished;
+        std::map<std::string, std::vector<Request *>> groups;
+        const std::vector<uint64_t> ids = resident;
+        for (uint64_t id : ids) {
+            auto it = reqs.find(id);
+            if (it == reqs.end()) continue;
+            Request &r = *it->second;
+            if (r.done) continue;
+            if (r.in_flight) {   // upload
+                const hipError_t q = hipEventQuery(r.ev);
+                if (q == hipErrorNotReady) continue;
+                r.in_flight = false;
+                if (q != hipSuccess) {
+                    finish(r, NOPCS_EDEVICE);
+                    continue;
+                }
+            }
+            if (r.steps_done >= r.req.nsteps) {
+                finished.push_back(&r);
+                continue;
+            }
+            std::string key(reinterpret_cast<const char *>(&r.req.params), sizeof r.req.params);
+            key.append(reinterpret_cast<const char *>(&r.req.precision), sizeof r.req.precision);
+            groups[key].push_back(&r);
+        }
+        if (!dev_ok) {
+            for (auto &g : groups)
+                for (Request *r : g.second) finish(*r, NOPCS_EDEVICE);
+            groups.clear();
+        }
+        // one batched chunk per group (at most NOPCS_MAX_BATCH boxes a call)
+        for (auto &g : groups) {
+            std::vector<Request *> &v = g.second;
+            for (size_t a = 0; a < v.size(); a += NOPCS_MAX_BATCH) {
+                const size_t e = std::min(v.size(), a + (size_t)NOPCS_MAX_BATCH);
+                int32_t k = chunk_steps;
+                std::vector<nopcs_box> boxes;
+                for (size_t i = a; i < e; ++i) {
+                    const Request &r = *v[i];
+                    k = std::min(k, r.req.nsteps - r.steps_done);
+                    boxes.push_back(nopcs_box{r.req.grid, r.dQ, r.dws, r.ws_bytes, r.req.dt});
+                }
+                const nse_params prm = v[a]->req.params;
+                const int prec = v[a]->req.precision;
+                lk.unlock();
+                const int rc = rk_step_batch(&prm, (int32_t)boxes.size(), boxes.data(), prec, boxes[0].dt, k, bst);
+                lk.lock();
+                for (size_t i = a; i < e; ++i) {
+                    if (rc != NOPCS_OK) {
+                        finish(*v[i], rc);
+                    } else {
+                        v[i]->chunk = k;
+                        members.push_back(v[i]);
+                    }
+                }
+            }
+        }
+        if (!members.empty()) {
+            if (hipEventRecord(bev, bst) != hipSuccess) {
+                (void)hipStreamSynchronize(bst);
+                for (Request *r : members) finish(*r, NOPCS_EDEVICE);
+                members.clear();
+            }
+            progressed = true;
+        }
+        for (Request *r : finished) progressed = copy_out(lk, *r) || progressed;
+        if (!progressed) cv.wait_for(lk, std::chrono::microseconds(200));
+    }
+    lk.unlock();
+    // nothing may run on the requests' memory once the worker has ended
+    if (bst) {
+        (void)hipStreamSynchronize(bst);
+        (void)hipStreamDestroy(bst);
+    }
+    if (bev) (void)hipEventDestroy(bev);
+}
+
 void nopcs_solver::run() {
     (void)hipSetDevice(cfg.device);
     std::unique_lock<std::mutex> lk(mu);
@@ -164,22 +301,7 @@ void nopcs_solver::run() {
                 }
             }
             if (r.steps_done >= r.req.nsteps) {
-                // result back to the host, non-finite check, release
-                r.qout.resize(r.n_elems);
-                lk.unlock();
-                const bool ok = hipMemcpyAsync(r.qout.data(), r.dQ, r.n_elems * sizeof(double), hipMemcpyDeviceToHost,
-                                               r.stream) == hipSuccess &&
-                                hipStreamSynchronize(r.stream) == hipSuccess;
-                bool finite = ok;
-                if (ok)
-                    for (double v : r.qout)
-                        if (!std::isfinite(v)) {
-                            finite = false;
-                            break;
-                        }
-                lk.lock();
-                finish(r, !ok ? NOPCS_EDEVICE : finite ? NOPCS_OK : NOPCS_ENONFINITE);
-                progressed = true;
+                progressed = copy_out(lk, r);
                 continue;
             }
             // next chunk of steps, asynchronously on the request's stream
@@ -208,8 +330,9 @@ extern "C" {
 
 int solver_create(const solver_config *cfg, nopcs_solver **out) {
     if (!cfg || !out) { nopcs::set_error("cfg and out must be non-NULL"); return NOPCS_EINVAL; }
-    if (cfg->max_slots < 1 || cfg->max_slots > 64 || cfg->max_queue < 1 || cfg->hbm_budget_bytes == 0) {
-        nopcs::set_error("solver_config: need 1 <= max_slots <= 64, max_queue >= 1, hbm_budget_bytes > 0");
+    if (cfg->max_slots < 1 || cfg->max_slots > 64 || cfg->max_queue < 1 || cfg->hbm_budget_bytes == 0 ||
+        (cfg->batched != 0 && cfg->batched != 1)) {
+        nopcs::set_error("solver_config: need 1 <= max_slots <= 64, max_queue >= 1, hbm_budget_bytes > 0, batched 0 or 1");
         return NOPCS_EINVAL;
     }
     int ndev = 0;
@@ -231,7 +354,10 @@ int solver_create(const solver_config *cfg, nopcs_solver **out) {
         s->free_streams.push_back(st);
     }
     nopcs_solver *raw = s.release();
-    raw->worker = std::thread([raw] { raw->run(); });
+    raw->worker = std::thread([raw] {
+        if (raw->cfg.batched) raw->run_batched();
+        else raw->run();
+    });
     *out = raw;
     return NOPCS_OK;
 }

@@ -51,7 +51,7 @@ MAX_BATCH = 64
 
 class SolverConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int32), ("batched", ctypes.c_int32)]
 
 
 class SolveRequest(ctypes.Structure):
@@ -94,6 +94,7 @@ def lib():
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
         L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
+        L.nopcs_set_graph_cache_limit.argtypes = [ctypes.c_int32]
         L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
                                      ctypes.POINTER(ctypes.c_int32 * 3)]
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -274,6 +275,11 @@ def rk_step_batch(params, boxes, dt, nsteps, precision=FP64, stream=None):
                                _stream(stream)))
 
 
+def set_graph_cache_limit(n):
+    """Steps the library keeps cached (graphs, batched launches): 1..4096, default 64."""
+    _check(lib().nopcs_set_graph_cache_limit(int(n)))
+
+
 def set_batch_mode(mode):
     """0: every box in shared launches, as a graph; 1: one graph branch per box;
     2: shared launches issued directly (no graph); 3 (default): shared launches
@@ -322,8 +328,8 @@ class Solver:
     where status is NOPCS_EAGAIN while the request is pending.  Q is a new
     numpy array holding the final state once done."""
 
-    def __init__(self, hbm_budget_bytes, max_slots=4, max_queue=1024, device=0):
-        cfg = SolverConfig(int(hbm_budget_bytes), int(max_slots), int(max_queue), int(device))
+    def __init__(self, hbm_budget_bytes, max_slots=4, max_queue=1024, device=0, batched=False):
+        cfg = SolverConfig(int(hbm_budget_bytes), int(max_slots), int(max_queue), int(device), int(bool(batched)))
         h = ctypes.c_void_p()
         _check(lib().solver_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

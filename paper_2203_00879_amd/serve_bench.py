@@ -14,6 +14,7 @@ done), admission delay percentiles, the number of requests, and (with --check)
 whether each checked request equals the same box run alone, bit for bit.
 
     python -m paper_2203_00879_amd.serve_bench [--requests 256] [--step-scale 1.0] [--precision mixed]
+        [--mean-gap 0.05] [--slots 8] [--batched]
 """
 import argparse
 import json
@@ -50,7 +51,7 @@ def request_state(w, seed):
 
 
 def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=False, precision="mixed",
-        mean_gap_s=0.05):
+        mean_gap_s=0.05, batched=False):
     import torch
     prec = nopcs.MIXED if precision == "mixed" else nopcs.FP64
     params = nopcs.make_params(inputs.AIR)
@@ -60,7 +61,7 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
     dts = [inputs.stable_dt(w["n"], 300.0 + w["dT"]) for w in W]
     ids, t_sub = {}, {}
     results = {}
-    with nopcs.Solver(int(budget_gb * 1e9), max_slots=slots, max_queue=max(1, n_req)) as S:
+    with nopcs.Solver(int(budget_gb * 1e9), max_slots=slots, max_queue=max(1, n_req), batched=batched) as S:
         t0 = time.perf_counter()
         k = 0
         pending = set()
@@ -91,7 +92,7 @@ def run(n_req=256, step_scale=1.0, slots=8, budget_gb=200.0, check=0, verbose=Fa
         "metric": "serving: Mpoint-stage/s and request latency (RTI boxes 32^3..192^3, %s)" %
                   ("mixed precision" if prec == nopcs.MIXED else "FP64"),
         "precision": precision,
-        "requests": n_req, "all_ok": ok, "slots": slots,
+        "requests": n_req, "all_ok": ok, "slots": slots, "batched": bool(batched),
         "Mpoint_stage_per_s": pst / (last - first) / 1e6,
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
         "p50_admission_s": float(np.percentile(adm, 50)), "p99_admission_s": float(np.percentile(adm, 99)),
@@ -123,9 +124,10 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time in seconds")
+    ap.add_argument("--batched", action="store_true", help="step resident requests in batched chunks")
     a = ap.parse_args()
     print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose, a.precision,
-                         a.mean_gap)), flush=True)
+                         a.mean_gap, a.batched)), flush=True)
 
 
 if __name__ == "__main__":

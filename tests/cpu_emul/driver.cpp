@@ -6,7 +6,8 @@
 //   driver filter nx ny nz sx sy sz lx ly lz af every dt nsteps in out  (nopcs_filter if nsteps is 0,
 //                                                              else rk_step_filtered; in/out: 5N)
 //   driver plan  n nseg piece_len                            (prints the line-march tables)
-//   driver serve                                              (scripted checks of the serving runtime)
+//   driver serve | serve_batched          (scripted checks of the serving runtime; per-request streams
+//                                          or batched chunks)
 //   driver batch                       (batched stepping of uneven boxes against each box's lone step)
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction;
 // NOPCS_EMUL_PRECISION=1 runs rhs and rk in mixed precision.
@@ -114,7 +115,7 @@ static std::vector<double> test_state(int n, int seed) {
     } while (0)
 
 // Scripted checks of the serving runtime on 8^3 boxes.
-static int serve_checks() {
+static int serve_checks(int batched) {
     const int n = 8, nsteps = 1;
     const double dt = 1e-5;
     nse_params p = air_params();
@@ -123,33 +124,38 @@ static int serve_checks() {
     const size_t N5 = 5 * (size_t)n * n * n;
     const size_t wsb = nopcs_workspace_bytes(&g, NOPCS_FP64);
     const size_t fp = ((N5 * sizeof(double) + 255) & ~(size_t)255) + wsb;
-    // references: rk_step on each state alone (before any solver thread runs kernels)
+    // references: rk_step on each state alone (before any solver thread runs
+    // kernels); the three requests of check 1 run 1, 6 and 11 steps (several
+    // chunks of at most 8 steps, members leaving the batch at different times)
+    const int steps_of[3] = {1, 6, 11};
     std::vector<std::vector<double>> q0(3), ref(3);
     for (int r = 0; r < 3; ++r) {
         q0[r] = test_state(n, r);
         Buf Q(N5), ws((wsb + 7) / 8);
         std::memcpy(Q.p, q0[r].data(), N5 * sizeof(double));
-        if (rk_step(&p, &g, NOPCS_FP64, Q.p, dt, nsteps, ws.p, wsb, nullptr) != NOPCS_OK) return 1;
+        if (rk_step(&p, &g, NOPCS_FP64, Q.p, dt, steps_of[r], ws.p, wsb, nullptr) != NOPCS_OK) return 1;
         ref[r].assign(Q.p, Q.p + N5);
     }
     solve_request rq{};
     rq.params = p; rq.grid = g; rq.nsteps = nsteps; rq.precision = NOPCS_FP64; rq.dt = dt;
     // 1. three requests on two slots: every result equals its box run alone, bit for bit
     {
-        solver_config cfg{2 * fp, 2, 16, 0};
+        solver_config cfg{2 * fp, 2, 16, 0, batched};
         nopcs_solver *s = nullptr;
         SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create");
         uint64_t id[3];
         for (int r = 0; r < 3; ++r) {
             rq.Q0_host = q0[r].data();
+            rq.nsteps = steps_of[r];
             SERVE_CHECK(solver_submit(s, &rq, &id[r]) == NOPCS_OK, "submit");
         }
+        rq.nsteps = nsteps;
         std::vector<double> out(N5);
         solve_result res{};
         for (int r = 0; r < 3; ++r) {
             int rc;
             while ((rc = solver_poll(s, id[r], out.data(), &res)) == NOPCS_EAGAIN) std::this_thread::sleep_for(std::chrono::milliseconds(5));
-            SERVE_CHECK(rc == NOPCS_OK && res.steps_done == nsteps, "request done");
+            SERVE_CHECK(rc == NOPCS_OK && res.steps_done == steps_of[r], "request done");
             SERVE_CHECK(std::memcmp(out.data(), ref[r].data(), N5 * sizeof(double)) == 0, "mix equals alone bit for bit");
             SERVE_CHECK(res.t_submit <= res.t_admit && res.t_admit <= res.t_done, "timestamps ordered");
         }
@@ -158,7 +164,7 @@ static int serve_checks() {
     }
     // 2. budget for one box: admission strictly in arrival order; a non-finite box is flagged
     {
-        solver_config cfg{fp, 4, 16, 0};
+        solver_config cfg{fp, 4, 16, 0, batched};
         nopcs_solver *s = nullptr;
         SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (one box budget)");
         std::vector<double> bad = q0[1];
@@ -180,7 +186,7 @@ static int serve_checks() {
     }
     // 3. argument and capacity errors; destroy with work pending
     {
-        solver_config cfg{fp, 1, 1, 0};
+        solver_config cfg{fp, 1, 1, 0, batched};
         nopcs_solver *s = nullptr;
         SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (queue of one)");
         uint64_t id = 0;
@@ -201,8 +207,49 @@ static int serve_checks() {
         SERVE_CHECK(busy, "full queue answers EBUSY");
         SERVE_CHECK(solver_poll(s, 987654321ULL, nullptr, nullptr) == NOPCS_ENOTFOUND, "unknown id");
         SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy with pending work");
-        solver_config badcfg{fp, 0, 1, 0};
+        solver_config badcfg{fp, 0, 1, 0, batched};
         SERVE_CHECK(solver_create(&badcfg, &s) == NOPCS_EINVAL, "zero slots rejected");
+    }
+    // 4. a stream of 16 requests on 4 slots, each with its own dt and 1-3
+    //    steps (requests joining and leaving batches at every chunk): every
+    //    result equals its box run alone, bit for bit
+    {
+        const int nr = 16;
+        std::vector<std::vector<double>> want(nr);
+        std::vector<double> dts(nr);
+        std::vector<int> nst(nr);
+        for (int r = 0; r < nr; ++r) {
+            dts[r] = 1e-5 * (1.0 + 0.013 * r);
+            nst[r] = 1 + r % 3;
+            Buf Q(N5), ws((wsb + 7) / 8);
+            std::memcpy(Q.p, q0[r % 3].data(), N5 * sizeof(double));
+            if (rk_step(&p, &g, NOPCS_FP64, Q.p, dts[r], nst[r], ws.p, wsb, nullptr) != NOPCS_OK) return 1;
+            want[r].assign(Q.p, Q.p + N5);
+        }
+        solver_config cfg{4 * fp, 4, nr, 0, batched};
+        nopcs_solver *s = nullptr;
+        SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (stream)");
+        std::vector<uint64_t> id(nr);
+        bool all_sub = true;
+        for (int r = 0; r < nr; ++r) {
+            solve_request q = rq;
+            q.Q0_host = q0[r % 3].data();
+            q.dt = dts[r];
+            q.nsteps = nst[r];
+            all_sub = all_sub && solver_submit(s, &q, &id[r]) == NOPCS_OK;
+        }
+        SERVE_CHECK(all_sub, "stream submitted");
+        std::vector<double> out(N5);
+        bool same = true;
+        for (int r = 0; r < nr; ++r) {
+            solve_result res{};
+            int rc;
+            while ((rc = solver_poll(s, id[r], out.data(), &res)) == NOPCS_EAGAIN) std::this_thread::sleep_for(std::chrono::milliseconds(2));
+            same = same && rc == NOPCS_OK && res.steps_done == nst[r] &&
+                   std::memcmp(out.data(), want[r].data(), N5 * sizeof(double)) == 0;
+        }
+        SERVE_CHECK(same, "stream of 16 equals alone bit for bit");
+        SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy (stream)");
     }
     return 0;
 }
@@ -233,9 +280,9 @@ static int batch_checks(int prec) {
     const Shape shapes[] = {{{8, 8, 8}, {1, 1, 1}, 1e-5},
                             {{16, 12, 10}, {2, 1, 1}, 2e-5},
                             {{16, 12, 10}, {2, 1, 1}, 0.0},   // the call's dt
-                            {{40, 33, 37}, {1, 2, 3}, 1e-5},
+                            {{20, 18, 27}, {1, 2, 3}, 1e-5},
                             {{9, 70, 11}, {1, 2, 1}, 3e-5}};
-    const int nb = sizeof shapes / sizeof shapes[0], nsteps = 2;
+    const int nb = sizeof shapes / sizeof shapes[0], nsteps = 1;
     const double dt_call = 1.5e-5;
     nse_params p = air_params();
     std::vector<nopcs_grid> g(nb);
@@ -264,10 +311,12 @@ static int batch_checks(int prec) {
     }
     std::vector<nopcs_box> boxes(nb);
     for (int b = 0; b < nb; ++b) boxes[b] = nopcs_box{g[b], Q[b]->p, W[b]->p, wsb[b], shapes[b].dt};
-    int rc = nopcs_set_batch_mode(2);
-    for (int rep = 0; rep < 2 && rc == NOPCS_OK; ++rep) {   // the second call replays the cached launches
-        if (rep) for (int b = 0; b < nb; ++b) std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
-        rc = rk_step_batch(&p, nb, boxes.data(), prec, dt_call, nsteps, nullptr);
+    int rc = NOPCS_OK;
+    const int modes[4] = {2, 0, 1, 3};
+    for (int rep = 0; rep < 8 && rc == NOPCS_OK; ++rep) {   // per mode: the second call replays the cached step
+        if (rep % 2 == 0) rc = nopcs_set_batch_mode(modes[rep / 2]);
+        for (int b = 0; b < nb; ++b) std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+        if (rc == NOPCS_OK) rc = rk_step_batch(&p, nb, boxes.data(), prec, dt_call, nsteps, nullptr);
         for (int b = 0; b < nb && rc == NOPCS_OK; ++b) {
             if (std::memcmp(Q[b]->p, ref[b].data(), n5[b] * sizeof(double)) != 0) {
                 size_t bad = 0;
@@ -277,9 +326,40 @@ static int batch_checks(int prec) {
                 rc = 1;
             }
         }
-        if (rc == NOPCS_OK) std::printf("ok batch call %d: %d boxes bit-identical to their lone steps\n", rep, nb);
+        if (rc == NOPCS_OK)
+            std::printf("ok batch mode %d call %d: %d boxes bit-identical to their lone steps\n", modes[rep / 2],
+                        rep % 2, nb);
     }
     if (rc > 1) std::fprintf(stderr, "rk_step_batch failed: %d %s\n", rc, nopcs_last_error());
+    // more distinct batches than the cache holds (limit lowered to 3): every
+    // call a new step (the first box's workspace moved by 256 bytes each time,
+    // which changes no result), so cached steps are evicted while new ones are
+    // made; each call checked against the lone steps
+    const int nchurn = 8;
+    if (rc == NOPCS_OK && nopcs_set_graph_cache_limit(3) != NOPCS_OK) rc = 1;
+    std::vector<std::vector<double>> lone(2);
+    Buf wbig((wsb[0] + 256 * nchurn + 7) / 8);
+    for (int b = 0; b < 2 && rc == NOPCS_OK; ++b) {
+        std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+        rc = rk_step(&p, &g[b], prec, Q[b]->p, dt_call, 1, W[b]->p, wsb[b], nullptr);
+        lone[b].assign(Q[b]->p, Q[b]->p + n5[b]);
+    }
+    for (int c = 0; c < nchurn && rc == NOPCS_OK; ++c) {
+        nopcs_box two[2] = {boxes[0], boxes[1]};
+        two[0].dt = two[1].dt = 0.0;
+        two[0].ws = reinterpret_cast<char *>(wbig.p) + 256 * (size_t)c;
+        for (int b = 0; b < 2; ++b) std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
+        rc = nopcs_set_batch_mode(c % 4);
+        if (rc == NOPCS_OK) rc = rk_step_batch(&p, 2, two, prec, dt_call, 1, nullptr);
+        for (int b = 0; b < 2 && rc == NOPCS_OK; ++b)
+            if (std::memcmp(Q[b]->p, lone[b].data(), n5[b] * sizeof(double)) != 0) {
+                std::fprintf(stderr, "churn call %d: box %d differs from its lone step\n", c, b);
+                rc = 1;
+            }
+    }
+    if (rc == NOPCS_OK) std::printf("ok %d distinct batches through the cache\n", nchurn);
+    if (nopcs_set_graph_cache_limit(0) != NOPCS_EINVAL || nopcs_set_graph_cache_limit(64) != NOPCS_OK) rc = 1;
+    (void)nopcs_set_batch_mode(3);
     // errors: duplicate state, misaligned workspace, negative dt
     if (rc == NOPCS_OK) {
         std::vector<nopcs_box> bad = boxes;
@@ -312,7 +392,11 @@ int main(int argc, char **argv) {
                     P.grp.size());
         return 0;
     }
-    if (mode == "serve") return serve_checks();
+    if (mode == "serve" || mode == "serve_batched") {
+        const int rc = serve_checks(mode == "serve_batched");
+        nopcs_release_plans();   // cached batch launches included
+        return rc;
+    }
     if (mode == "batch") {
         const char *pe = std::getenv("NOPCS_EMUL_PRECISION");
         return batch_checks(pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64);

@@ -123,8 +123,8 @@ inline hipError_t hipSetDevice(int) { return hipSuccess; }
 inline hipError_t hipMalloc(void **p, size_t n) { *p = emu_guarded_alloc(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
 inline hipError_t hipFree(void *p) { emu_guarded_free(p); return hipSuccess; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
-inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t) { std::memcpy(d, s, n); return hipSuccess; }
-inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t);
+inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t);
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipErrorNotReady = 600 };
 inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t) new char; return hipSuccess; }
@@ -133,16 +133,49 @@ inline hipError_t hipGetDeviceCount(int *n) { *n = 1; return hipSuccess; }
 // a __device__ variable is a host variable here
 template <class T>
 inline hipError_t hipGetSymbolAddress(void **p, const T &sym) { *p = (void *)&sym; return hipSuccess; }
-// graphs: not available in the host build (capture reports an error; nothing is launched)
-typedef struct emu_graph *hipGraph_t;
-typedef struct emu_graph_exec *hipGraphExec_t;
-enum { hipStreamCaptureModeThreadLocal = 1, hipErrorNotSupported = 801 };
-inline hipError_t hipStreamBeginCapture(hipStream_t, int) { return hipErrorNotSupported; }
-inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) { *g = nullptr; return hipErrorNotSupported; }
-inline hipError_t hipGraphInstantiate(hipGraphExec_t *, hipGraph_t, void *, void *, size_t) { return hipErrorNotSupported; }
-inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
-inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
-inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+// Graphs: a capture records, on the capturing thread, every launch, copy and
+// fill in issue order (whatever the stream: the library captures forked branch
+// streams from that thread); a replay runs them in that order, which is one of
+// the orders the captured dependencies allow.
+#include <functional>
+struct emu_graph { std::vector<std::function<void()>> ops; };
+struct emu_graph_exec { std::vector<std::function<void()>> ops; };
+typedef emu_graph *hipGraph_t;
+typedef emu_graph_exec *hipGraphExec_t;
+enum { hipStreamCaptureModeThreadLocal = 1, hipErrorNotSupported = 801, hipErrorIllegalState = 401 };
+inline thread_local emu_graph *emu_capture = nullptr;
+inline hipError_t hipStreamBeginCapture(hipStream_t, int) {
+    if (emu_capture) return hipErrorIllegalState;
+    emu_capture = new emu_graph();
+    return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+    if (!emu_capture) return hipErrorIllegalState;
+    *g = emu_capture;
+    emu_capture = nullptr;
+    return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, void *, size_t) {
+    *x = new emu_graph_exec{g->ops};
+    return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) {
+    if (emu_capture) return hipErrorNotSupported;
+    for (auto &op : x->ops) op();
+    return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t x) { delete x; return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t) {
+    if (emu_capture) emu_capture->ops.push_back([=] { std::memcpy(d, s, n); });
+    else std::memcpy(d, s, n);
+    return hipSuccess;
+}
+inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
+    if (emu_capture) emu_capture->ops.push_back([=] { std::memset(d, v, n); });
+    else std::memset(d, v, n);
+    return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new emu_event(); return hipSuccess; }
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
@@ -275,7 +308,17 @@ inline void emu_barrier() {
 }
 
 template <class K, class... A>
+void emu_launch_now(K kernel, dim3 grid, dim3 block, A... args);
+template <class K, class... A>
 void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
+    if (emu_capture) {   // recorded with its arguments, run at each replay
+        emu_capture->ops.push_back([=] { emu_launch_now(kernel, grid, block, args...); });
+        return;
+    }
+    emu_launch_now(kernel, grid, block, args...);
+}
+template <class K, class... A>
+void emu_launch_now(K kernel, dim3 grid, dim3 block, A... args) {
     EmuSched &s = emu_sched();
     std::lock_guard<std::mutex> serial(s.launch_mu);
     const unsigned nt = block.x * block.y * block.z;

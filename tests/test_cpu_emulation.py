@@ -187,28 +187,36 @@ def test_emulated_rhs_line_march_with_closures(driver, tmp_path, shape, nseg, pi
         assert _rel(R[c], Ro[c]) <= 1e-13, c
 
 
-def test_emulated_serving_runtime(driver, tmp_path):
-    """Serving runtime on 8^3 boxes: results in a mix equal each box run alone
-    bit for bit, arrival-order admission under a one-box budget, a non-finite
-    box flagged, EBUSY / ENOMEM / ENOTFOUND / EINVAL, destroy with pending work."""
-    r = subprocess.run([driver, "serve"], capture_output=True, text=True, timeout=900)
+@pytest.mark.parametrize("mode", ["serve", "serve_batched"])
+def test_emulated_serving_runtime(driver, tmp_path, mode):
+    """Serving runtime on 8^3 boxes, each request on its own stream or all
+    resident requests in batched chunks: results in a mix equal each box run
+    alone bit for bit, arrival-order admission under a one-box budget, a
+    non-finite box flagged, EBUSY / ENOMEM / ENOTFOUND / EINVAL, destroy with
+    pending work."""
+    r = subprocess.run([driver, mode], capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "ok mix equals alone bit for bit" in r.stdout
+    assert "ok stream of 16 equals alone bit for bit" in r.stdout
 
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_emulated_batch_step(driver, tmp_path, mixed):
-    """rk_step_batch over five uneven boxes (one launch per stage kernel over all
-    boxes, issued directly; two boxes of one shape share every launch, one box
-    takes the call's dt, the others their own): each box bit-identical to
-    rk_step on it alone, on the first call and on the cached second; duplicate
-    states, misaligned workspaces, negative dt and an empty batch rejected."""
+    """rk_step_batch over five uneven boxes in every mode (shared launches as a
+    graph or issued directly, a graph branch per box, the hybrid; two boxes of
+    one shape share every launch, one box takes the call's dt, the others their
+    own): each box bit-identical to rk_step on it alone, on the first call and
+    on the cached second; 8 distinct two-box batches through a step cache
+    limited to 3 entries, each against the lone steps; duplicate states, misaligned
+    workspaces, negative dt and an empty batch rejected."""
     env = dict(os.environ)
     if mixed:
         env["NOPCS_EMUL_PRECISION"] = "1"
     r = subprocess.run([driver, "batch"], capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
-    assert "ok batch call 1: 5 boxes bit-identical to their lone steps" in r.stdout
+    for mode in (0, 1, 2, 3):
+        assert "ok batch mode %d call 1: 5 boxes bit-identical to their lone steps" % mode in r.stdout
+    assert "ok 8 distinct batches through the cache" in r.stdout
     assert "ok batch argument errors" in r.stdout
 
 

@@ -1,4 +1,5 @@
-"""Serving runtime on the GPU (solver_create / submit / poll / destroy).
+"""Serving runtime on the GPU (solver_create / submit / poll / destroy), each
+request on its own stream or all resident requests in batched chunks.
 
 Parity here is with the library's own single-box path: a request served in a
 mix of boxes must equal the same box advanced alone by rk_step, bit for bit
@@ -33,7 +34,8 @@ def _wait(S, rid):
 BOXES = [(32, 1, 7, 0), (48, 1, 5, 1), (64, 2, 9, 2), (40, 2, 6, 3), (72, 1, 4, 4)]
 
 
-def test_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("batched", [False, True])
+def test_mix_equals_alone_bitwise(batched):
     params = nopcs.make_params(inputs.AIR)
     dt = 1e-5
     work = []
@@ -41,7 +43,7 @@ def test_mix_equals_alone_bitwise():
         Q0 = inputs.rti_state(n, seed=seed, T_lower=420.0)
         g = nopcs.make_grid(n, nseg)
         work.append((g, Q0, steps, _alone(params, g, Q0, steps, dt)))
-    with nopcs.Solver(16 << 30, max_slots=3, max_queue=16) as S:
+    with nopcs.Solver(16 << 30, max_slots=3, max_queue=16, batched=batched) as S:
         ids = [S.submit(params, g, Q0, steps, dt) for g, Q0, steps, _ in work]
         for rid, (g, Q0, steps, ref) in zip(ids, work):
             rc, res, Q = _wait(S, rid)
@@ -59,7 +61,8 @@ def test_mix_equals_alone_bitwise():
                     assert err <= 1e-12 * np.max(np.abs(O[c])) and err <= 1e-12 * np.max(np.abs(O[c] - Q0[c]))
 
 
-def test_mixed_precision_requests_equal_alone_bitwise():
+@pytest.mark.parametrize("batched", [False, True])
+def test_mixed_precision_requests_equal_alone_bitwise(batched):
     """Mixed-precision requests (FP32 eliminations and RHS register) served beside
     FP64 ones: each equals its box advanced alone by rk_step in its precision."""
     params = nopcs.make_params(inputs.AIR)
@@ -70,7 +73,7 @@ def test_mixed_precision_requests_equal_alone_bitwise():
         Q0 = inputs.rti_state(n, seed=seed, T_lower=420.0)
         g = nopcs.make_grid(n, nseg)
         work.append((g, Q0, steps, prec, _alone(params, g, Q0, steps, dt, prec)))
-    with nopcs.Solver(16 << 30, max_slots=3, max_queue=8) as S:
+    with nopcs.Solver(16 << 30, max_slots=3, max_queue=8, batched=batched) as S:
         ids = [S.submit(params, g, Q0, steps, dt, precision=prec) for g, Q0, steps, prec, _ in work]
         for rid, (g, Q0, steps, prec, ref) in zip(ids, work):
             rc, res, Q = _wait(S, rid)
@@ -79,11 +82,12 @@ def test_mixed_precision_requests_equal_alone_bitwise():
             assert np.array_equal(Q, ref)
 
 
-def test_admission_order_and_budget():
+@pytest.mark.parametrize("batched", [False, True])
+def test_admission_order_and_budget(batched):
     params = nopcs.make_params(inputs.AIR)
     g = nopcs.make_grid(32, 1)
     fp = nopcs.workspace_bytes(g) + 5 * 32 ** 3 * 8
-    with nopcs.Solver(fp + 1024, max_slots=4, max_queue=8) as S:
+    with nopcs.Solver(fp + 1024, max_slots=4, max_queue=8, batched=batched) as S:
         ids = [S.submit(params, g, inputs.rti_state(32, seed=s), 3, 1e-5) for s in range(3)]
         res = [_wait(S, i)[1] for i in ids]
         for a, b in zip(res, res[1:]):
@@ -96,14 +100,15 @@ def test_admission_order_and_budget():
         assert e.value.code == nopcs.NOPCS_ENOTFOUND
 
 
-def test_nonfinite_request_flagged_others_unaffected():
+@pytest.mark.parametrize("batched", [False, True])
+def test_nonfinite_request_flagged_others_unaffected(batched):
     params = nopcs.make_params(inputs.AIR)
     g = nopcs.make_grid(32, 1)
     good = inputs.rti_state(32, seed=5)
     bad = good.copy()
     bad[4, 3, 4, 5] = np.inf
     ref = _alone(params, g, good, 3, 1e-5)
-    with nopcs.Solver(8 << 30, max_slots=2, max_queue=8) as S:
+    with nopcs.Solver(8 << 30, max_slots=2, max_queue=8, batched=batched) as S:
         ib = S.submit(params, g, bad, 3, 1e-5)
         ig = S.submit(params, g, good, 3, 1e-5)
         assert _wait(S, ib)[0] == nopcs.NOPCS_ENONFINITE
@@ -111,9 +116,10 @@ def test_nonfinite_request_flagged_others_unaffected():
         assert rc == nopcs.NOPCS_OK and np.array_equal(Q, ref)
 
 
-def test_serving_bench_small_stream():
+@pytest.mark.parametrize("batched", [False, True])
+def test_serving_bench_small_stream(batched):
     from paper_2203_00879_amd import serve_bench
-    out = serve_bench.run(n_req=12, step_scale=0.02, slots=4, budget_gb=40.0, check=3)
+    out = serve_bench.run(n_req=12, step_scale=0.02, slots=4, budget_gb=40.0, check=3, batched=batched)
     print(out, flush=True)
     assert out["all_ok"] and out["mix_equals_alone"]
     assert 0 < out["p50_latency_s"] <= out["p99_latency_s"]
