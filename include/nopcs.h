@@ -429,7 +429,10 @@ typedef struct {
     int32_t device;          /* HIP device ordinal */
     int32_t batched;         /* 0: each resident request steps on its own stream;
                                 1: all resident requests step together through
-                                rk_step_batch, one batch in flight at a time */
+                                rk_step_batch, one batch in flight at a time
+                                (switched off on the GPU: solver_create answers
+                                NOPCS_EINVAL; only the CPU build of the
+                                kernels runs it) */
 } solver_config;
 
 typedef struct {

@@ -124,7 +124,8 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time in seconds")
-    ap.add_argument("--batched", action="store_true", help="step resident requests in batched chunks")
+    ap.add_argument("--batched", action="store_true",
+                    help="step resident requests in batched chunks (the GPU build refuses it: switched off)")
     a = ap.parse_args()
     print(json.dumps(run(a.requests, a.step_scale, a.slots, a.budget_gb, a.check, a.verbose, a.precision,
                          a.mean_gap, a.batched)), flush=True)

@@ -12,6 +12,7 @@
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction;
 // NOPCS_EMUL_PRECISION=1 runs rhs and rk in mixed precision.
 #include <chrono>
+#include <random>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -381,6 +382,73 @@ static int batch_checks(int prec) {
     return rc == NOPCS_OK ? 0 : 1;
 }
 
+// A stream like the serving benchmark's on the CPU build: requests of
+// uneven small boxes arrive over time (seeded), every pending request polled
+// every millisecond, half of them in mixed precision, each with its own dt
+// and 1-20 steps; every result against its lone rk_step, bit for bit.
+static int serve_stress(int batched, int nr) {
+    std::mt19937 rng(4);
+    const int sizes[4][3] = {{8, 8, 8}, {12, 10, 9}, {16, 16, 12}, {9, 20, 10}};
+    const int segs[4][3] = {{1, 1, 1}, {1, 2, 1}, {2, 1, 1}, {1, 2, 1}};
+    nse_params p = air_params();
+    struct W { nopcs_grid g; std::vector<double> q0, want; int steps, prec; double dt, t; };
+    std::vector<W> w(nr);
+    double t = 0.0;
+    for (int r = 0; r < nr; ++r) {
+        const int k = (int)(rng() % 4);
+        for (int d = 0; d < 3; ++d) { w[r].g.n[d] = sizes[k][d]; w[r].g.nseg[d] = segs[k][d]; w[r].g.len[d] = 1.0; }
+        w[r].q0 = box_state(w[r].g.n, r);
+        w[r].steps = 1 + (int)(rng() % 20);
+        w[r].prec = (r % 2) ? NOPCS_MIXED : NOPCS_FP64;
+        w[r].dt = 1e-5 * (1.0 + 0.01 * (double)(rng() % 50));
+        t += 0.002 * (double)(rng() % 20);
+        w[r].t = t;
+        const size_t n5 = w[r].q0.size();
+        const size_t wsb = nopcs_workspace_bytes(&w[r].g, w[r].prec);
+        Buf Q(n5), ws((wsb + 7) / 8);
+        std::memcpy(Q.p, w[r].q0.data(), n5 * sizeof(double));
+        if (rk_step(&p, &w[r].g, w[r].prec, Q.p, w[r].dt, w[r].steps, ws.p, wsb, nullptr) != NOPCS_OK) return 1;
+        w[r].want.assign(Q.p, Q.p + n5);
+    }
+    solver_config cfg{(size_t)1 << 32, 8, nr, 0, batched};
+    nopcs_solver *s = nullptr;
+    SERVE_CHECK(solver_create(&cfg, &s) == NOPCS_OK, "create (stress)");
+    std::vector<uint64_t> id(nr);
+    std::vector<int> state(nr, 0);   // 0 not submitted, 1 pending, 2 done
+    int done = 0, k = 0;
+    bool same = true;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (done < nr) {
+        const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        while (k < nr && w[k].t <= now) {
+            solve_request q{};
+            q.params = p; q.grid = w[k].g; q.nsteps = w[k].steps; q.precision = w[k].prec; q.dt = w[k].dt;
+            q.Q0_host = w[k].q0.data();
+            if (solver_submit(s, &q, &id[k]) != NOPCS_OK) { std::fprintf(stderr, "submit %d failed\n", k); return 1; }
+            state[k++] = 1;
+        }
+        for (int r = 0; r < k; ++r) {
+            if (state[r] != 1) continue;
+            std::vector<double> out(w[r].q0.size());
+            solve_result res{};
+            const int rc = solver_poll(s, id[r], out.data(), &res);
+            if (rc == NOPCS_EAGAIN) continue;
+            state[r] = 2;
+            ++done;
+            if (rc != NOPCS_OK || res.steps_done != w[r].steps ||
+                std::memcmp(out.data(), w[r].want.data(), out.size() * sizeof(double)) != 0) {
+                std::fprintf(stderr, "request %d: status %d, steps %d of %d, or result differs\n", r, rc,
+                             res.steps_done, w[r].steps);
+                same = false;
+            }
+        }
+        std::this_thread::sleep_for(std::chrono::milliseconds(1));
+    }
+    SERVE_CHECK(same, "stress stream equals alone bit for bit");
+    SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy (stress)");
+    return 0;
+}
+
 int main(int argc, char **argv) {
     if (argc < 2) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
@@ -391,6 +459,11 @@ int main(int argc, char **argv) {
         std::printf("nrun %zu ncl %zu max_m %d k1_S %d ngrp %zu\n", P.runs.size(), P.cl_row.size(), P.max_m, P.k1_S,
                     P.grp.size());
         return 0;
+    }
+    if (mode == "serve_stress" && argc >= 4) {   // driver serve_stress batched nrequests
+        const int rc = serve_stress(std::atoi(argv[2]), std::atoi(argv[3]));
+        nopcs_release_plans();
+        return rc;
     }
     if (mode == "serve" || mode == "serve_batched") {
         const int rc = serve_checks(mode == "serve_batched");

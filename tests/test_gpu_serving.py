@@ -1,5 +1,5 @@
 """Serving runtime on the GPU (solver_create / submit / poll / destroy), each
-request on its own stream or all resident requests in batched chunks.
+request on its own stream (batched chunks: skipped, see BATCHED).
 
 Parity here is with the library's own single-box path: a request served in a
 mix of boxes must equal the same box advanced alone by rk_step, bit for bit
@@ -11,6 +11,13 @@ import oracle
 from paper_2203_00879_amd import inputs, nopcs
 
 pytestmark = pytest.mark.gpu
+
+# Batched serving (solver_config.batched = 1) is switched off on the GPU: a
+# stream of 256 boxes ended in a segmentation fault in a non-Python thread,
+# twice, without an explained cause.  Its cases stay here, skipped; the CPU
+# build of the kernels runs batched serving under AddressSanitizer.
+BATCHED = [False, pytest.param(True, marks=pytest.mark.skip(
+    reason="batched serving switched off on the GPU: unexplained host segfault in a 256-box stream"))]
 
 
 def _alone(params, grid, Q0, steps, dt, precision=nopcs.FP64):
@@ -34,7 +41,7 @@ def _wait(S, rid):
 BOXES = [(32, 1, 7, 0), (48, 1, 5, 1), (64, 2, 9, 2), (40, 2, 6, 3), (72, 1, 4, 4)]
 
 
-@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("batched", BATCHED)
 def test_mix_equals_alone_bitwise(batched):
     params = nopcs.make_params(inputs.AIR)
     dt = 1e-5
@@ -61,7 +68,7 @@ def test_mix_equals_alone_bitwise(batched):
                     assert err <= 1e-12 * np.max(np.abs(O[c])) and err <= 1e-12 * np.max(np.abs(O[c] - Q0[c]))
 
 
-@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("batched", BATCHED)
 def test_mixed_precision_requests_equal_alone_bitwise(batched):
     """Mixed-precision requests (FP32 eliminations and RHS register) served beside
     FP64 ones: each equals its box advanced alone by rk_step in its precision."""
@@ -82,7 +89,7 @@ def test_mixed_precision_requests_equal_alone_bitwise(batched):
             assert np.array_equal(Q, ref)
 
 
-@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("batched", BATCHED)
 def test_admission_order_and_budget(batched):
     params = nopcs.make_params(inputs.AIR)
     g = nopcs.make_grid(32, 1)
@@ -100,7 +107,7 @@ def test_admission_order_and_budget(batched):
         assert e.value.code == nopcs.NOPCS_ENOTFOUND
 
 
-@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("batched", BATCHED)
 def test_nonfinite_request_flagged_others_unaffected(batched):
     params = nopcs.make_params(inputs.AIR)
     g = nopcs.make_grid(32, 1)
@@ -116,10 +123,16 @@ def test_nonfinite_request_flagged_others_unaffected(batched):
         assert rc == nopcs.NOPCS_OK and np.array_equal(Q, ref)
 
 
-@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("batched", BATCHED)
 def test_serving_bench_small_stream(batched):
     from paper_2203_00879_amd import serve_bench
     out = serve_bench.run(n_req=12, step_scale=0.02, slots=4, budget_gb=40.0, check=3, batched=batched)
     print(out, flush=True)
     assert out["all_ok"] and out["mix_equals_alone"]
     assert 0 < out["p50_latency_s"] <= out["p99_latency_s"]
+
+
+def test_batched_serving_refused_on_the_gpu():
+    with pytest.raises(nopcs.NopcsError) as e:
+        nopcs.Solver(1 << 30, max_slots=2, max_queue=4, batched=True)
+    assert e.value.code == nopcs.NOPCS_EINVAL
