@@ -569,9 +569,6 @@ struct ClosureLineBody {
 template <int DIR, bool FULL, class TR, class TC, int RKS>
 struct MarchBody {
     using Args = MarchArgs;
-#ifdef NOPCS_MARCH_WAVES
-    static constexpr int kMinWaves = NOPCS_MARCH_WAVES;
-#endif
     __device__ static void run(const Args &a, int b, int) {
         march_sweep_body<DIR, FULL, TR, TC, RKS>(a.Q, static_cast<TR *>(a.R), a.clo, a.g, a.pl, a.c, a.F, b);
     }

@@ -286,9 +286,6 @@ struct SweepArgs {
 template <int DIR, int NMAX, class TR>
 struct SweepBody {
     using Args = SweepArgs;
-#ifdef NOPCS_SWEEP_WAVES
-    static constexpr int kMinWaves = NOPCS_SWEEP_WAVES;
-#endif
     __device__ static void run(const Args &x, int b, int) { nse_sweep_body<DIR, NMAX, TR>(x.a, x.g, x.pl, b); }
 };
 struct RkUpdArgs {
