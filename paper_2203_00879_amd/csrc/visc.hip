@@ -6,7 +6,9 @@
 // wall nodes (Section 4).
 //
 // One block owns a CTX x CTY tile of output columns plus a two-column halo and
-// marches along z over a chunk of planes; one thread per column.  Each thread
+// marches along z over a chunk of planes; one thread per column, one barrier
+// per plane (primitives and fluxes of plane k in LDS buffer k mod 2 while the
+// divergence of plane k-1 reads the other buffer).  Each thread
 // keeps the primitives (u, v, w, T) of its own column for planes k-2..k+2 in
 // registers, so z differences need no shared memory.  Per plane, every column
 // publishes its primitives in LDS once; every node then evaluates its gradients,
@@ -98,7 +100,9 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     const bool needE = indom && ci >= 1 && ci <= CTX + 2 && iny;   // includes every center
     const bool needF = indom && cj >= 1 && cj <= CTY + 2 && inx;
     const long long col = indom ? gi + (long long)A.nx * gj : 0;
-    double *const Pu = S, *const Pv = S + CNT, *const Pw = S + 2 * CNT, *const PT = S + 3 * CNT;
+    // S holds two buffers of 12 fields (planes of even and odd k), each per
+    // column slot: u, v, w, T of the plane (fields 0-3), Ev (4-7), Fv (8-11)
+    constexpr int SB = 12 * CNT;
 
     // raw state of one plane of this column (a benign dummy outside the box);
     // the loads are unconditional (clamped address, select afterwards) so that
@@ -144,9 +148,16 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     load(kb + 1, raw);
     if (VPF >= 2) load(kb + 2, rawB);
     if (VPF == 3) load(kb + 3, rawC);
-    // G history (planes k-2, k-1, k) and the pending dEv/dx + dFv/dy of plane k-1
+    // G history (planes k-2, k-1, k)
     double G[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double partPrev[4] = {0, 0, 0, 0};
+    // dEv/dx + dFv/dy at plane p from the fluxes in buffer p & 1
+    auto xy_part = [&](int p, double part[4]) {
+        const double *Sc = S + (p & 1) * SB;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            part[q] = dplane<WALL>(Sc + (4 + q) * CNT, tid, 1, gi, A.nx, A.ihx) +
+                      dplane<WALL>(Sc + (8 + q) * CNT, tid, CX, gj, A.ny, A.ihy);
+    };
 
     // plane k; cur holds the raw state of plane k+1 and receives that of
     // k+1+VPF; nxt (two or three planes in flight) holds k+2.  With VPF
@@ -168,6 +179,10 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
         wr[2] = cur[0];
         wy[2] = cur[2];
         load(k + 1 + VPF, cur);
+        // one barrier per plane: the primitives and fluxes of plane k go to
+        // buffer k & 1 while the divergence of plane k-1 reads buffer (k-1) & 1
+        double *const Sb = S + (k & 1) * SB;
+        double *const Pu = Sb, *const Pv = Sb + CNT, *const Pw = Sb + 2 * CNT, *const PT = Sb + 3 * CNT;
         Pu[tid] = wu[1];
         Pv[tid] = wv[1];
         Pw[tid] = ww[1];
@@ -203,17 +218,17 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             const double tyz = m * (dz(wv, vm2, vp2, k, A.nz, A.ihz) + dplane<WALL>(Pw, tid, CX, gj, A.ny, A.ihy)) * c.iRe;
             if (needE) {
                 const double qx = -c.kappa * m * dplane<WALL>(PT, tid, 1, gi, A.nx, A.ihx);
-                S[4 * CNT + tid] = txx;
-                S[5 * CNT + tid] = txy;
-                S[6 * CNT + tid] = txz;
-                S[7 * CNT + tid] = u * txx + v * txy + w * txz - qx;
+                Sb[4 * CNT + tid] = txx;
+                Sb[5 * CNT + tid] = txy;
+                Sb[6 * CNT + tid] = txz;
+                Sb[7 * CNT + tid] = u * txx + v * txy + w * txz - qx;
             }
             if (needF) {
                 const double qy = -c.kappa * m * dplane<WALL>(PT, tid, CX, gj, A.ny, A.ihy);
-                S[8 * CNT + tid] = txy;
-                S[9 * CNT + tid] = tyy;
-                S[10 * CNT + tid] = tyz;
-                S[11 * CNT + tid] = u * txy + v * tyy + w * tyz - qy;
+                Sb[8 * CNT + tid] = txy;
+                Sb[9 * CNT + tid] = tyy;
+                Sb[10 * CNT + tid] = tyz;
+                Sb[11 * CNT + tid] = u * txy + v * tyy + w * tyz - qy;
             }
             if (center) {
                 const double qz = -c.kappa * m * dz(wT, Tm2, Tp2, k, A.nz, A.ihz);
@@ -223,7 +238,6 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
                 Gk[3] = u * txz + v * tyz + w * tzz - qz;
             }
         }
-        __syncthreads();
         if (center) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -231,24 +245,20 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
                 G[1][q] = G[2][q];
                 G[2][q] = Gk[q];
             }
-            // dEv/dx + dFv/dy at plane k
+            // plane k-1: its fluxes were written before this plane's barrier
+            const bool own_prev = k - 1 >= k0 && k - 1 < k1 && k - 1 >= kb;
             double part[4] = {0, 0, 0, 0};
-            if (k >= k0 && k < k1) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    part[q] = dplane<WALL>(S + (4 + q) * CNT, tid, 1, gi, A.nx, A.ihx) +
-                              dplane<WALL>(S + (8 + q) * CNT, tid, CX, gj, A.ny, A.ihy);
-            }
+            if (own_prev) xy_part(k - 1, part);
             // finish plane k-1 (inside): needs G(k) - G(k-2)
-            if (k - 1 >= k0 && k - 1 < k1 && k - 1 >= 1 && k - 1 <= A.nz - 2) {
+            if (own_prev && k - 1 >= 1 && k - 1 <= A.nz - 2) {
                 double acc[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = partPrev[q] + d2c(G[0][q], G[2][q], A.ihz);
+                for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2c(G[0][q], G[2][q], A.ihz);
                 write_R(k - 1, acc, wr[0], wy[0]);
             }
             // the bottom wall plane waits for G(0), G(1), G(2); its x-y part is
             // parked in R, where only this thread reads it back
-            if (k == 0) {
+            if (own_prev && k - 1 == 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) R[(q + 1) * N3 + col] = TR(part[q]);
             }
@@ -259,15 +269,6 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
                     acc[q] = double(R[(q + 1) * N3 + col]) + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
                 write_R(0, acc, Q[col], Q[2 * N3 + col]);
             }
-            // the top wall plane nz-1 is finished with G(nz-1), G(nz-2), G(nz-3)
-            if (k == A.nz - 1 && k < k1) {
-                double acc[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], A.ihz, true);
-                write_R(k, acc, wr[1], wy[1]);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) partPrev[q] = part[q];
         }
     };
     if (VPF == 1) {
@@ -285,6 +286,18 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             plane_step(k, raw, rawB);
             if (k + 1 <= ke) plane_step(k + 1, rawB, rawC);
             if (k + 2 <= ke) plane_step(k + 2, rawC, raw);
+        }
+    }
+    // the top wall plane nz-1 (its fluxes written by the last plane step) is
+    // finished with G(nz-1), G(nz-2), G(nz-3)
+    if (ke == A.nz - 1 && ke < k1) {
+        __syncthreads();
+        if (center) {
+            double part[4], acc[4];
+            xy_part(ke, part);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], A.ihz, true);
+            write_R(ke, acc, wr[1], wy[1]);
         }
     }
 }
@@ -314,7 +327,7 @@ __device__ inline void visc_body(const VArgs &A, int b) {
         }
         return;
     }
-    __shared__ double S[12 * CNT];
+    __shared__ double S[2 * 12 * CNT];
     // every column and every flux node of the tile off the x and y walls
     const bool interior = i0 >= 2 && i0 + CTX + 2 <= A.nx && j0 >= 2 && j0 + CTY + 2 <= A.ny;
     if (interior) visc_march<false, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
