@@ -37,12 +37,12 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 KERNEL_NAMES = ["viscous", "sweep_x", "sweep_y", "sweep_z", "wall", "derivative", "rk_update", "closure_y",
                 "closure_z"]
 KERNEL_SOURCES = {
-    "viscous": ["visc.hip", "common.hpp", "kernels.hpp"],
-    "sweep_x": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp"],
-    "sweep_y": ["march.hip", "common.hpp", "plan.cpp"],
-    "sweep_z": ["march.hip", "common.hpp", "plan.cpp", "kernels.hpp"],
-    "closure_y": ["march.hip", "common.hpp", "plan.cpp"],
-    "closure_z": ["march.hip", "common.hpp", "plan.cpp"],
+    "viscous": ["visc.hip", "common.hpp", "kernels.hpp", "batch.hpp"],
+    "sweep_x": ["sweep.hip", "sweep.hpp", "common.hpp", "plan.cpp", "batch.hpp"],
+    "sweep_y": ["march.hip", "common.hpp", "plan.cpp", "batch.hpp"],
+    "sweep_z": ["march.hip", "common.hpp", "plan.cpp", "kernels.hpp", "batch.hpp"],
+    "closure_y": ["march.hip", "common.hpp", "plan.cpp", "batch.hpp"],
+    "closure_z": ["march.hip", "common.hpp", "plan.cpp", "batch.hpp"],
     "rk_update": ["sweep.hip"],
     "wall": ["visc.hip", "common.hpp"],
 }
