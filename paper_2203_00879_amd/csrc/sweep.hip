@@ -34,19 +34,26 @@ __device__ inline int wall_row(int s, int n) {
 // ---------------------------------------------------------------------------
 // Lines per pencil of the standalone derivative: along y and z the lines of a
 // pencil are neighbours in x, so every row is one contiguous run of P values;
-// with a single LDS component the pencil holds 4096 values (twice the
-// multi-component sweeps' share): 16 lines of up to 256 points, 8 of 512, 4 of
-// 1024.
+// with a single LDS component the pencil holds 8192 values: 32 lines of up to
+// 256 points, 16 of 512, 8 of 1024.
 template <int DIR, int NMAX>
 constexpr int deriv_pencil_width() {
-    return DIR == 0 || NMAX <= 128 ? 0 : 4096 / NMAX;
+    return DIR == 0 || NMAX <= 128 ? 0 : 8192 / NMAX;
+}
+// threads per block of the standalone single-field pencil kernels: along y
+// and z 512 threads stage 8192 values (16 lines of 512 points, 128-byte rows;
+// 75 KB of LDS, two blocks per CU at 107 VGPRs), 256 elsewhere
+template <int DIR, int NMAX>
+constexpr int deriv_threads() {
+    return DIR == 0 || NMAX <= 128 ? 256 : 512;
 }
 
 template <int DIR, int NMAX>
-__global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, double *d1, double *d2, SweepGeom g,
-                                               LinePlanDev pl) {
+__global__ __launch_bounds__((deriv_threads<DIR, NMAX>())) void k_deriv(const double *__restrict__ f, double *d1,
+                                                                      double *d2, SweepGeom g, LinePlanDev pl) {
     constexpr int PW = deriv_pencil_width<DIR, NMAX>();
-    using C = SweepCfg<DIR, NMAX, PW>;
+    constexpr int NTH = deriv_threads<DIR, NMAX>();
+    using C = SweepCfg<DIR, NMAX, PW, NTH>;
     __shared__ double F[C::FSZ];
     __shared__ double KN[C::P * C::KMAX];
     int np;
@@ -54,7 +61,7 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
     pencil_of<C>(g, np, base);
     const int n = g.n;
     int ks[C::PTS];
-    owned_slots<DIR, NMAX, PW>(pl, ks);
+    owned_slots<DIR, NMAX, PW, NTH>(pl, ks);
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
@@ -62,13 +69,13 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
         if (l < np && i < n) F[C::fidx(l, i)] = f[base + l * g.sA + i * g.sD];
     }
     __syncthreads();
-    lds_line_solve<DIR, NMAX, 1, PW>(F, KN, pl, np);
+    lds_line_solve<DIR, NMAX, 1, PW, OP_D1, NTH>(F, KN, pl, np);
     if (d1) {
 #pragma unroll
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
+            if (l < np && i < n) d1[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW, NTH>(F, KN, 0, ks[s], l, i);
         }
     }
     if (d2) {
@@ -81,12 +88,12 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
             F[C::fidx(l, row)] = KN[C::kidx(s, l)];
         }
         __syncthreads();
-        lds_line_solve<DIR, NMAX, 1, PW>(F, KN, pl, np);
+        lds_line_solve<DIR, NMAX, 1, PW, OP_D1, NTH>(F, KN, pl, np);
 #pragma unroll
         for (int s = 0; s < C::PTS; ++s) {
             int l, i;
             C::owned(threadIdx.x + s * C::NT, l, i);
-            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
+            if (l < np && i < n) d2[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW, NTH>(F, KN, 0, ks[s], l, i);
         }
     }
 }
@@ -96,9 +103,11 @@ __global__ __launch_bounds__(256) void k_deriv(const double *__restrict__ f, dou
 // reads its whole pencil before it writes any of it, and pencils are disjoint).
 // ---------------------------------------------------------------------------
 template <int DIR, int NMAX>
-__global__ __launch_bounds__(256) void k_filter(const double *f, double *out, SweepGeom g, LinePlanDev pl) {
+__global__ __launch_bounds__((deriv_threads<DIR, NMAX>())) void k_filter(const double *f, double *out, SweepGeom g,
+                                                                         LinePlanDev pl) {
     constexpr int PW = deriv_pencil_width<DIR, NMAX>();
-    using C = SweepCfg<DIR, NMAX, PW>;
+    constexpr int NTH = deriv_threads<DIR, NMAX>();
+    using C = SweepCfg<DIR, NMAX, PW, NTH>;
     __shared__ double F[C::FSZ];
     __shared__ double KN[C::P * C::KMAX];
     int np;
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256) void k_filter(const double *f, double *out, Sw
     pencil_of<C>(g, np, base);
     const int n = g.n;
     int ks[C::PTS];
-    owned_slots<DIR, NMAX, PW>(pl, ks);
+    owned_slots<DIR, NMAX, PW, NTH>(pl, ks);
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
@@ -114,12 +123,12 @@ __global__ __launch_bounds__(256) void k_filter(const double *f, double *out, Sw
         if (l < np && i < n) F[C::fidx(l, i)] = f[base + l * g.sA + i * g.sD];
     }
     __syncthreads();
-    lds_line_solve<DIR, NMAX, 1, PW, OP_FILTER>(F, KN, pl, np);
+    lds_line_solve<DIR, NMAX, 1, PW, OP_FILTER, NTH>(F, KN, pl, np);
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;
         C::owned(threadIdx.x + s * C::NT, l, i);
-        if (l < np && i < n) out[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW>(F, KN, 0, ks[s], l, i);
+        if (l < np && i < n) out[base + l * g.sA + i * g.sD] = lds_result<DIR, NMAX, PW, NTH>(F, KN, 0, ks[s], l, i);
     }
 }
 
@@ -335,7 +344,7 @@ hipError_t launch_rk_update(const NseSweepArgs &a, hipStream_t st, BatchCollecto
 template <int DIR, int NMAX>
 static hipError_t launch_deriv_t(const double *f, double *d1, double *d2, const SweepGeom &g, const LinePlanDev &pl,
                                  hipStream_t st) {
-    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>()>;
+    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>(), deriv_threads<DIR, NMAX>()>;
     const int npa = (g.nA + C::P - 1) / C::P;
     const long long blocks = (long long)npa * g.nB;
     hipLaunchKernelGGL((k_deriv<DIR, NMAX>), dim3((unsigned)blocks), dim3(C::NT), 0, st, f, d1, d2, g, pl);
@@ -345,7 +354,7 @@ static hipError_t launch_deriv_t(const double *f, double *d1, double *d2, const 
 template <int DIR, int NMAX>
 static hipError_t launch_filter_t(const double *f, double *out, const SweepGeom &g, const LinePlanDev &pl,
                                   hipStream_t st) {
-    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>()>;
+    using C = SweepCfg<DIR, NMAX, deriv_pencil_width<DIR, NMAX>(), deriv_threads<DIR, NMAX>()>;
     const int npa = (g.nA + C::P - 1) / C::P;
     const long long blocks = (long long)npa * g.nB;
     hipLaunchKernelGGL((k_filter<DIR, NMAX>), dim3((unsigned)blocks), dim3(C::NT), 0, st, f, out, g, pl);

@@ -25,12 +25,12 @@
 
 namespace nopcs {
 
-template <int DIR, int NMAX, int PW = 0>
+template <int DIR, int NMAX, int PW = 0, int NTH = 256>
 struct SweepCfg {
     // lines per pencil: every configuration keeps the block within 64 KB of LDS;
     // PW > 0 sets it (a single-component kernel can afford wider pencils)
     static constexpr int P = PW > 0 ? PW : NMAX <= 128 ? 1024 / NMAX : 2048 / NMAX;
-    static constexpr int NT = 256;                                   // threads per block
+    static constexpr int NT = NTH;                                   // threads per block
     static constexpr int PTS = (P * NMAX) / NT;                      // owned slots per thread
     static constexpr int G = 2;                                      // components per LDS pass
     static constexpr int KMAX = NMAX <= 128 ? NMAX / 2 + 4 : NMAX / 8 + 8;
@@ -84,9 +84,9 @@ inline SweepGeom sweep_geom(const int n[3], int dir) {
 // derivative: closure rows f_e + sum_j C_ej (f_j - f_e) (the filter's rows sum
 // to 1), wall rows unfiltered, interior right-hand side
 // a0 f_i + a1/2 (f_{i+1} + f_{i-1}) + a2/2 (f_{i+2} + f_{i-2}), A = (af, 1, af).
-template <int DIR, int NMAX, int NC, int PW = 0, int OP = OP_D1>
+template <int DIR, int NMAX, int NC, int PW = 0, int OP = OP_D1, int NTH = 256>
 __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev &pl, int np) {
-    using C = SweepCfg<DIR, NMAX, PW>;
+    using C = SweepCfg<DIR, NMAX, PW, NTH>;
     constexpr int KS = C::P * C::KMAX;
     auto F = [&](int c) -> double * { return Fb + c * C::FSZ; };
     auto KN = [&](int c) -> double * { return KNb + c * KS; };
@@ -260,16 +260,16 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
 
 // f' of component c at (l, i) after lds_line_solve; ks = pl.kslot[i] (the
 // known-row slot of row i, -1 for a compact row), read once by the caller
-template <int DIR, int NMAX, int PW = 0>
+template <int DIR, int NMAX, int PW = 0, int NTH = 256>
 __device__ inline double lds_result(const double *Fb, const double *KNb, int c, int ks, int l, int i) {
-    using C = SweepCfg<DIR, NMAX, PW>;
+    using C = SweepCfg<DIR, NMAX, PW, NTH>;
     return ks < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(ks, l)];
 }
 
 // known-row slots of a thread's owned points (clamped index: always a valid read)
-template <int DIR, int NMAX, int PW = 0>
-__device__ inline void owned_slots(const LinePlanDev &pl, int ks[SweepCfg<DIR, NMAX, PW>::PTS]) {
-    using C = SweepCfg<DIR, NMAX, PW>;
+template <int DIR, int NMAX, int PW = 0, int NTH = 256>
+__device__ inline void owned_slots(const LinePlanDev &pl, int ks[SweepCfg<DIR, NMAX, PW, NTH>::PTS]) {
+    using C = SweepCfg<DIR, NMAX, PW, NTH>;
 #pragma unroll
     for (int s = 0; s < C::PTS; ++s) {
         int l, i;

@@ -8,7 +8,8 @@
 //   driver plan  n nseg piece_len                            (prints the line-march tables)
 //   driver serve | serve_batched          (scripted checks of the serving runtime; per-request streams
 //                                          or batched chunks)
-//   driver batch                       (batched stepping of uneven boxes against each box's lone step)
+//   driver batch [modes]               (batched stepping of uneven boxes against each box's lone step,
+//                                       in the listed batch modes, default 2013)
 // Environment: NOPCS_EMUL_PIECE sets the extra-cut length of every direction;
 // NOPCS_EMUL_PRECISION=1 runs rhs and rk in mixed precision.
 #include <chrono>
@@ -211,11 +212,11 @@ static int serve_checks(int batched) {
         solver_config badcfg{fp, 0, 1, 0, batched};
         SERVE_CHECK(solver_create(&badcfg, &s) == NOPCS_EINVAL, "zero slots rejected");
     }
-    // 4. a stream of 16 requests on 4 slots, each with its own dt and 1-3
+    // 4. a stream of 8 requests on 4 slots, each with its own dt and 1-3
     //    steps (requests joining and leaving batches at every chunk): every
     //    result equals its box run alone, bit for bit
     {
-        const int nr = 16;
+        const int nr = 8;
         std::vector<std::vector<double>> want(nr);
         std::vector<double> dts(nr);
         std::vector<int> nst(nr);
@@ -249,7 +250,7 @@ static int serve_checks(int batched) {
             same = same && rc == NOPCS_OK && res.steps_done == nst[r] &&
                    std::memcmp(out.data(), want[r].data(), N5 * sizeof(double)) == 0;
         }
-        SERVE_CHECK(same, "stream of 16 equals alone bit for bit");
+        SERVE_CHECK(same, "stream of 8 equals alone bit for bit");
         SERVE_CHECK(solver_destroy(s) == NOPCS_OK, "destroy (stream)");
     }
     return 0;
@@ -276,7 +277,7 @@ static std::vector<double> box_state(const int n[3], int seed) {
 
 // Batched stepping (rk_step_batch, direct launches) of uneven boxes against
 // rk_step on each box alone: every box bit for bit.
-static int batch_checks(int prec) {
+static int batch_checks(int prec, const std::string &mode_list) {
     struct Shape { int n[3], s[3]; double dt; };
     const Shape shapes[] = {{{8, 8, 8}, {1, 1, 1}, 1e-5},
                             {{16, 12, 10}, {2, 1, 1}, 2e-5},
@@ -313,8 +314,10 @@ static int batch_checks(int prec) {
     std::vector<nopcs_box> boxes(nb);
     for (int b = 0; b < nb; ++b) boxes[b] = nopcs_box{g[b], Q[b]->p, W[b]->p, wsb[b], shapes[b].dt};
     int rc = NOPCS_OK;
-    const int modes[4] = {2, 0, 1, 3};
-    for (int rep = 0; rep < 8 && rc == NOPCS_OK; ++rep) {   // per mode: the second call replays the cached step
+    std::vector<int> modes;
+    for (char ch : mode_list) modes.push_back(ch - '0');
+    const int nrep = 2 * (int)modes.size();
+    for (int rep = 0; rep < nrep && rc == NOPCS_OK; ++rep) {   // per mode: the second call replays the cached step
         if (rep % 2 == 0) rc = nopcs_set_batch_mode(modes[rep / 2]);
         for (int b = 0; b < nb; ++b) std::memcpy(Q[b]->p, q0[b].data(), n5[b] * sizeof(double));
         if (rc == NOPCS_OK) rc = rk_step_batch(&p, nb, boxes.data(), prec, dt_call, nsteps, nullptr);
@@ -470,9 +473,9 @@ int main(int argc, char **argv) {
         nopcs_release_plans();   // cached batch launches included
         return rc;
     }
-    if (mode == "batch") {
+    if (mode == "batch") {   // driver batch [modes, e.g. 2013]
         const char *pe = std::getenv("NOPCS_EMUL_PRECISION");
-        return batch_checks(pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64);
+        return batch_checks(pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64, argc > 2 ? argv[2] : "2013");
     }
     if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
     // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)

@@ -197,24 +197,27 @@ def test_emulated_serving_runtime(driver, tmp_path, mode):
     r = subprocess.run([driver, mode], capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "ok mix equals alone bit for bit" in r.stdout
-    assert "ok stream of 16 equals alone bit for bit" in r.stdout
+    assert "ok stream of 8 equals alone bit for bit" in r.stdout
 
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_emulated_batch_step(driver, tmp_path, mixed):
-    """rk_step_batch over five uneven boxes in every mode (shared launches as a
-    graph or issued directly, a graph branch per box, the hybrid; two boxes of
-    one shape share every launch, one box takes the call's dt, the others their
-    own): each box bit-identical to rk_step on it alone, on the first call and
-    on the cached second; 8 distinct two-box batches through a step cache
-    limited to 3 entries, each against the lone steps; duplicate states, misaligned
+    """rk_step_batch over five uneven boxes (two of one shape sharing every
+    launch, one taking the call's dt, the others their own), in every mode in
+    FP64 (shared launches as a graph or issued directly, a graph branch per
+    box, the hybrid) and in the direct and the default mode in mixed precision:
+    each box bit-identical to rk_step on it alone, on the first call and on the
+    cached second; 8 distinct two-box batches through a step cache limited to
+    3 entries, each against the lone steps; duplicate states, misaligned
     workspaces, negative dt and an empty batch rejected."""
     env = dict(os.environ)
     if mixed:
         env["NOPCS_EMUL_PRECISION"] = "1"
-    r = subprocess.run([driver, "batch"], capture_output=True, text=True, timeout=900, env=env)
+    modes = (2, 3) if mixed else (2, 0, 1, 3)   # mixed precision: the direct and the default mode
+    r = subprocess.run([driver, "batch", "".join(map(str, modes))], capture_output=True, text=True, timeout=900,
+                       env=env)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
-    for mode in (0, 1, 2, 3):
+    for mode in modes:
         assert "ok batch mode %d call 1: 5 boxes bit-identical to their lone steps" % mode in r.stdout
     assert "ok 8 distinct batches through the cache" in r.stdout
     assert "ok batch argument errors" in r.stdout
