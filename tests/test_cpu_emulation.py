@@ -64,12 +64,16 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("shape, nseg", [((27, 19, 22), (3, 2, 4)), ((16, 17, 20), (4, 4, 5)),
-                                         ((10, 300, 9), (1, 3, 1)), ((9, 8, 520), (1, 1, 4))])
+                                         ((10, 300, 9), (1, 3, 1)), ((9, 8, 520), (1, 1, 4)),
+                                         ((1024, 9, 8), (7, 1, 1)), ((8, 1024, 9), (1, 13, 1)),
+                                         ((9, 8, 1024), (1, 1, 60))])
 def test_emulated_derivative_segmented(driver, tmp_path, shape, nseg):
     """Segmented lines, the second case with 4-point segments (Thomas runs of a
-    single unknown, whose first row is also its last); the last two take the
-    wide pencils of 300-point y lines (8 per block) and 520-point z lines (4 per
-    block), with a ragged last pencil."""
+    single unknown, whose first row is also its last); the next two take the
+    512-thread pencils of 300-point y lines (16 per block) and 520-point z
+    lines (8 per block), with a ragged last pencil; the last three the longest
+    lines (1024 points) along x, y and z, the last with 60 segments (118
+    closure rows, near the pencil's capacity of 132)."""
     f = np.random.default_rng(1).normal(size=shape[::-1])
     fin, fout = tmp_path / "f.raw", tmp_path / "d.raw"
     f.tofile(fin)
@@ -170,7 +174,8 @@ def test_emulated_rhs_tiles(driver, tmp_path, shape, v, g):
         assert _rel(R[c], Ro[c]) <= 4e-15
 
 
-@pytest.mark.parametrize("shape, nseg, piece", [((8, 36, 100), (1, 2, 3), 16), ((8, 20, 200), (1, 1, 2), -1)])
+@pytest.mark.parametrize("shape, nseg, piece", [((8, 36, 100), (1, 2, 3), 16), ((8, 20, 200), (1, 1, 2), -1),
+                                                ((1024, 9, 8), (5, 1, 1), -1), ((8, 1024, 9), (1, 7, 1), -1)])
 def test_emulated_rhs_line_march_with_closures(driver, tmp_path, shape, nseg, piece):
     """Lines along y and z long enough to be cut into pieces: the line-march
     sweeps (closure pass with 16 or 8 accumulator slots, run march with one or

@@ -59,6 +59,9 @@ DERIV_CASES = [
     ((64, 64, 64), (2, 4, 16)),      # maximum segment count for 64 points
     ((130, 70, 97), (3, 1, 2)),      # crosses the 128-point class, ragged tails
     ((257, 36, 20), (5, 2, 1)),      # long x lines (512 class)
+    ((1024, 9, 8), (7, 1, 1)),       # longest lines: x, 7 uneven segments
+    ((8, 1024, 9), (1, 13, 1)),      # longest lines: y (512-thread pencils of 8 lines)
+    ((9, 8, 1024), (1, 1, 60)),      # longest lines: z, 60 segments (118 closure rows of 132)
 ]
 
 
@@ -140,6 +143,9 @@ RHS_CASES = [
     ((33, 70, 29), (1, 4, 2), 1, 0),
     ((64, 24, 40), (4, 2, 2), 0, 1),
     ((100, 20, 131), (3, 1, 5), 1, 1),
+    ((1024, 10, 9), (5, 1, 1), 1, 1),     # longest x lines (1024-point pencils)
+    ((10, 1024, 9), (1, 7, 1), 1, 1),     # longest y lines (line march with pieces)
+    ((9, 10, 1024), (1, 1, 9), 0, 1),     # longest z lines
 ]
 
 
@@ -287,6 +293,31 @@ def test_rk_smooth_state_segmented_short():
         e = rel_err(G[c], O[c])
         say("  field", c, "err %.3e" % e)
         assert e <= TOL
+
+
+@pytest.mark.parametrize("shape,nseg", [((1024, 12, 10), (4, 1, 1)), ((10, 12, 1024), (1, 1, 6))])
+def test_rk_longest_lines(shape, nseg):
+    """Two RK4 steps with 1024-point lines along x (pencil sweep) or z (the z
+    march carrying the stage update), smooth state: every field within 1e-12."""
+    say("rk longest lines", shape, nseg)
+    p = dict(inputs.AIR)
+    Q = inputs.smooth_state(shape, seed=5, amp_u=0.02)
+    G = run_gpu_rk(p, Q, nseg, 2e-6, 2)
+    O = oracle.rk4(p, Q, 2e-6, 2)
+    for c in range(5):
+        e = rel_err(G[c], O[c])
+        say("  field", c, "err %.3e" % e)
+        assert e <= TOL
+
+
+def test_too_many_segments_rejected():
+    """More closure rows than a pencil holds (1024 points in 256 segments): the
+    call fails with NOPCS_EINVAL before any launch."""
+    f = torch.zeros((1024, 8, 8), dtype=torch.float64, device=DEV)
+    g = nopcs.make_grid((8, 8, 1024), (1, 1, 256))
+    with pytest.raises(nopcs.NopcsError) as e:
+        nopcs.nopcs_derivative(g, 2, f, torch.empty_like(f), None)
+    assert e.value.code == nopcs.NOPCS_EINVAL
 
 
 def test_rk_paper_setup_anisotropic_uneven_segments():
