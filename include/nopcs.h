@@ -383,12 +383,26 @@ int nopcs_set_piece_length(int32_t dir, int32_t piece_len);
  * timing rk_step (one untimed step, then two timed with HIP events on
  * hip_stream) on a scratch copy of Q for each candidate (n <= 64: 0, 16, 32;
  * longer lines: 16, 24, 32 points), one direction after the other, and leave
- * the fastest set with nopcs_set_piece_length (process-wide).  Candidates whose
+ * the fastest set with nopcs_set_piece_length (process-wide); then the
+ * viscous kernel's z chunk (16, 32, 64, 128 planes, nopcs_set_visc_chunk).  Candidates whose
  * closure array would not fit ws_bytes are skipped.  Q is not modified; the
  * call allocates and frees a 5-field scratch state and synchronises hip_stream.
  * piece_out[3]: the lengths in force on return.  Results of later calls change
  * by round-off only.
  */
+/*
+ * nopcs_set_visc_chunk -- planes per z chunk of the viscous kernel (one block
+ * marches a 28 x 12-column tile over that many planes, re-reading two planes
+ * at each chunk end): 0 restores the default (64 planes, halved down to 16
+ * while the box would have fewer than 1024 blocks), else 8..1024 (larger than
+ * nz means one chunk).  Results do not
+ * depend on it (every plane is computed by one chunk with the same
+ * arithmetic).  Process-wide; NOPCS_EINVAL outside the range.
+ * nopcs_visc_chunk -- the chunk in force for this grid, or NOPCS_EINVAL.
+ */
+int nopcs_set_visc_chunk(int32_t planes);
+int32_t nopcs_visc_chunk(const nopcs_grid *grid);
+
 int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precision, const double *Q, void *ws,
                    size_t ws_bytes, void *hip_stream, int32_t piece_out[3]);
 

@@ -444,6 +444,7 @@ static int step_graph(const nse_params &params, const nopcs_grid *grid, int prec
     put_bytes(key, precision);
     put_bytes(key, dt);
     for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, grid->n[d]));
+    put_bytes(key, visc_z_chunk(grid->n));
     std::lock_guard<std::mutex> lk(g_gmu);
     auto it = g_graph_cache.find(key);
     if (it != g_graph_cache.end()) return replay(it->second, nsteps, st);
@@ -894,6 +895,7 @@ static int batch_step(const nse_params &params, int nbox, const nopcs_box *boxes
         put_bytes(key, boxes[b].ws);
         put_bytes(key, boxes[b].dt);
         for (int d = 0; d < 3; ++d) put_bytes(key, piece_length(d, boxes[b].grid.n[d]));
+        put_bytes(key, visc_z_chunk(boxes[b].grid.n));
     }
     std::lock_guard<std::mutex> lk(g_gmu);
     auto it = g_graph_cache.find(key);
@@ -1128,14 +1130,50 @@ int nopcs_autotune(const nse_params *params, const nopcs_grid *grid, int precisi
         g_piece_len[d].store(best_len);
         best[d] = best_len;
     }
-    if (rc != NOPCS_OK)
+    // then the z chunk of the viscous kernel (planes per block), with the pieces chosen
+    const int chunk0 = visc_z_chunk_setting();
+    int best_chunk = chunk0;
+    if (rc == NOPCS_OK) {
+        float best_ms = 0.0f;
+        bool any = false;
+        for (int zc : {16, 32, 64, 128}) {
+            if (zc > grid->n[2] && zc != 16) continue;
+            set_visc_z_chunk(zc);
+            float ms = 0.0f;
+            rc = time_it(&ms);
+            if (rc != NOPCS_OK) break;
+            if (!any || ms < best_ms) {
+                best_ms = ms;
+                best_chunk = zc;
+                any = true;
+            }
+        }
+        set_visc_z_chunk(best_chunk);
+    }
+    if (rc != NOPCS_OK) {
         for (int d = 0; d < 3; ++d) g_piece_len[d].store(best[d]);
+        set_visc_z_chunk(chunk0);
+    }
     for (int d = 0; d < 3; ++d) piece_out[d] = piece_length(d, grid->n[d]);
     (void)hipStreamSynchronize(st);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(scratch);
     return rc;
+}
+
+int nopcs_set_visc_chunk(int32_t planes) {
+    if (planes != 0 && (planes < 8 || planes > 1024)) {
+        set_error("viscous z chunk must be 0 (default) or 8..1024 planes");
+        return NOPCS_EINVAL;
+    }
+    set_visc_z_chunk(planes);
+    return NOPCS_OK;
+}
+
+int32_t nopcs_visc_chunk(const nopcs_grid *grid) {
+    if (!check_grid(grid)) return NOPCS_EINVAL;
+    return visc_z_chunk(grid->n);
 }
 
 int nopcs_set_graphs(int32_t on) {

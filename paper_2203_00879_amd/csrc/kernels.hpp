@@ -89,6 +89,12 @@ hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c
                              const LinePlanDev &pl, const NdConst &c, hipStream_t st, const RkFuse *rk = nullptr,
                              BatchCollector *col = nullptr, int phase = 0);
 
+// Planes per z chunk of the viscous kernel on an n[0] x n[1] x n[2] box
+// (set_visc_z_chunk(0) restores the default).
+int visc_z_chunk(const int n[3]);
+void set_visc_z_chunk(int planes);
+int visc_z_chunk_setting();   // 0: the default rule
+
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
                        hipStream_t st, BatchCollector *col = nullptr, int phase = 0);

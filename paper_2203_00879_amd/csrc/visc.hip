@@ -21,6 +21,9 @@
 // neighbour, which writes identical values) so that the one-sided wall
 // stencils stay inside the halo.  The summation order is that of the oracle:
 // (dEv/dx + dFv/dy) + dGv/dz, then the source.
+#include <algorithm>
+#include <atomic>
+
 #include "kernels.hpp"
 
 namespace nopcs {
@@ -341,6 +344,23 @@ struct ViscBody {
 };
 }  // namespace
 
+// Planes per z chunk of the viscous kernel: the setting (> 0), else 64,
+// halved (down to 16) while the grid would have fewer than 1024 blocks (four
+// per CU: at 192^3 a 64-plane chunk leaves 336).  Each output plane is
+// computed by one chunk with the same arithmetic, so results do not depend on
+// it.
+static std::atomic<int> g_visc_chunk{0};
+int visc_z_chunk(const int n[3]) {
+    const int v = g_visc_chunk.load();
+    if (v > 0) return std::min(v, n[2]);
+    const long long tiles = (long long)((n[0] + CTX - 1) / CTX) * ((n[1] + CTY - 1) / CTY);
+    int zc = 64;
+    while (zc > 16 && tiles * ((n[2] + zc - 1) / zc) < 1024) zc /= 2;
+    return std::min(zc, n[2]);
+}
+void set_visc_z_chunk(int planes) { g_visc_chunk.store(planes); }
+int visc_z_chunk_setting() { return g_visc_chunk.load(); }
+
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
                        hipStream_t st, BatchCollector *col, int phase) {
     VArgs A;
@@ -351,7 +371,7 @@ hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const
     A.nz = n[2];
     A.ntx = (n[0] + CTX - 1) / CTX;
     A.nty = (n[1] + CTY - 1) / CTY;
-    A.zc = n[2] <= 64 ? 16 : 64;
+    A.zc = visc_z_chunk(n);
     A.N3 = (long long)n[0] * n[1] * n[2];
     A.ihx = ih[0];
     A.ihy = ih[1];

@@ -98,6 +98,9 @@ def lib():
         L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
                                      ctypes.POINTER(ctypes.c_int32 * 3)]
         L.nopcs_set_piece_length.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.nopcs_set_visc_chunk.argtypes = [ctypes.c_int32]
+        L.nopcs_visc_chunk.argtypes = [ctypes.POINTER(Grid)]
+        L.nopcs_visc_chunk.restype = ctypes.c_int32
         L.nopcs_disturbance_pressure.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _V, _V, _V, _V]
         L.nopcs_line_spectrum.argtypes = [_V, ctypes.c_int32, ctypes.c_int64, _V, _V]
         L.nopcs_compact_viscous_workspace_bytes.restype = ctypes.c_size_t
@@ -301,8 +304,9 @@ def rk_step(params, grid, Q, dt, nsteps, ws, precision=FP64, stream=None):
 
 
 def autotune(params, grid, Q, ws, precision=FP64, stream=None):
-    """Time rk_step for the candidate piece lengths on a copy of Q; returns the
-    chosen (x, y, z) lengths, which stay in force (process-wide)."""
+    """Time rk_step for the candidate piece lengths, then the viscous z chunk,
+    on a copy of Q; returns the chosen (x, y, z) lengths; lengths and chunk
+    stay in force (process-wide; the chunk: visc_chunk(grid))."""
     out = (ctypes.c_int32 * 3)()
     _check(lib().nopcs_autotune(ctypes.byref(params), ctypes.byref(grid), int(precision), _ptr(Q), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(out)))
@@ -311,6 +315,19 @@ def autotune(params, grid, Q, ws, precision=FP64, stream=None):
 
 def set_piece_length(direction, length):
     _check(lib().nopcs_set_piece_length(int(direction), int(length)))
+
+
+def set_visc_chunk(planes):
+    """Planes per z chunk of the viscous kernel (0: the default)."""
+    _check(lib().nopcs_set_visc_chunk(int(planes)))
+
+
+def visc_chunk(grid):
+    """The viscous z chunk in force for this grid."""
+    v = lib().nopcs_visc_chunk(ctypes.byref(grid))
+    if v < 0:
+        raise NopcsError(v, last_error())
+    return v
 
 
 def alloc_workspace(grid, precision=FP64, device="cuda"):

@@ -478,6 +478,9 @@ int main(int argc, char **argv) {
         return batch_checks(pe && std::atoi(pe) == 1 ? NOPCS_MIXED : NOPCS_FP64, argc > 2 ? argv[2] : "2013");
     }
     if (argc < 11) { std::fprintf(stderr, "usage\n"); return 2; }
+    // NOPCS_EMUL_VISC_CHUNK: planes per z chunk of the viscous kernel (0 default)
+    if (const char *vc = std::getenv("NOPCS_EMUL_VISC_CHUNK"))
+        if (nopcs_set_visc_chunk(std::atoi(vc)) != NOPCS_OK) return 2;
     // NOPCS_EMUL_PIECE: extra-cut length for all directions (-1 default, 0 none)
     if (const char *pc = std::getenv("NOPCS_EMUL_PIECE"))
         for (int d = 0; d < 3; ++d)

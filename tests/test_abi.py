@@ -169,3 +169,22 @@ def test_batch_argument_checks():
     arr[1].ws_bytes = ws - 8                         # short workspace
     assert call(ctypes.byref(p), 2, arr, 0, 1e-5, 1, None) == -1
     assert b"workspace" in lib.nopcs_last_error()
+
+
+def test_visc_chunk_setting():
+    """The viscous kernel's z chunk: 0 (default: 64 planes, halved down to 16
+    while the box has fewer than 1024 blocks) or 8..1024 planes, capped at nz;
+    other values rejected (host only)."""
+    lib = nopcs.lib()
+    try:
+        assert nopcs.visc_chunk(nopcs.make_grid(48)) == 16
+        assert nopcs.visc_chunk(nopcs.make_grid(192, 3)) == 16    # 112 tiles: 64 planes would give 336 blocks
+        assert nopcs.visc_chunk(nopcs.make_grid(256, 4)) == 32    # 220 tiles
+        assert nopcs.visc_chunk(nopcs.make_grid(512, 4)) == 64
+        for bad in (-1, 1, 7, 1025):
+            assert lib.nopcs_set_visc_chunk(bad) == nopcs.NOPCS_EINVAL
+        nopcs.set_visc_chunk(32)
+        assert nopcs.visc_chunk(nopcs.make_grid(512, 4)) == 32
+        assert nopcs.visc_chunk(nopcs.make_grid((16, 16, 20))) == 20
+    finally:
+        nopcs.set_visc_chunk(0)

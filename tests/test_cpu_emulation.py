@@ -155,19 +155,24 @@ def test_emulated_rk_line_march(driver, tmp_path, mixed):
         assert np.max(np.abs(G[c] - O[c])) <= tol * d, (c, np.max(np.abs(G[c] - O[c])) / d)
 
 
-@pytest.mark.parametrize("shape, v, g", [((60, 30, 20), 1, 1), ((30, 14, 131), 1, 0)])
-def test_emulated_rhs_tiles(driver, tmp_path, shape, v, g):
+@pytest.mark.parametrize("shape, v, g, chunk", [((60, 30, 20), 1, 1, 0), ((30, 14, 131), 1, 0, 0),
+                                                ((30, 20, 41), 1, 1, 8)])
+def test_emulated_rhs_tiles(driver, tmp_path, shape, v, g, chunk):
     """No extra cuts and one segment per direction: interior tiles (no wall
     inside the halo), wall tiles, shifted edge tiles and several z chunks of
-    the viscous kernel all reproduce the oracle to rounding (the viscous terms
-    and fluxes in the oracle's operation order, the Thomas elimination with
-    reciprocal pivots)."""
+    the viscous kernel (the last case: 8-plane chunks, the top one partial)
+    all reproduce the oracle to rounding (the viscous terms and fluxes in the
+    oracle's operation order, the Thomas elimination with reciprocal pivots)."""
     p = dict(inputs.AIR, viscous=v, gravity=g)
     Q = inputs.smooth_state(shape, seed=11)
     qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
     Q.tofile(qin)
     L = (1.0, 0.6, 1.4)
-    _run(driver, ["rhs", *shape, 1, 1, 1, *L, v, g, qin, rout], tmp_path, piece=0)
+    os.environ["NOPCS_EMUL_VISC_CHUNK"] = str(chunk)
+    try:
+        _run(driver, ["rhs", *shape, 1, 1, 1, *L, v, g, qin, rout], tmp_path, piece=0)
+    finally:
+        del os.environ["NOPCS_EMUL_VISC_CHUNK"]
     R = np.fromfile(rout).reshape(Q.shape)
     Ro = oracle.rhs(p, Q, L)
     for c in range(5):
