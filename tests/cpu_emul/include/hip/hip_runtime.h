@@ -204,14 +204,34 @@ extern "C" void __sanitizer_finish_switch_fiber(void *fake_stack_save, const voi
 extern "C" void __asan_unpoison_memory_region(void const volatile *addr, size_t size);
 #endif
 
+#if defined(__SANITIZE_THREAD__) && !defined(EMU_TSAN)
+#define EMU_TSAN 1
+#endif
+#if defined(__has_feature)
+#if __has_feature(thread_sanitizer) && !defined(EMU_TSAN)
+#define EMU_TSAN 1
+#endif
+#endif
+#if defined(EMU_TSAN)
+extern "C" void *__tsan_get_current_fiber(void);
+extern "C" void *__tsan_create_fiber(unsigned flags);
+extern "C" void __tsan_destroy_fiber(void *fiber);
+extern "C" void __tsan_switch_to_fiber(void *fiber, unsigned flags);
+#endif
+
 struct EmuFiber {
+    void *tsan = nullptr;     // ThreadSanitizer's fiber of this device thread
     void *sp = nullptr;
     char *stack = nullptr;
     bool done = false;
     unsigned long nbar = 0;   // barriers reached
 };
 struct EmuSched {
+#if defined(EMU_TSAN)
+    static constexpr size_t kStack = (size_t)4 << 20;     // instrumented frames are larger
+#else
     static constexpr size_t kStack = (size_t)512 << 10;
+#endif
     std::mutex launch_mu;
     std::vector<EmuFiber> fib;
     void *sched_sp = nullptr;
@@ -220,6 +240,7 @@ struct EmuSched {
     std::function<void()> body;
     const void *sched_bottom = nullptr;   // the scheduler's own stack (for the sanitizer)
     size_t sched_size = 0;
+    void *sched_tsan = nullptr;           // ThreadSanitizer's fiber of the launching thread
     // switch from the running fiber to the scheduler; dying: the fiber never returns
     void to_sched(bool dying) {
 #if defined(__SANITIZE_ADDRESS__)
@@ -227,6 +248,10 @@ struct EmuSched {
         __sanitizer_start_switch_fiber(dying ? nullptr : &fake, sched_bottom, sched_size);
         emu_ctx_switch(&fib[cur].sp, sched_sp);
         __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#elif defined(EMU_TSAN)
+        (void)dying;
+        __tsan_switch_to_fiber(sched_tsan, 0);
+        emu_ctx_switch(&fib[cur].sp, sched_sp);
 #else
         (void)dying;
         emu_ctx_switch(&fib[cur].sp, sched_sp);
@@ -241,6 +266,10 @@ struct EmuSched {
         __sanitizer_start_switch_fiber(&fake, fib[t].stack, kStack);
         emu_ctx_switch(&sched_sp, fib[t].sp);
         __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#elif defined(EMU_TSAN)
+        sched_tsan = __tsan_get_current_fiber();
+        __tsan_switch_to_fiber(fib[t].tsan, 0);
+        emu_ctx_switch(&sched_sp, fib[t].sp);
 #else
         emu_ctx_switch(&sched_sp, fib[t].sp);
 #endif
@@ -254,6 +283,12 @@ struct EmuSched {
             if (f.stack == (char *)MAP_FAILED) std::abort();
             mprotect(f.stack, (size_t)sysconf(_SC_PAGESIZE), PROT_NONE);   // overflow guard
         }
+#if defined(EMU_TSAN)
+        // entry() never returns, so a fiber's shadow call stack would keep its
+        // frames from one block to the next: a fresh sanitizer fiber per block
+        if (f.tsan) __tsan_destroy_fiber(f.tsan);
+        f.tsan = __tsan_create_fiber(0);
+#endif
 #if defined(__SANITIZE_ADDRESS__)
         __asan_unpoison_memory_region(f.stack, kStack);
 #endif
@@ -319,6 +354,13 @@ void emu_launch(K kernel, dim3 grid, dim3 block, A... args) {
 }
 template <class K, class... A>
 void emu_launch_now(K kernel, dim3 grid, dim3 block, A... args) {
+    // NOPCS_EMUL_HOST_ONLY=1: launches do nothing (host-side checks of the
+    // runtime's own logic, e.g. under ThreadSanitizer; results are not computed)
+    static const bool host_only = [] {
+        const char *e = std::getenv("NOPCS_EMUL_HOST_ONLY");
+        return e && e[0] == '1';
+    }();
+    if (host_only) return;
     EmuSched &s = emu_sched();
     std::lock_guard<std::mutex> serial(s.launch_mu);
     const unsigned nt = block.x * block.y * block.z;
