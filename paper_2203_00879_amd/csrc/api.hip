@@ -349,6 +349,15 @@ template <class T>
 void put_bytes(std::string &k, const T &v) {
     k.append(reinterpret_cast<const char *>(&v), sizeof v);
 }
+// the grid field by field: its padding bytes (after n and nseg) are whatever
+// the caller's memory held and must not make equal grids differ
+void put_grid(std::string &k, const nopcs_grid &g) {
+    for (int d = 0; d < 3; ++d) {
+        put_bytes(k, g.n[d]);
+        put_bytes(k, g.len[d]);
+        put_bytes(k, g.nseg[d]);
+    }
+}
 
 // Destroy an entry once its replays have run (the executable may still be
 // queued on a caller's stream).
@@ -416,6 +425,11 @@ int instantiate(GraphEntry &e) {
 }
 }  // namespace
 
+size_t nopcs::graph_cache_entries() {
+    std::lock_guard<std::mutex> lk(g_gmu);
+    return g_graph_cache.size();
+}
+
 static void release_graphs() {
     std::lock_guard<std::mutex> lk(g_gmu);
     for (auto &kv : g_graph_cache) drop_graph(kv.second);
@@ -439,7 +453,7 @@ static int step_graph(const nse_params &params, const nopcs_grid *grid, int prec
     put_bytes(key, dev);
     put_bytes(key, Q);
     put_bytes(key, ws);
-    put_bytes(key, *grid);
+    put_grid(key, *grid);
     put_bytes(key, params);
     put_bytes(key, precision);
     put_bytes(key, dt);
@@ -890,7 +904,7 @@ static int batch_step(const nse_params &params, int nbox, const nopcs_box *boxes
     put_bytes(key, precision);
     put_bytes(key, dt);
     for (int b = 0; b < nbox; ++b) {
-        put_bytes(key, boxes[b].grid);
+        put_grid(key, boxes[b].grid);
         put_bytes(key, boxes[b].Q);
         put_bytes(key, boxes[b].ws);
         put_bytes(key, boxes[b].dt);

@@ -23,6 +23,10 @@
 #include <vector>
 
 #include "../../include/nopcs.h"
+
+namespace nopcs {
+size_t graph_cache_entries();   // cached RK4 steps (library-internal)
+}
 #include "../../paper_2203_00879_amd/csrc/plan.hpp"
 #include "hip/hip_runtime.h"
 
@@ -335,6 +339,34 @@ static int batch_checks(int prec, const std::string &mode_list) {
                         rep % 2, nb);
     }
     if (rc > 1) std::fprintf(stderr, "rk_step_batch failed: %d %s\n", rc, nopcs_last_error());
+    // equal grids whose padding bytes differ (memory a C caller never wrote)
+    // reuse the cached step: a batch and a lone graph step, each called twice
+    if (rc == NOPCS_OK) {
+        std::vector<nopcs_box> junk = boxes;
+        for (int b = 0; b < nb; ++b) {
+            std::memset(static_cast<void *>(&junk[b].grid), 0xA5 + b, sizeof(nopcs_grid));
+            for (int d = 0; d < 3; ++d) {
+                junk[b].grid.n[d] = g[b].n[d];
+                junk[b].grid.len[d] = g[b].len[d];
+                junk[b].grid.nseg[d] = g[b].nseg[d];
+            }
+        }
+        const size_t before = nopcs::graph_cache_entries();
+        rc = rk_step_batch(&p, nb, junk.data(), prec, dt_call, nsteps, nullptr);
+        const size_t after_batch = nopcs::graph_cache_entries();
+        if (rc == NOPCS_OK) rc = nopcs_set_graphs(1);
+        if (rc == NOPCS_OK) rc = rk_step(&p, &g[1], prec, Q[1]->p, dt_call, 1, W[1]->p, wsb[1], nullptr);
+        const size_t after_lone = nopcs::graph_cache_entries();
+        if (rc == NOPCS_OK) rc = rk_step(&p, &junk[1].grid, prec, Q[1]->p, dt_call, 1, W[1]->p, wsb[1], nullptr);
+        const size_t after_junk = nopcs::graph_cache_entries();
+        (void)nopcs_set_graphs(0);
+        if (rc == NOPCS_OK && (after_batch != before || after_lone != before + 1 || after_junk != after_lone)) {
+            std::fprintf(stderr, "graph cache keyed by padding: %zu %zu %zu %zu entries\n", before, after_batch,
+                         after_lone, after_junk);
+            rc = 1;
+        }
+        if (rc == NOPCS_OK) std::printf("ok grids differing in padding only reuse the cached steps\n");
+    }
     // more distinct batches than the cache holds (limit lowered to 3): every
     // call a new step (the first box's workspace moved by 256 bytes each time,
     // which changes no result), so cached steps are evicted while new ones are

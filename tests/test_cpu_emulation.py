@@ -217,8 +217,9 @@ def test_emulated_batch_step(driver, tmp_path, mixed):
     FP64 (shared launches as a graph or issued directly, a graph branch per
     box, the hybrid) and in the direct and the default mode in mixed precision:
     each box bit-identical to rk_step on it alone, on the first call and on the
-    cached second; 8 distinct two-box batches through a step cache limited to
-    3 entries, each against the lone steps; duplicate states, misaligned
+    cached second; grids that differ only in their padding bytes reuse the
+    cached batch and lone graph steps; 8 distinct two-box batches through a
+    step cache limited to 3 entries, each against the lone steps; duplicate states, misaligned
     workspaces, negative dt and an empty batch rejected."""
     env = dict(os.environ)
     if mixed:
@@ -229,6 +230,7 @@ def test_emulated_batch_step(driver, tmp_path, mixed):
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     for mode in modes:
         assert "ok batch mode %d call 1: 5 boxes bit-identical to their lone steps" % mode in r.stdout
+    assert "ok grids differing in padding only reuse the cached steps" in r.stdout
     assert "ok 8 distinct batches through the cache" in r.stdout
     assert "ok batch argument errors" in r.stdout
 
