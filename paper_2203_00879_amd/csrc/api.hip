@@ -13,6 +13,10 @@
 
 namespace nopcs {
 
+// cached RK4 steps (graphs or direct batched launches) across devices; not
+// part of the C ABI (the CPU build's checks of the step cache read it)
+size_t graph_cache_entries();
+
 namespace {
 thread_local std::string g_err;
 }

@@ -94,8 +94,6 @@ hipError_t launch_march_runs(int dir, const double *Q, void *R, bool r32, bool c
 int visc_z_chunk(const int n[3]);
 void set_visc_z_chunk(int planes);
 int visc_z_chunk_setting();   // 0: the default rule
-// cached RK4 steps (graphs or direct batched launches) across devices
-size_t graph_cache_entries();
 
 // Viscous fluxes (explicit second order) + gravity source: R = div(Fv) + S.
 hipError_t launch_visc(const double *Q, void *R, bool r32, const int n[3], const double ih[3], const NdConst &c,
