@@ -138,9 +138,25 @@ int nopcs_line_plan(int32_t n, int32_t nseg, int32_t piece_len, int32_t cap, int
  * dir: 0 = x, 1 = y, 2 = z.  precision: NOPCS_FP64 (NOPCS_MIXED is rejected here).
  * f: device, n0*n1*n2 doubles (read only).  d1, d2: device outputs of the same
  * size, either may be NULL but not both; they must not overlap f.
+ * The first derivative alone (d2 NULL) along y or z on a box with at least
+ * 2^17 lines along dir runs as a closure pass and a line march (one thread per
+ * line), with the closure values in scratch taken with hipMallocAsync on
+ * hip_stream and freed there (8 bytes per closure row and line); every other
+ * case runs as a staged pencil solve in LDS (see nopcs_set_deriv_form).
  */
 int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const double *f, double *d1, double *d2,
                      void *hip_stream);
+
+/*
+ * nopcs_set_deriv_form -- how nopcs_derivative computes the first derivative
+ * alone along y or z: 0 (the default) the line march on boxes with at least
+ * 2^17 lines along dir and the pencil solve on smaller ones; 1 always the
+ * pencil solve; 2 always the line march (where the plan allows: runs of at
+ * most 32 unknowns and at most 8 closure slots per row, else the pencil).  The
+ * forms differ by rounding order only.  Process-wide; NOPCS_EINVAL for other
+ * values.
+ */
+int nopcs_set_deriv_form(int32_t form);
 
 /*
  * nopcs_vorticity_workspace_bytes -- bytes of device workspace that

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnopcs.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "sweep.hip", "march.hip", "visc.hip", "cvisc.hip", "diag.hip", "plan.cpp"]
+SOURCES = ["api.hip", "sweep.hip", "march.hip", "dmarch.hip", "visc.hip", "cvisc.hip", "diag.hip", "plan.cpp"]
 OPTIONAL_SOURCES = ["mixed.hip", "batch.hip", "solver.cpp"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]

@@ -94,6 +94,7 @@ def lib():
         L.rk_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, ctypes.c_double, ctypes.c_int32,
                               _V, ctypes.c_size_t, _V]
         L.nopcs_set_graphs.argtypes = [ctypes.c_int32]
+        L.nopcs_set_deriv_form.argtypes = [ctypes.c_int32]
         L.nopcs_set_graph_cache_limit.argtypes = [ctypes.c_int32]
         L.nopcs_autotune.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Grid), _I, _V, _V, ctypes.c_size_t, _V,
                                      ctypes.POINTER(ctypes.c_int32 * 3)]
@@ -176,6 +177,15 @@ def nopcs_derivative(grid, direction, f, d1=None, d2=None, precision=FP64, strea
     """D1 and/or D2 of a device field f (float64 tensor of n0*n1*n2 elements)."""
     _check(lib().nopcs_derivative(ctypes.byref(grid), int(direction), int(precision), _ptr(f), _ptr(d1), _ptr(d2),
                                   _stream(stream)))
+
+
+DERIV_BY_SIZE, DERIV_PENCIL, DERIV_MARCH = 0, 1, 2
+
+
+def set_deriv_form(form):
+    """How the first derivative alone along y or z is computed: DERIV_BY_SIZE
+    (default: the line march from 2^17 lines), DERIV_PENCIL or DERIV_MARCH."""
+    _check(lib().nopcs_set_deriv_form(int(form)))
 
 
 def vorticity_workspace_bytes(grid):

@@ -543,6 +543,25 @@ int main(int argc, char **argv) {
             std::memcpy(out.data() + N, d2.p, N * sizeof(double));
             write_raw(argv[13], out.data(), 2 * N);
         }
+    } else if (mode == "deriv1") {
+        // the first derivative alone (line march along y and z), then the same
+        // through the pencil solve: both written, march first
+        const int dir = std::atoi(argv[11]);
+        std::vector<double> fh = read_raw(argv[12], N);
+        Buf f(N), a(N), b(N);
+        std::memcpy(f.p, fh.data(), N * sizeof(double));
+        rc = nopcs_set_deriv_form(2);
+        if (rc == 0) rc = nopcs_derivative(&g, dir, NOPCS_FP64, f.p, a.p, nullptr, nullptr);
+        if (rc == 0) rc = nopcs_set_deriv_form(1);
+        if (rc == 0) rc = nopcs_derivative(&g, dir, NOPCS_FP64, f.p, b.p, nullptr, nullptr);
+        if (nopcs_set_deriv_form(3) != NOPCS_EINVAL) rc = 1;
+        (void)nopcs_set_deriv_form(0);
+        if (rc == 0) {
+            std::vector<double> out(2 * N);
+            std::memcpy(out.data(), a.p, N * sizeof(double));
+            std::memcpy(out.data() + N, b.p, N * sizeof(double));
+            write_raw(argv[13], out.data(), 2 * N);
+        }
     } else if (mode == "rhs") {
         p.viscous = std::atoi(argv[11]);
         p.gravity = std::atoi(argv[12]);

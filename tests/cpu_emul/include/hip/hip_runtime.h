@@ -122,6 +122,9 @@ inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
 inline hipError_t hipMalloc(void **p, size_t n) { *p = emu_guarded_alloc(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
 inline hipError_t hipFree(void *p) { emu_guarded_free(p); return hipSuccess; }
+// stream-ordered allocation: work on a stream runs at once here (outside a capture)
+inline hipError_t hipMallocAsync(void **p, size_t n, hipStream_t) { return hipMalloc(p, n); }
+inline hipError_t hipFreeAsync(void *p, hipStream_t) { return hipFree(p); }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { std::memcpy(d, s, n); return hipSuccess; }
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t);
 inline hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t);

@@ -188,3 +188,16 @@ def test_visc_chunk_setting():
         assert nopcs.visc_chunk(nopcs.make_grid((16, 16, 20))) == 20
     finally:
         nopcs.set_visc_chunk(0)
+
+
+def test_deriv_form_setting():
+    """The form of the first derivative alone along y and z: 0 (by size), 1
+    (pencil) or 2 (line march); other values rejected (host only)."""
+    lib = nopcs.lib()
+    try:
+        for bad in (-1, 3):
+            assert lib.nopcs_set_deriv_form(bad) == nopcs.NOPCS_EINVAL
+        for form in (nopcs.DERIV_PENCIL, nopcs.DERIV_MARCH, nopcs.DERIV_BY_SIZE):
+            nopcs.set_deriv_form(form)
+    finally:
+        nopcs.set_deriv_form(nopcs.DERIV_BY_SIZE)

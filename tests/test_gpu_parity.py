@@ -89,11 +89,68 @@ def test_derivative_only_one_output():
     assert rel_err(d2, oracle.d2(f, 2)) <= TOL
 
 
+def gpu_d1_forms(f, direction, nseg, length=1.0, forms=(nopcs.DERIV_MARCH, nopcs.DERIV_PENCIL)):
+    """The first derivative alone in each of the given forms."""
+    out = []
+    try:
+        for form in forms:
+            nopcs.set_deriv_form(form)
+            out.append(gpu_deriv(f, direction, nseg, length, want=(1,))[0])
+    finally:
+        nopcs.set_deriv_form(nopcs.DERIV_BY_SIZE)
+    return out
+
+
+@pytest.mark.parametrize("shape,nseg", DERIV_CASES)
+def test_first_derivative_line_march_parity(shape, nseg):
+    """The first derivative alone: along y and z a closure pass and a line march
+    (the pencil solve along x and where a row needs more than 8 closure slots),
+    within 1e-12 of the oracle and within 1e-13 of the pencil solve."""
+    nx, ny, nz = shape
+    say("first derivative line march", shape, nseg)
+    f = np.random.default_rng(nx * 5 + nz).normal(size=(nz, ny, nx))
+    length = (1.0, 0.7, 1.3)
+    for d in range(3):
+        d1m, d1p = gpu_d1_forms(f, d, nseg, length)
+        e, ep = rel_err(d1m, oracle.d1(f, d, length)), rel_err(d1m, d1p)
+        say("  dir", d, "oracle %.3e pencil %.3e" % (e, ep))
+        assert e <= TOL and ep <= 1e-13
+
+
+def test_first_derivative_line_march_512():
+    """512^3, 4 segments per direction (the derivative benchmark's box): the
+    form chosen by size is the line march (bit for bit), which agrees with the
+    pencil solve everywhere (1e-13) and with the oracle on sampled lines (every
+    line along y of 3 x 2 (x, z) columns, along z of 3 x 2 (x, y) columns,
+    including the first and last)."""
+    n = 512
+    say("first derivative line march 512^3")
+    f = np.random.default_rng(512).normal(size=(n, n, n))
+    for d in (1, 2):
+        d1s, d1m, d1p = gpu_d1_forms(f, d, 4, forms=(nopcs.DERIV_BY_SIZE, nopcs.DERIV_MARCH, nopcs.DERIV_PENCIL))
+        assert np.array_equal(d1s, d1m)
+        del d1s
+        ep = rel_err(d1m, d1p)
+        cols_a, cols_b = [0, 200, n - 1], [0, n - 1]
+        if d == 1:   # lines along y at (x, z)
+            sub = f[cols_b][:, :, cols_a]
+            got = d1m[cols_b][:, :, cols_a]
+        else:        # lines along z at (x, y)
+            sub = f[:, cols_b][:, :, cols_a]
+            got = d1m[:, cols_b][:, :, cols_a]
+        e = rel_err(got, oracle.d1(np.ascontiguousarray(sub), d))
+        say("  dir", d, "oracle (sampled lines) %.3e pencil %.3e" % (e, ep))
+        assert e <= TOL and ep <= 1e-13
+        del d1m, d1p
+
+
 def test_derivative_constant_field_is_exactly_zero():
     f = np.full((24, 20, 36), 3.25)
     for d in range(3):
         d1, d2 = gpu_deriv(f, d, (3, 2, 4))
         assert np.all(d1 == 0.0) and np.all(d2 == 0.0)
+        d1, _ = gpu_deriv(f, d, (3, 2, 4), want=(1,))   # line march along y and z
+        assert np.all(d1 == 0.0)
 
 
 def _keq(w, h):
