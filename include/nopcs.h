@@ -148,13 +148,16 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
                      void *hip_stream);
 
 /*
- * nopcs_set_deriv_form -- how nopcs_derivative computes the first derivative
- * alone along y or z: 0 (the default) the line march on boxes with at least
- * 2^17 lines along dir and the pencil solve on smaller ones; 1 always the
- * pencil solve; 2 always the line march (where the plan allows: runs of at
- * most 32 unknowns and at most 8 closure slots per row, else the pencil).  The
- * forms differ by rounding order only.  Process-wide; NOPCS_EINVAL for other
- * values.
+ * nopcs_set_deriv_form -- how nopcs_derivative, nopcs_vorticity_budget and the
+ * compact viscous variant (nse_rhs_compact_viscous, rk_step_compact_viscous)
+ * compute first derivatives alone along y or z: 0 (the default) the line march
+ * on boxes with at least 2^17 lines along the direction and the pencil solve on
+ * smaller ones; 1 always the pencil solve; 2 always the line march (where the
+ * plan allows: runs of at most 32 unknowns and at most 8 closure slots per
+ * row, else the pencil).  The forms differ by rounding order only.  A call
+ * that marches takes its closure values (8 bytes per closure row and line of
+ * the larger marching direction) with hipMallocAsync on its stream and frees
+ * them there.  Process-wide; NOPCS_EINVAL for other values.
  */
 int nopcs_set_deriv_form(int32_t form);
 

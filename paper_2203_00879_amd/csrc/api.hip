@@ -170,6 +170,42 @@ static hipError_t timed_impl(int id, hipStream_t st, F &&f) {
     return hipSuccess;
 }
 
+// How a call computes first derivatives alone: along y and z the closure pass
+// and line march where the form setting and the box size choose it and the
+// plan allows (never inside a graph capture or the allocation-free entry
+// point: the march takes stream-ordered scratch), the LDS pencil solve
+// otherwise.  The scratch holds the closure values of the largest marching
+// direction and is released on the stream when the object goes.
+struct D1Forms {
+    bool march[3] = {false, false, false};
+    double *clo = nullptr;
+    hipStream_t st = nullptr;
+    D1Forms(const nopcs_grid *grid, const LinePlanDev pl[3], hipStream_t s) : st(s) {
+        const int form = g_deriv_form.load();
+        if (t_capturing || t_no_alloc) return;
+        for (int d = 1; d < 3; ++d) {
+            const long long lines = (long long)field_elems(grid) / grid->n[d];
+            march[d] = (form == 2 || (form == 0 && lines >= kDerivMarchLines)) && dmarch_usable(d, pl[d]);
+        }
+    }
+    D1Forms(const D1Forms &) = delete;
+    D1Forms &operator=(const D1Forms &) = delete;
+    ~D1Forms() {
+        if (clo) (void)hipFreeAsync(clo, st);
+    }
+    // scratch for the marching directions (only: one direction, -1: both)
+    hipError_t alloc(const nopcs_grid *grid, const LinePlanDev pl[3], int only = -1) {
+        size_t b = 0;
+        for (int d = 1; d < 3; ++d)
+            if (march[d] && (only < 0 || only == d)) b = std::max(b, dmarch_closure_bytes(grid->n, d, pl[d]));
+        return b ? hipMallocAsync(reinterpret_cast<void **>(&clo), b, st) : hipSuccess;
+    }
+    hipError_t launch(int d, const double *f, double *d1, const nopcs_grid *grid, const LinePlanDev pl[3]) const {
+        if (march[d]) return launch_dmarch(d, f, d1, clo, grid->n, pl[d], st);
+        return launch_deriv(d, f, d1, nullptr, sweep_geom(grid->n, d), pl[d], st);
+    }
+};
+
 }  // namespace nopcs
 
 using namespace nopcs;
@@ -239,22 +275,22 @@ static int compact_visc_into(const NdConst &c, const nopcs_grid *grid, const Lin
     }
     const long long N = (long long)field_elems(grid), S = field_stride(grid);
     double *P = X, *G = X + 4 * S, *F = X + 16 * S;
+    D1Forms fm(grid, pl, st);
+    NOPCS_HIP_CHECK(fm.alloc(grid, pl));
     NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_prims(Q, N, S, c, P, st); }));
     for (int a = 0; a < 4; ++a)
         for (int d = 0; d < 3; ++d) {
-            const SweepGeom g = sweep_geom(grid->n, d);
             double *dst = G + (3 * a + d) * S;
             const double *src = P + a * S;
-            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return fm.launch(d, src, dst, grid, pl); }));
         }
     NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_flux(P, G, N, S, c, F, st); }));
     // D_d of flux component 4d + q into the gradient slots
     for (int d = 0; d < 3; ++d)
         for (int q = 0; q < 4; ++q) {
-            const SweepGeom g = sweep_geom(grid->n, d);
             double *dst = G + (4 * d + q) * S;
             const double *src = F + (4 * d + q) * S;
-            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src, dst, nullptr, g, pl[d], st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return fm.launch(d, src, dst, grid, pl); }));
         }
     NOPCS_HIP_CHECK(timed(NOPCS_K_VISCOUS, st, [&] { return launch_cv_assemble(Q, G, N, S, c, R, st); }));
     return NOPCS_OK;
@@ -556,19 +592,14 @@ int nopcs_derivative(const nopcs_grid *grid, int dir, int precision, const doubl
     int rc = get_plans(grid, pl);
     if (rc != NOPCS_OK) return rc;
     const hipStream_t st = (hipStream_t)hip_stream;
-    const int form = g_deriv_form.load();
-    const long long lines = (long long)field_elems(grid) / grid->n[dir];
-    const bool march = form == 2 || (form == 0 && lines >= kDerivMarchLines);
-    if (d1 && !d2 && march && dmarch_usable(dir, pl[dir])) {
-        // the first derivative alone along y or z: closure pass and line march,
-        // the closure values in stream-ordered scratch
-        double *clo = nullptr;
-        const size_t cb = dmarch_closure_bytes(grid->n, dir, pl[dir]);
-        if (cb) NOPCS_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&clo), cb, st));
-        const hipError_t he = timed(NOPCS_K_DERIV, st, [&] { return launch_dmarch(dir, f, d1, clo, grid->n, pl[dir], st); });
-        if (clo) (void)hipFreeAsync(clo, st);
-        NOPCS_HIP_CHECK(he);
-        return NOPCS_OK;
+    if (d1 && !d2) {
+        // the first derivative alone: the line march along y or z where it is chosen
+        D1Forms fm(grid, pl, st);
+        if (fm.march[dir]) {
+            NOPCS_HIP_CHECK(fm.alloc(grid, pl, dir));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return fm.launch(dir, f, d1, grid, pl); }));
+            return NOPCS_OK;
+        }
     }
     const SweepGeom g = sweep_geom(grid->n, dir);
     NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(dir, f, d1, d2, g, pl[dir], st); }));
@@ -600,11 +631,12 @@ int nopcs_vorticity_budget(const nse_params *params, const nopcs_grid *grid, con
     NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_prims(Q, N, S, params->gamma - 1.0, P, st); }));
     // gradients of u, v, w (from P), rho (field 0 of Q) and p' (P field 3)
     const double *src[5] = {P, P + S, P + 2 * S, Q, P + 3 * S};
+    D1Forms fm(grid, pl, st);
+    NOPCS_HIP_CHECK(fm.alloc(grid, pl));
     for (int a = 0; a < 5; ++a)
         for (int d = 0; d < 3; ++d) {
-            const SweepGeom g = sweep_geom(grid->n, d);
             double *dst = G + (3 * a + d) * S;
-            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return launch_deriv(d, src[a], dst, nullptr, g, pl[d], st); }));
+            NOPCS_HIP_CHECK(timed(NOPCS_K_DERIV, st, [&] { return fm.launch(d, src[a], dst, grid, pl); }));
         }
     NOPCS_HIP_CHECK(timed(NOPCS_K_VORT, st, [&] { return launch_vort_combine(Q, G, N, S, out, st); }));
     return NOPCS_OK;

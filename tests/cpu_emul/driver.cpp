@@ -487,6 +487,9 @@ static int serve_stress(int batched, int nr) {
 int main(int argc, char **argv) {
     if (argc < 2) { std::fprintf(stderr, "usage\n"); return 2; }
     const std::string mode = argv[1];
+    // NOPCS_EMUL_DERIV_FORM: the form of first derivatives alone (0 by size, 1 pencil, 2 line march)
+    if (const char *e = std::getenv("NOPCS_EMUL_DERIV_FORM"))
+        if (nopcs_set_deriv_form(std::atoi(e)) != NOPCS_OK) return 2;
     if (mode == "plan" && argc >= 5) {  // driver plan n nseg piece: line-march tables of one line plan
         nopcs::LinePlanHost P;
         std::string err;

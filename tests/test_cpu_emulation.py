@@ -48,10 +48,12 @@ def driver():
     return BIN
 
 
-def _run(driver, args, tmp_path, piece=None, mixed=False):
+def _run(driver, args, tmp_path, piece=None, mixed=False, deriv_form=None):
     env = dict(os.environ)
     if piece is not None:
         env["NOPCS_EMUL_PIECE"] = str(piece)
+    if deriv_form is not None:
+        env["NOPCS_EMUL_DERIV_FORM"] = str(deriv_form)
     if mixed:
         env["NOPCS_EMUL_PRECISION"] = "1"
     r = subprocess.run([driver] + [str(a) for a in args], capture_output=True, text=True, timeout=900, env=env)
@@ -278,16 +280,19 @@ def test_emulated_rhs_mixed_precision(driver, tmp_path):
     assert max(errs) > 0.0     # the FP32 path really ran
 
 
-def test_emulated_vorticity_budget(driver, tmp_path):
+@pytest.mark.parametrize("form", [0, 2])
+def test_emulated_vorticity_budget(driver, tmp_path, form):
     """Vorticity budget of Eq. eqn12_1 on a ragged box with segmented lines and
-    unequal lengths, against the oracle's global line solves."""
+    unequal lengths, against the oracle's global line solves; first
+    derivatives along y and z by the pencil solve (form 0 on this small box)
+    and by the line march (form 2)."""
     p = dict(inputs.AIR)
     shape = (18, 13, 16)   # x, y, z
     Q = inputs.smooth_state(shape, seed=6)
     L = (1.0, 0.8, 1.1)
     qin, oout = tmp_path / "q.raw", tmp_path / "o.raw"
     Q.tofile(qin)
-    _run(driver, ["vort", *shape, 3, 1, 2, *L, qin, oout], tmp_path)
+    _run(driver, ["vort", *shape, 3, 1, 2, *L, qin, oout], tmp_path, deriv_form=form)
     G = np.fromfile(oout).reshape((12,) + Q.shape[1:])
     O = oracle.vorticity_budget(p, Q, np.array(L))
     for c in range(12):
@@ -313,31 +318,37 @@ def test_emulated_disturbance_pressure_and_line_spectrum(driver, tmp_path):
     assert _rel(amp, oracle.line_spectrum(want[shape[2] // 2, :, shape[0] // 2])) <= 1e-12
 
 
-def test_emulated_rhs_compact_viscous(driver, tmp_path):
-    """D1-based viscous variant on a ragged, segmented box with unequal lengths."""
+@pytest.mark.parametrize("form", [0, 2])
+def test_emulated_rhs_compact_viscous(driver, tmp_path, form):
+    """D1-based viscous variant on a ragged, segmented box with unequal
+    lengths; first derivatives along y and z by the pencil solve (form 0) and
+    by the line march (form 2)."""
     p = dict(inputs.AIR)
     shape = (17, 14, 19)   # x, y, z
     L = (1.0, 0.9, 1.2)
     Q = inputs.smooth_state(shape, seed=9, length=L)
     qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
     Q.tofile(qin)
-    _run(driver, ["cvisc", *shape, 2, 1, 3, *L, 1, 1, qin, rout], tmp_path)
+    _run(driver, ["cvisc", *shape, 2, 1, 3, *L, 1, 1, qin, rout], tmp_path, deriv_form=form)
     R = np.fromfile(rout).reshape(Q.shape)
     Ro = oracle.rhs_compact_viscous(p, Q, np.array(L))
     for c in range(5):
         assert _rel(R[c], Ro[c]) <= 1e-12, c
 
 
-def test_emulated_rk_step_compact_viscous(driver, tmp_path):
+@pytest.mark.parametrize("form", [0, 2])
+def test_emulated_rk_step_compact_viscous(driver, tmp_path, form):
     """One RK4 step with the D1-based viscous variant (z line march carrying
     the stage update on an 8 x 10 x 24 box with pieces), against the oracle:
-    the fields and their change over the step."""
+    the fields and their change over the step; first derivatives along y and z
+    by the pencil solve (form 0) and by the line march (form 2)."""
     p = dict(inputs.AIR)
     shape = (8, 10, 24)
     Q = inputs.rti_state(shape, seed=2, noise_K=1e-3)
     qin, qout = tmp_path / "q.raw", tmp_path / "o.raw"
     Q.tofile(qin)
-    _run(driver, ["cvisc", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, qin, qout, "2e-5:1"], tmp_path, piece=16)
+    _run(driver, ["cvisc", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, qin, qout, "2e-5:1"], tmp_path, piece=16,
+         deriv_form=form)
     G = np.fromfile(qout).reshape(Q.shape)
     O = oracle.rk4_compact_viscous(p, Q, 2e-5, 1)
     for c in range(5):

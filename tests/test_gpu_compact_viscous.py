@@ -65,6 +65,24 @@ def test_compact_viscous_rhs_parity(shape, nseg, length, gravity):
     check(R, oracle.rhs_compact_viscous(p, Q, np.broadcast_to(np.asarray(length, float), (3,)).copy()))
 
 
+@pytest.mark.parametrize("shape, nseg, length, gravity", CASES[1:3])
+def test_compact_viscous_rhs_line_march_form(shape, nseg, length, gravity):
+    """First derivatives along y and z by the line march (asked for on these
+    small boxes): against the oracle, and within 1e-12 of the pencil form."""
+    say("compact viscous parity, line march", shape, nseg, length, gravity)
+    p = dict(inputs.AIR, gravity=gravity)
+    Q = inputs.smooth_state(shape, seed=14, length=length)
+    try:
+        nopcs.set_deriv_form(nopcs.DERIV_MARCH)
+        R = gpu_rhs(p, Q, nseg, length)
+        nopcs.set_deriv_form(nopcs.DERIV_PENCIL)
+        P = gpu_rhs(p, Q, nseg, length)
+    finally:
+        nopcs.set_deriv_form(nopcs.DERIV_BY_SIZE)
+    check(R, oracle.rhs_compact_viscous(p, Q, np.broadcast_to(np.asarray(length, float), (3,)).copy()))
+    check(R, P)
+
+
 def test_compact_viscous_rhs_parity_rti():
     say("compact viscous parity RTI 32^3")
     p = dict(inputs.AIR)

@@ -67,6 +67,23 @@ def test_vorticity_budget_parity_smooth_state(shape, nseg, length):
     check(G, oracle.vorticity_budget(PARAMS, Q, np.broadcast_to(np.asarray(length, float), (3,)).copy()))
 
 
+@pytest.mark.parametrize("shape, nseg, length", CASES[1:])
+def test_vorticity_budget_line_march_form(shape, nseg, length):
+    """First derivatives along y and z by the line march (asked for on these
+    small boxes): against the oracle, and within 1e-13 of the pencil form."""
+    say("vorticity parity, line march", shape, nseg, length)
+    Q = inputs.smooth_state(shape, seed=12, length=length)
+    try:
+        nopcs.set_deriv_form(nopcs.DERIV_MARCH)
+        G = gpu_budget(Q, nseg, length)
+        nopcs.set_deriv_form(nopcs.DERIV_PENCIL)
+        P = gpu_budget(Q, nseg, length)
+    finally:
+        nopcs.set_deriv_form(nopcs.DERIV_BY_SIZE)
+    check(G, oracle.vorticity_budget(PARAMS, Q, np.broadcast_to(np.asarray(length, float), (3,)).copy()))
+    check(G, P, tol=1e-13)
+
+
 def test_vorticity_budget_parity_rti_after_steps():
     """An RTI box a few oracle RK4 steps after the partition is removed: the
     baroclinic term at the interface is the largest source (Section 5)."""
