@@ -138,10 +138,15 @@ __global__ __launch_bounds__((deriv_threads<DIR, NMAX>())) void k_filter(const d
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int DIR, int NMAX, int C0, int NC, class TR>
+// TF = float (mixed precision): the group is staged in FP32 as the offset
+// fluxes of nse_sweep_body (flux less FREF, its line's first-row value,
+// rounded once) and solved in FP32.  FREF is written before a barrier of the
+// caller that precedes the first group.
+template <int DIR, int NMAX, int C0, int NC, class TR, class TF>
 __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, int np,
                                  long long base, double (&flux)[5][SweepCfg<DIR, NMAX>::PTS],
-                                 const int (&ks)[SweepCfg<DIR, NMAX>::PTS], double *F, double *KN) {
+                                 const int (&ks)[SweepCfg<DIR, NMAX>::PTS], TF *F, double *KN,
+                                 const double (*FREF)[SweepCfg<DIR, NMAX>::P]) {
     using C = SweepCfg<DIR, NMAX>;
     const int n = g.n;
     const long long N3 = a.N3;
@@ -151,11 +156,14 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
         C::owned(threadIdx.x + s * C::NT, l, i);
         if (l < np && i < n) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) F[c * C::FSZ + C::fidx(l, i)] = flux[C0 + c][s];
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (sizeof(TF) == 8) F[c * C::FSZ + C::fidx(l, i)] = flux[C0 + c][s];
+                else F[c * C::FSZ + C::fidx(l, i)] = TF(flux[C0 + c][s] - FREF[C0 + c][l]);
+            }
         }
     }
     __syncthreads();
-    lds_line_solve<DIR, NMAX, NC>(F, KN, pl, np);
+    lds_line_solve<DIR, NMAX, NC, 0, OP_D1, C::NT, TF>(F, KN, pl, np);
     // R of the owned points; unconditional loads at clamped indices (no branch
     // makes the compiler drain the loads in flight), unused values dropped
     TR *const R = static_cast<TR *>(a.R);
@@ -176,17 +184,26 @@ __device__ inline void nse_group(const NseSweepArgs &a, const SweepGeom &g, cons
         const long long o = base + l * g.sA + i * g.sD;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            R[(C0 + c) * N3 + o] = rv[c][s] - TR(lds_result<DIR, NMAX>(F, KN, c, ks[s], l, i));
+            R[(C0 + c) * N3 + o] = rv[c][s] - TR(lds_result<DIR, NMAX, 0, C::NT, TF>(F, KN, c, ks[s], l, i));
     }
 }
 
 }  // namespace
 
+// TR = float (mixed precision): R in FP32, and the line solves in FP32 on
+// offset fluxes: each flux component less its value at the line's first row
+// (FREF, FP64), rounded once.  The derivative of a constant is exactly zero in
+// every row type (interior B f, the shifted closure sums, the wall
+// differences), so the offset changes nothing but the size of what FP32
+// carries: the line's own variation (for the pressure in the momentum flux,
+// the hydrostatic level of the line drops out).  Known rows stay FP64.
 template <int DIR, int NMAX, class TR>
 __device__ inline void nse_sweep_body(const NseSweepArgs &a, const SweepGeom &g, const LinePlanDev &pl, int b) {
     using C = SweepCfg<DIR, NMAX>;
-    __shared__ double F[C::G * C::FSZ];
+    using TF = TR;
+    __shared__ TF F[C::G * C::FSZ];
     __shared__ double KN[C::G * C::P * C::KMAX];
+    __shared__ double FREF[sizeof(TF) == 8 ? 1 : 5][C::P];
     int np;
     long long base;
     pencil_at<C>(g, b, np, base);
@@ -211,15 +228,23 @@ __device__ inline void nse_sweep_body(const NseSweepArgs &a, const SweepGeom &g,
         flux[2][s] = DIR == 1 ? my * ud + pr.pp : my * ud;
         flux[3][s] = DIR == 2 ? mz * ud + pr.pp : mz * ud;
         flux[4][s] = ((Ep + pr.pp) + c.H) * ud;
+        if constexpr (sizeof(TF) != 8) {
+            // the offsets: fluxes of the first row of every line
+            if (i == 0 && l < np) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) FREF[q][l] = flux[q][s];
+            }
+        }
     }
     int ks[C::PTS];
     owned_slots<DIR, NMAX>(pl, ks);
     static_assert(C::G == 2, "component grouping below assumes groups {0,1}, {2,3} and {4}");
-    nse_group<DIR, NMAX, 0, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    if constexpr (sizeof(TF) != 8) __syncthreads();   // FREF published
+    nse_group<DIR, NMAX, 0, 2, TR, TF>(a, g, pl, np, base, flux, ks, F, KN, FREF);
     __syncthreads();
-    nse_group<DIR, NMAX, 2, 2, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    nse_group<DIR, NMAX, 2, 2, TR, TF>(a, g, pl, np, base, flux, ks, F, KN, FREF);
     __syncthreads();
-    nse_group<DIR, NMAX, 4, 1, TR>(a, g, pl, np, base, flux, ks, F, KN);
+    nse_group<DIR, NMAX, 4, 1, TR, TF>(a, g, pl, np, base, flux, ks, F, KN, FREF);
 }
 
 // ---------------------------------------------------------------------------
@@ -295,6 +320,8 @@ struct SweepArgs {
 template <int DIR, int NMAX, class TR>
 struct SweepBody {
     using Args = SweepArgs;
+    // the FP32 x sweep fits 128 VGPRs: four blocks per CU instead of three
+    static constexpr int kMinWaves = DIR == 0 && sizeof(TR) == 4 ? 4 : 1;
     __device__ static void run(const Args &x, int b, int) { nse_sweep_body<DIR, NMAX, TR>(x.a, x.g, x.pl, b); }
 };
 struct RkUpdArgs {

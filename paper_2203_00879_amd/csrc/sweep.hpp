@@ -77,42 +77,49 @@ inline SweepGeom sweep_geom(const int n[3], int dir) {
     return g;
 }
 
-// Phases A and C for NC components staged in F[c] (FP64).  Known-row values
-// land in KN(c)[slot * P + l].  All threads of the block call it; it ends with
+// Phases A and C for NC components staged in F[c].  Known-row values land in
+// KN(c)[slot * P + l] (FP64).  All threads of the block call it; it ends with
 // a barrier; f' is then in F (compact rows) and KN (known rows).
+// TF = float (mixed precision): F holds FP32 values; the closure and wall rows
+// are still summed in FP64 from them, the Thomas runs eliminate in FP32 with
+// the plan's FP32 pivot tables.
 // OP = OP_FILTER applies the plan's implicit filter instead of the first
 // derivative: closure rows f_e + sum_j C_ej (f_j - f_e) (the filter's rows sum
 // to 1), wall rows unfiltered, interior right-hand side
 // a0 f_i + a1/2 (f_{i+1} + f_{i-1}) + a2/2 (f_{i+2} + f_{i-2}), A = (af, 1, af).
-template <int DIR, int NMAX, int NC, int PW = 0, int OP = OP_D1, int NTH = 256>
-__device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev &pl, int np) {
+template <int DIR, int NMAX, int NC, int PW = 0, int OP = OP_D1, int NTH = 256, class TF = double>
+__device__ inline void lds_line_solve(TF *Fb, double *KNb, const LinePlanDev &pl, int np) {
     using C = SweepCfg<DIR, NMAX, PW, NTH>;
     constexpr int KS = C::P * C::KMAX;
-    auto F = [&](int c) -> double * { return Fb + c * C::FSZ; };
+    auto F = [&](int c) -> TF * { return Fb + c * C::FSZ; };
     auto KN = [&](int c) -> double * { return KNb + c * KS; };
     constexpr bool FILT = OP == OP_FILTER;
+    static_assert(!FILT || sizeof(TF) == 8, "the filter runs in FP64");
     const int tid = threadIdx.x;
     const int n = pl.n;
     const double ih = pl.ih;
     const double alpha = FILT ? pl.alpha : kAlpha;
+    const TF ih_t = TF(ih), alpha_t = TF(alpha), b1_t = TF(kB1), b2_t = TF(kB2);
     const double fa0 = pl.fc.a0, fa1 = pl.fc.a1h, fa2 = pl.fc.a2h;
     // interior right-hand side of row i from the window f_{i-2} .. f_{i+2}
-    auto rhs5 = [&](double w0, double w1, double w2, double w3, double w4) {
+    auto rhs5 = [&](TF w0, TF w1, TF w2, TF w3, TF w4) -> TF {
         if constexpr (FILT) return fa0 * w2 + fa1 * (w1 + w3) + fa2 * (w0 + w4);
-        else return ih * (kB1 * (w3 - w1) + kB2 * (w4 - w0));
+        else return ih_t * (b1_t * (w3 - w1) + b2_t * (w4 - w0));
     };
     // plan tables through the scalar path where the index is wave-uniform
     const auto runs_i = NOPCS_SCALAR_PTR(int, pl.runs);
     const auto slot_i = NOPCS_SCALAR_PTR(int, pl.run_slot);
-    const auto rden = NOPCS_SCALAR_PTR(double, pl.rden);
-    const auto cp = NOPCS_SCALAR_PTR(double, pl.cp);
+    const TF *const rden_v = sizeof(TF) == 8 ? (const TF *)(const void *)pl.rden : (const TF *)(const void *)pl.rden32;
+    const TF *const cp_v = sizeof(TF) == 8 ? (const TF *)(const void *)pl.cp : (const TF *)(const void *)pl.cp32;
+    const auto rden = NOPCS_SCALAR_PTR(TF, rden_v);
+    const auto cp = NOPCS_SCALAR_PTR(TF, cp_v);
     // rows n .. (n rounded up to 32) - 1 of every staged line read as zeros
     // (phase A walks whole 32-row blocks)
     const int ntail = ((n + 31) & ~31) - n;
     if (ntail > 0) {
         for (int q = tid; q < NC * C::P * ntail; q += C::NT) {
             const int c = q / (C::P * ntail), rest = q - c * (C::P * ntail);
-            F(c)[C::fidx(rest % C::P, n + rest / C::P)] = 0.0;
+            F(c)[C::fidx(rest % C::P, n + rest / C::P)] = TF(0);
         }
         __syncthreads();
     }
@@ -126,7 +133,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         const int l = w % C::P, rest = w / C::P;
         const int c = rest % NC, s = rest / NC;     // s: closure index, or wall slot 0..3
         if (l >= np) continue;
-        const double *f = F(c);
+        const TF *f = F(c);
         double v;
         if (clo) {
             // f'_e = sum_t C_{e,j0+t} (f_{j0+t} - f_e) / h, walked over the aligned
@@ -141,12 +148,12 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             const int row = pl.cl_row[s], j0 = pl.cl_j0[s], len = pl.cl_len[s];
             const int b0 = j0 >> 5, nb = ((j0 + len - 1) >> 5) - b0 + 1;   // 1..4 blocks
             const double2 *ctab = reinterpret_cast<const double2 *>(pl.cl_coefA);
-            const double fe = f[C::fidx(l, row)];
+            const double fe = double(f[C::fidx(l, row)]);
             double a0 = 0.0, a1 = 0.0;
             for (int bb = 0; bb < 4; ++bb) {
                 if (bb >= nb) break;
                 const int r0 = (b0 + bb) << 5;
-                const double *fb = f + C::fidx(l, r0);
+                const TF *fb = f + C::fidx(l, r0);
                 NOPCS_LDS_BOUND(C::fidx(l, r0) + 31 * RS, C::FSZ);
                 const unsigned cofs = (unsigned)(16 * bb * ncl + s);
 #pragma unroll
@@ -156,7 +163,7 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
 #pragma unroll
                     for (int u = 0; u < TB / 2; ++u) cf[u] = (ctab + (size_t)(j8 / 2 + u) * ncl)[cofs];
 #pragma unroll
-                    for (int u = 0; u < TB; ++u) fv[u] = fb[(j8 + u) * RS] - fe;
+                    for (int u = 0; u < TB; ++u) fv[u] = double(fb[(j8 + u) * RS]) - fe;
 #pragma unroll
                     for (int u = 0; u < TB / 2; ++u) {
                         a0 = fma_(cf[u].x, fv[2 * u], a0);
@@ -166,17 +173,17 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             }
             v = FILT ? fe + (a0 + a1) : (a0 + a1) * ih;
         } else if (FILT) {
-            v = f[C::fidx(l, s == 0 ? 0 : s == 1 ? 1 : s == 2 ? n - 2 : n - 1)];
+            v = double(f[C::fidx(l, s == 0 ? 0 : s == 1 ? 1 : s == 2 ? n - 2 : n - 1)]);
         } else if (s == 0) {
-            const double f0 = f[C::fidx(l, 0)];
-            v = 0.5 * ih * (4.0 * (f[C::fidx(l, 1)] - f0) - (f[C::fidx(l, 2)] - f0));
+            const double f0 = double(f[C::fidx(l, 0)]);
+            v = 0.5 * ih * (4.0 * (double(f[C::fidx(l, 1)]) - f0) - (double(f[C::fidx(l, 2)]) - f0));
         } else if (s == 1) {
-            v = 0.5 * ih * (f[C::fidx(l, 2)] - f[C::fidx(l, 0)]);
+            v = 0.5 * ih * (double(f[C::fidx(l, 2)]) - double(f[C::fidx(l, 0)]));
         } else if (s == 2) {
-            v = 0.5 * ih * (f[C::fidx(l, n - 1)] - f[C::fidx(l, n - 3)]);
+            v = 0.5 * ih * (double(f[C::fidx(l, n - 1)]) - double(f[C::fidx(l, n - 3)]));
         } else {
-            const double fl = f[C::fidx(l, n - 1)];
-            v = -0.5 * ih * (4.0 * (f[C::fidx(l, n - 2)] - fl) - (f[C::fidx(l, n - 3)] - fl));
+            const double fl = double(f[C::fidx(l, n - 1)]);
+            v = -0.5 * ih * (4.0 * (double(f[C::fidx(l, n - 2)]) - fl) - (double(f[C::fidx(l, n - 3)]) - fl));
         }
         KN(c)[C::kidx(clo ? 4 + s : s, l)] = v;
     }
@@ -191,26 +198,26 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
         const int c = q / (C::P * pl.nrun), rest = q - c * (C::P * pl.nrun);
         const int l = rest % C::P, r = rest / C::P;
         if (l >= np) continue;
-        double *f = F(c);
+        TF *f = F(c);
         const double *kn = KN(c);
         const int lo = runs_i[2 * r], hi = runs_i[2 * r + 1], m = hi - lo - 1;
-        const double xlo = kn[C::kidx(slot_i[2 * r], l)];
-        const double xhi = kn[C::kidx(slot_i[2 * r + 1], l)];
+        const TF xlo = TF(kn[C::kidx(slot_i[2 * r], l)]);
+        const TF xhi = TF(kn[C::kidx(slot_i[2 * r + 1], l)]);
         // window f_{i-2} .. f_{i+2} at i = lo + 1; rows lo - 1 and hi + 1 are
         // known rows (closures and walls come in adjacent pairs), whose F keeps f
-        double w0 = f[C::fidx(l, lo - 1)];
-        double w1 = f[C::fidx(l, lo)];
-        double w2 = f[C::fidx(l, lo + 1)];
-        double w3 = f[C::fidx(l, min(lo + 2, hi + 1))];
-        double w4 = f[C::fidx(l, min(lo + 3, hi + 1))];
+        TF w0 = f[C::fidx(l, lo - 1)];
+        TF w1 = f[C::fidx(l, lo)];
+        TF w2 = f[C::fidx(l, lo + 1)];
+        TF w3 = f[C::fidx(l, min(lo + 2, hi + 1))];
+        TF w4 = f[C::fidx(l, min(lo + 3, hi + 1))];
         // row k = 1 (every lane starts there) with the lower known value; the
         // upper known value enters row m after the loop: d_m gains
         // -alpha x_hi / den_m, the only place where it appears
-        double dprev;
+        TF dprev;
         {
-            const double fn = f[C::fidx(l, min(lo + 4, hi + 1))];
-            double rr = rhs5(w0, w1, w2, w3, w4);
-            rr = rr - alpha * xlo;
+            const TF fn = f[C::fidx(l, min(lo + 4, hi + 1))];
+            TF rr = rhs5(w0, w1, w2, w3, w4);
+            rr = rr - alpha_t * xlo;
             dprev = rr * rden[1];
             f[C::fidx(l, lo + 1)] = dprev;
             w0 = w1;
@@ -219,14 +226,14 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             w3 = w4;
             w4 = fn;
         }
-        double cpk = cp[2], rdk = rden[2];
+        TF cpk = cp[2], rdk = rden[2];
 #pragma unroll 2
         for (int k = 2; k <= m; ++k) {
             const int i = lo + k;
-            const double fn = f[C::fidx(l, min(i + 3, hi + 1))];
-            const double cpn = cp[k + 1], rdn = rden[k + 1];
-            const double rr = rhs5(w0, w1, w2, w3, w4);
-            const double dp = fma_(-cpk, dprev, rr * rdk);
+            const TF fn = f[C::fidx(l, min(i + 3, hi + 1))];
+            const TF cpn = cp[k + 1], rdn = rden[k + 1];
+            const TF rr = rhs5(w0, w1, w2, w3, w4);
+            const TF dp = fma_(-cpk, dprev, rr * rdk);
             f[C::fidx(l, i)] = dp;
             dprev = dp;
             cpk = cpn;
@@ -237,17 +244,17 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
             w3 = w4;
             w4 = fn;
         }
-        dprev = fma_(-alpha * xhi, pl.rden[m], dprev);
+        dprev = fma_(-alpha_t * xhi, rden_v[m], dprev);
         f[C::fidx(l, lo + m)] = dprev;
         // backward: x_m = d_m, x_k = d_k - c'_k x_{k+1}; k runs from the plan's
         // longest run down, lanes of shorter runs wait until k < m
-        double fcur = f[C::fidx(l, lo + max(min(kmax - 1, m - 1), 1))];
+        TF fcur = f[C::fidx(l, lo + max(min(kmax - 1, m - 1), 1))];
         cpk = cp[max(kmax - 1, 1)];
         for (int k = kmax - 1; k >= 1; --k) {
-            const double fnx = f[C::fidx(l, lo + max(min(k - 1, m - 1), 1))];
-            const double cpx = cp[max(k - 1, 1)];
+            const TF fnx = f[C::fidx(l, lo + max(min(k - 1, m - 1), 1))];
+            const TF cpx = cp[max(k - 1, 1)];
             if (k < m) {
-                const double x = fma_(-cpk, dprev, fcur);
+                const TF x = fma_(-cpk, dprev, fcur);
                 f[C::fidx(l, lo + k)] = x;
                 dprev = x;
             }
@@ -260,10 +267,10 @@ __device__ inline void lds_line_solve(double *Fb, double *KNb, const LinePlanDev
 
 // f' of component c at (l, i) after lds_line_solve; ks = pl.kslot[i] (the
 // known-row slot of row i, -1 for a compact row), read once by the caller
-template <int DIR, int NMAX, int PW = 0, int NTH = 256>
-__device__ inline double lds_result(const double *Fb, const double *KNb, int c, int ks, int l, int i) {
+template <int DIR, int NMAX, int PW = 0, int NTH = 256, class TF = double>
+__device__ inline double lds_result(const TF *Fb, const double *KNb, int c, int ks, int l, int i) {
     using C = SweepCfg<DIR, NMAX, PW, NTH>;
-    return ks < 0 ? Fb[c * C::FSZ + C::fidx(l, i)] : KNb[c * C::P * C::KMAX + C::kidx(ks, l)];
+    return ks < 0 ? double(Fb[c * C::FSZ + C::fidx(l, i)]) : KNb[c * C::P * C::KMAX + C::kidx(ks, l)];
 }
 
 // known-row slots of a thread's owned points (clamped index: always a valid read)
