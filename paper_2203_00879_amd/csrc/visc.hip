@@ -9,18 +9,26 @@
 // marches along z over a chunk of planes; one thread per column, one barrier
 // per plane (primitives and fluxes of plane k in LDS buffer k mod 2 while the
 // divergence of plane k-1 reads the other buffer).  Each thread
-// keeps the primitives (u, v, w, T) of its own column for planes k-2..k+2 in
-// registers, so z differences need no shared memory.  Per plane, every column
+// keeps the primitives (u, v, w, T) of its own column for planes k-1..k+1 in
+// registers (planes k-2 and k+2 are loaded again at the walls), so z
+// differences need no shared memory.  Per plane, every column
 // publishes its primitives in LDS once; every node then evaluates its gradients,
 // mu, beta and the flux vectors it contributes (Ev at x-neighbours, Fv at
 // y-neighbours, Gv at the column itself) exactly once.  The x and y parts of
 // the divergence are taken from LDS at plane k; the z part is finished one
 // plane later from a three-plane register history of Gv.  Each state value is
-// read from HBM about 1.5 times (tile halo), each flux vector computed once.
+// read from HBM about 1.8 times (tile halo of 32 x 16 columns for 28 x 12
+// outputs, the z-chunk overlap, the planes loaded ahead of a chunk's end),
+// each flux vector computed once.
 // Tiles at the high end of x and y are shifted inward (overlapping their
 // neighbour, which writes identical values) so that the one-sided wall
 // stencils stay inside the halo.  The summation order is that of the oracle:
 // (dEv/dx + dFv/dy) + dGv/dz, then the source.
+// Mixed precision (R in FP32): the primitives are formed in FP64 from the
+// state and rounded once; their differences, the stresses, heat fluxes and
+// the divergence run in FP32 (mu and beta from the rounded temperature in
+// FP64), with one plane in flight: 128 VGPRs and 48 KB of LDS, two blocks
+// per CU instead of one.
 #include <algorithm>
 #include <atomic>
 
@@ -33,8 +41,10 @@ namespace {
 // 512 threads holds its CU alone (two waves per SIMD), so registers up to 256
 // per thread cost no occupancy: three planes in flight (231 VGPRs) hide more
 // of the load latency than one (166): 4.39 -> 4.08 ms at 512^3.
-constexpr int VPF = 3;
-static_assert(VPF >= 1 && VPF <= 3, "one to three planes in flight");
+// The FP32 form (mixed precision) keeps one plane in flight instead, so that
+// two blocks share a CU (at most 128 VGPRs, see ViscBody).
+constexpr int VPF64 = 3, VPF32 = 1;
+static_assert(VPF64 >= 1 && VPF64 <= 3 && VPF32 >= 1 && VPF32 <= 3, "one to three planes in flight");
 // Outputs per block (CTX x CTY) and columns per block (with a two-point halo).
 constexpr int CTX = 28, CTY = 12, CX = CTX + 4, CY = CTY + 4, CNT = CX * CY;
 
@@ -50,16 +60,18 @@ struct VArgs {
 // second-order derivative from three values along an axis: f(-1), f(+1)
 // inside, or the one-sided form at a wall node (f0 on the wall, f1, f2 inward;
 // the high wall flips the sign)
-__device__ inline double d2c(double fm, double fp, double ih) { return 0.5 * ih * (fp - fm); }
-__device__ inline double d2w(double f0, double f1, double f2, double ih, bool high) {
-    const double v = 0.5 * ih * (4.0 * (f1 - f0) - (f2 - f0));
+template <class T>
+__device__ inline T d2c(T fm, T fp, T ih) { return T(0.5) * ih * (fp - fm); }
+template <class T>
+__device__ inline T d2w(T f0, T f1, T f2, T ih, bool high) {
+    const T v = T(0.5) * ih * (T(4.0) * (f1 - f0) - (f2 - f0));
     return high ? -v : v;
 }
 
 // derivative of LDS field P at slot o along x (st = 1) or y (st = CX); g is
 // the node's global index along that axis.  WALL: the node may lie on a wall.
-template <bool WALL>
-__device__ inline double dplane(const double *P, int o, int st, int g, int n, double ih) {
+template <bool WALL, class T>
+__device__ inline T dplane(const T *P, int o, int st, int g, int n, T ih) {
     if (WALL) {
         if (g == 0) {
             NOPCS_LDS_BOUND(o + 2 * st, CNT);
@@ -77,7 +89,8 @@ __device__ inline double dplane(const double *P, int o, int st, int g, int n, do
 
 // z derivative at plane k from the column window w = planes k-1, k, k+1; the
 // walls also need plane k+2 (fp2, bottom) or k-2 (fm2, top)
-__device__ inline double dz(const double w[3], double fm2, double fp2, int k, int nz, double ih) {
+template <class T>
+__device__ inline T dz(const T w[3], T fm2, T fp2, int k, int nz, T ih) {
     if (k == 0) return d2w(w[1], w[2], fp2, ih, false);
     if (k == nz - 1) return d2w(w[1], w[0], fm2, ih, true);
     return d2c(w[0], w[2], ih);
@@ -86,9 +99,14 @@ __device__ inline double dz(const double w[3], double fm2, double fp2, int k, in
 // One block's march over planes k0..k1-1 (see the file header).  S holds, per
 // column slot: u, v, w, T of plane k (fields 0-3), Ev (4-7) and Fv (8-11).
 // Output columns with gi < own_i or gj < own_j belong to the neighbouring tile.
-template <bool WALL, class TR>
-__device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int own_i, int own_j, int k0,
+// TV: arithmetic of the primitives' differences, the stresses and fluxes and
+// the divergence (FP64; FP32 in mixed precision, where R is FP32 too); the
+// state is read and turned into primitives in FP64, the gravity source and
+// mu, beta are formed in FP64.
+template <bool WALL, class TR, class TV>
+__device__ inline void visc_march(const VArgs &A, TV *S, int i0, int j0, int own_i, int own_j, int k0,
                                   int k1) {
+    constexpr int VPF = sizeof(TV) == 8 ? VPF64 : VPF32;
     TR *const R = static_cast<TR *>(A.R);
     const NdConst &c = A.c;
     const double *Q = A.Q;
@@ -119,15 +137,16 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             q[f] = in ? v : (f == 0 ? 1.0 : 0.0);
         }
     };
-    auto prim = [&](const double q[5], double &u, double &v, double &w, double &T) {
+    auto prim = [&](const double q[5], TV &u, TV &v, TV &w, TV &T) {
         const Prim pr = prim_from(c, q[0], q[1], q[2], q[3], q[4]);
-        u = pr.u;
-        v = pr.v;
-        w = pr.w;
-        T = pr.T;
+        u = TV(pr.u);
+        v = TV(pr.v);
+        w = TV(pr.w);
+        T = TV(pr.T);
     };
+    const TV ihx = TV(A.ihx), ihy = TV(A.ihy), ihz = TV(A.ihz), iRe = TV(c.iRe), kap = TV(c.kappa);
     // R of plane k: the divergence plus the gravity source (rho and rho v of that plane)
-    auto write_R = [&](int k, const double acc[4], double rho, double my) {
+    auto write_R = [&](int k, const TV acc[4], double rho, double my) {
         const long long o = col + plane * k;
         R[o] = TR(0.0);
         R[N3 + o] = TR(acc[0]);
@@ -140,7 +159,8 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     const int kb = max(0, min(k0 - 1, A.nz - 3)), ke = min(A.nz - 1, k1);
     // window before the first shift: planes kb-2, kb-1, kb; raw states of
     // kb+1 (rawA) and, with two planes in flight, kb+2 (rawB)
-    double wu[3], wv[3], ww[3], wT[3], wr[3], wy[3], raw[5], rawB[5], rawC[5];
+    TV wu[3], wv[3], ww[3], wT[3];
+    double wr[3], wy[3], raw[5], rawB[5], rawC[5];
 #pragma unroll
     for (int s = 1; s < 3; ++s) {
         load(kb - 2 + s, raw);
@@ -152,14 +172,14 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     if (VPF >= 2) load(kb + 2, rawB);
     if (VPF == 3) load(kb + 3, rawC);
     // G history (planes k-2, k-1, k)
-    double G[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    TV G[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     // dEv/dx + dFv/dy at plane p from the fluxes in buffer p & 1
-    auto xy_part = [&](int p, double part[4]) {
-        const double *Sc = S + (p & 1) * SB;
+    auto xy_part = [&](int p, TV part[4]) {
+        const TV *Sc = S + (p & 1) * SB;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            part[q] = dplane<WALL>(Sc + (4 + q) * CNT, tid, 1, gi, A.nx, A.ihx) +
-                      dplane<WALL>(Sc + (8 + q) * CNT, tid, CX, gj, A.ny, A.ihy);
+            part[q] = dplane<WALL>(Sc + (4 + q) * CNT, tid, 1, gi, A.nx, ihx) +
+                      dplane<WALL>(Sc + (8 + q) * CNT, tid, CX, gj, A.ny, ihy);
     };
 
     // plane k; cur holds the raw state of plane k+1 and receives that of
@@ -184,57 +204,56 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
         load(k + 1 + VPF, cur);
         // one barrier per plane: the primitives and fluxes of plane k go to
         // buffer k & 1 while the divergence of plane k-1 reads buffer (k-1) & 1
-        double *const Sb = S + (k & 1) * SB;
-        double *const Pu = Sb, *const Pv = Sb + CNT, *const Pw = Sb + 2 * CNT, *const PT = Sb + 3 * CNT;
+        TV *const Sb = S + (k & 1) * SB;
+        TV *const Pu = Sb, *const Pv = Sb + CNT, *const Pw = Sb + 2 * CNT, *const PT = Sb + 3 * CNT;
         Pu[tid] = wu[1];
         Pv[tid] = wv[1];
         Pw[tid] = ww[1];
         PT[tid] = wT[1];
         __syncthreads();
         // ---- node fluxes at (column, plane k): each computed once ----
-        double Gk[4] = {0, 0, 0, 0};
+        TV Gk[4] = {0, 0, 0, 0};
         if (needE || needF) {
-            double um2 = 0.0, vm2 = 0.0, wm2 = 0.0, Tm2 = 0.0, up2 = 0.0, vp2 = 0.0, wp2 = 0.0, Tp2 = 0.0;
+            TV um2 = 0, vm2 = 0, wm2 = 0, Tm2 = 0, up2 = 0, vp2 = 0, wp2 = 0, Tp2 = 0;
             if (k == 0) prim(VPF == 1 ? cur : nxt, up2, vp2, wp2, Tp2);
             if (k == A.nz - 1) {
                 double q2[5];
                 load(k - 2, q2);
                 prim(q2, um2, vm2, wm2, Tm2);
             }
-            const double u = wu[1], v = wv[1], w = ww[1], T = wT[1];
-            const double m = mu_of(c, T), bb = beta_of(c, T);
-            const double Aa = (4.0 / 3.0) * m + bb, Bb = bb - (2.0 / 3.0) * m;
+            const TV u = wu[1], v = wv[1], w = ww[1], T = wT[1];
+            const TV m = TV(mu_of(c, double(T))), bb = TV(beta_of(c, double(T)));
+            const TV Aa = TV(4.0 / 3.0) * m + bb, Bb = bb - TV(2.0 / 3.0) * m;
             // the stress tensor first (bv1-bv3), so that the nine velocity
             // gradients die early; each entry is formed exactly as the oracle does
-            double txx, tyy, tzz;
+            TV txx, tyy, tzz;
             {
-                const double ux = dplane<WALL>(Pu, tid, 1, gi, A.nx, A.ihx);
-                const double vy = dplane<WALL>(Pv, tid, CX, gj, A.ny, A.ihy);
-                const double wz = dz(ww, wm2, wp2, k, A.nz, A.ihz);
-                txx = (Aa * ux + Bb * (vy + wz)) * c.iRe;
-                tyy = (Aa * vy + Bb * (ux + wz)) * c.iRe;
-                tzz = (Aa * wz + Bb * (ux + vy)) * c.iRe;
+                const TV ux = dplane<WALL>(Pu, tid, 1, gi, A.nx, ihx);
+                const TV vy = dplane<WALL>(Pv, tid, CX, gj, A.ny, ihy);
+                const TV wz = dz(ww, wm2, wp2, k, A.nz, ihz);
+                txx = (Aa * ux + Bb * (vy + wz)) * iRe;
+                tyy = (Aa * vy + Bb * (ux + wz)) * iRe;
+                tzz = (Aa * wz + Bb * (ux + vy)) * iRe;
             }
-            const double txy =
-                m * (dplane<WALL>(Pu, tid, CX, gj, A.ny, A.ihy) + dplane<WALL>(Pv, tid, 1, gi, A.nx, A.ihx)) * c.iRe;
-            const double txz = m * (dz(wu, um2, up2, k, A.nz, A.ihz) + dplane<WALL>(Pw, tid, 1, gi, A.nx, A.ihx)) * c.iRe;
-            const double tyz = m * (dz(wv, vm2, vp2, k, A.nz, A.ihz) + dplane<WALL>(Pw, tid, CX, gj, A.ny, A.ihy)) * c.iRe;
+            const TV txy = m * (dplane<WALL>(Pu, tid, CX, gj, A.ny, ihy) + dplane<WALL>(Pv, tid, 1, gi, A.nx, ihx)) * iRe;
+            const TV txz = m * (dz(wu, um2, up2, k, A.nz, ihz) + dplane<WALL>(Pw, tid, 1, gi, A.nx, ihx)) * iRe;
+            const TV tyz = m * (dz(wv, vm2, vp2, k, A.nz, ihz) + dplane<WALL>(Pw, tid, CX, gj, A.ny, ihy)) * iRe;
             if (needE) {
-                const double qx = -c.kappa * m * dplane<WALL>(PT, tid, 1, gi, A.nx, A.ihx);
+                const TV qx = -kap * m * dplane<WALL>(PT, tid, 1, gi, A.nx, ihx);
                 Sb[4 * CNT + tid] = txx;
                 Sb[5 * CNT + tid] = txy;
                 Sb[6 * CNT + tid] = txz;
                 Sb[7 * CNT + tid] = u * txx + v * txy + w * txz - qx;
             }
             if (needF) {
-                const double qy = -c.kappa * m * dplane<WALL>(PT, tid, CX, gj, A.ny, A.ihy);
+                const TV qy = -kap * m * dplane<WALL>(PT, tid, CX, gj, A.ny, ihy);
                 Sb[8 * CNT + tid] = txy;
                 Sb[9 * CNT + tid] = tyy;
                 Sb[10 * CNT + tid] = tyz;
                 Sb[11 * CNT + tid] = u * txy + v * tyy + w * tyz - qy;
             }
             if (center) {
-                const double qz = -c.kappa * m * dz(wT, Tm2, Tp2, k, A.nz, A.ihz);
+                const TV qz = -kap * m * dz(wT, Tm2, Tp2, k, A.nz, ihz);
                 Gk[0] = txz;
                 Gk[1] = tyz;
                 Gk[2] = tzz;
@@ -250,13 +269,13 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
             }
             // plane k-1: its fluxes were written before this plane's barrier
             const bool own_prev = k - 1 >= k0 && k - 1 < k1 && k - 1 >= kb;
-            double part[4] = {0, 0, 0, 0};
+            TV part[4] = {0, 0, 0, 0};
             if (own_prev) xy_part(k - 1, part);
             // finish plane k-1 (inside): needs G(k) - G(k-2)
             if (own_prev && k - 1 >= 1 && k - 1 <= A.nz - 2) {
-                double acc[4];
+                TV acc[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2c(G[0][q], G[2][q], A.ihz);
+                for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2c(G[0][q], G[2][q], ihz);
                 write_R(k - 1, acc, wr[0], wy[0]);
             }
             // the bottom wall plane waits for G(0), G(1), G(2); its x-y part is
@@ -266,10 +285,10 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
                 for (int q = 0; q < 4; ++q) R[(q + 1) * N3 + col] = TR(part[q]);
             }
             if (k == 2 && k0 == 0) {
-                double acc[4];
+                TV acc[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    acc[q] = double(R[(q + 1) * N3 + col]) + d2w(G[0][q], G[1][q], G[2][q], A.ihz, false);
+                    acc[q] = TV(R[(q + 1) * N3 + col]) + d2w(G[0][q], G[1][q], G[2][q], ihz, false);
                 write_R(0, acc, Q[col], Q[2 * N3 + col]);
             }
         }
@@ -296,10 +315,10 @@ __device__ inline void visc_march(const VArgs &A, double *S, int i0, int j0, int
     if (ke == A.nz - 1 && ke < k1) {
         __syncthreads();
         if (center) {
-            double part[4], acc[4];
+            TV part[4], acc[4];
             xy_part(ke, part);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], A.ihz, true);
+            for (int q = 0; q < 4; ++q) acc[q] = part[q] + d2w(G[2][q], G[1][q], G[0][q], ihz, true);
             write_R(ke, acc, wr[1], wy[1]);
         }
     }
@@ -330,16 +349,19 @@ __device__ inline void visc_body(const VArgs &A, int b) {
         }
         return;
     }
-    __shared__ double S[2 * 12 * CNT];
+    using TV = TR;
+    __shared__ TV S[2 * 12 * CNT];
     // every column and every flux node of the tile off the x and y walls
     const bool interior = i0 >= 2 && i0 + CTX + 2 <= A.nx && j0 >= 2 && j0 + CTY + 2 <= A.ny;
-    if (interior) visc_march<false, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
-    else visc_march<true, TR>(A, S, i0, j0, own_i, own_j, k0, k1);
+    if (interior) visc_march<false, TR, TV>(A, S, i0, j0, own_i, own_j, k0, k1);
+    else visc_march<true, TR, TV>(A, S, i0, j0, own_i, own_j, k0, k1);
 }
 
 template <class TR>
 struct ViscBody {
     using Args = VArgs;
+    // FP32 form: four waves per SIMD (two 512-thread blocks per CU)
+    static constexpr int kMinWaves = sizeof(TR) == 4 ? 4 : 1;
     __device__ static void run(const Args &a, int b, int) { visc_body<TR>(a, b); }
 };
 }  // namespace

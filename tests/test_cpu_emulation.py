@@ -262,12 +262,13 @@ def test_emulated_batch_step(driver, tmp_path, mixed):
 
 def test_emulated_rhs_mixed_precision(driver, tmp_path):
     """Mixed precision (FP32 eliminations along y and z, the x sweep in FP32 on
-    offset fluxes, FP64 known rows and viscous terms) against the oracle's
-    FP64 right-hand side.  Error budget: the FP32 runs see their right-hand
-    side rounded once (relative 6e-8 of (B f)_i along y and z, of the line's
-    own flux variation along x) and amplify it by at most the row sum of
-    |A^-1| (< 4.4); with the viscous part exact to FP64 the RHS error stays
-    below 1e-6 of each component's maximum (measured 2.4e-7)."""
+    offset fluxes, FP32 viscous differences and stresses, FP64 known rows)
+    against the oracle's FP64 right-hand side.  Error budget: the FP32 runs
+    see their right-hand side rounded once (relative 6e-8 of (B f)_i along y
+    and z, of the line's own flux variation along x) and amplify it by at most
+    the row sum of |A^-1| (< 4.4); the viscous terms carry FP32 roundings of
+    their own size; the RHS error stays below 1e-6 of each component's
+    maximum (measured 2.4e-7)."""
     p = dict(inputs.AIR)
     shape = (12, 40, 70)
     Q = inputs.smooth_state(shape, seed=31)

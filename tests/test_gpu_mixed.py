@@ -1,14 +1,16 @@
 """Mixed precision (NOPCS_MIXED) on the GPU: FP32 eliminations along y and z,
 the x sweep staged and solved in FP32 on offset fluxes (each flux less its
-line's first-row value), an FP32 RHS register; known rows, viscous terms and
-the RK registers in FP64.
+line's first-row value), the viscous differences, stresses, heat fluxes and
+their divergence in FP32, an FP32 RHS register; state, primitives, known rows
+and the RK registers in FP64.
 
 Error budget: each FP32 run sees its right-hand side rounded once (unit
 roundoff 6e-8: (B f)_i along y and z, the offset flux values along x, whose
 size is the line's own variation) and amplifies it by at most the row sum of
 |A^-1| (< 4.4), so the right-hand side is within about 3e-7 of each
-component's maximum; the RHS register in FP32 adds one more rounding.  The
-tolerances below give a factor of 3-30 over that."""
+component's maximum; the viscous terms carry FP32 roundings of the same size
+relative to their own magnitude, and the RHS register in FP32 adds one more
+rounding.  The tolerances below give a factor of 3-30 over that."""
 import numpy as np
 import pytest
 
