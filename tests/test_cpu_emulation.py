@@ -283,6 +283,27 @@ def test_emulated_rhs_mixed_precision(driver, tmp_path):
     assert max(errs) > 0.0     # the FP32 path really ran
 
 
+def test_emulated_rhs_mixed_uniform_motion(driver, tmp_path):
+    """Mixed precision on a uniform state in uniform motion: every derivative
+    vanishes exactly (offset x fluxes of zero, (B f)_i and the closure and wall
+    rows of the y and z runs from equal values, FP32 viscous differences of
+    equal numbers), so rho, rho u, rho w are exactly zero and the gravity
+    source components within one FP32 rounding of the oracle's closed form."""
+    p = dict(inputs.AIR)
+    shape = (12, 40, 70)
+    Q = inputs.uniform_state(shape, T=1.3, rho=0.83, velocity=(0.31, -0.47, 0.19), params=p)
+    qin, rout = tmp_path / "q.raw", tmp_path / "r.raw"
+    Q.tofile(qin)
+    _run(driver, ["rhs", *shape, 1, 2, 2, 1.0, 1.0, 1.0, 1, 1, qin, rout], tmp_path, mixed=True)
+    R = np.fromfile(rout).reshape(Q.shape)
+    Ro = oracle.rhs(p, Q)
+    for c in (0, 1, 3):
+        assert np.all(R[c] == 0.0), c
+    for c in (2, 4):
+        s = np.max(np.abs(Ro[c]))
+        assert np.max(np.abs(R[c] - Ro[c])) <= 2.0 ** -23 * s, c
+
+
 @pytest.mark.parametrize("form", [0, 2])
 def test_emulated_vorticity_budget(driver, tmp_path, form):
     """Vorticity budget of Eq. eqn12_1 on a ragged box with segmented lines and

@@ -42,6 +42,34 @@ def test_rhs_mixed_against_oracle(shape, nseg):
     assert max(errs) <= 1e-6 and max(errs) > 0
 
 
+@pytest.mark.parametrize("shape, nseg", [((40, 36, 70), (2, 3, 2)), ((130, 24, 40), (3, 1, 2))])
+def test_rhs_mixed_uniform_motion_is_the_gravity_source(shape, nseg):
+    """A uniform state in uniform motion has no derivative of any flux (the
+    oracle's pin: R = [0, 0, -rho, 0, -rho v]).  In mixed precision every
+    derivative must still vanish exactly: the x sweep stages offset fluxes that
+    are exact zeros, the y and z runs form (B f)_i and their closure and wall
+    rows from equal FP64 values, the FP32 viscous differences subtract equal
+    numbers.  So rho, rho u and rho w come out exactly zero, and the two source
+    components within one FP32 rounding (the RHS register) of the oracle."""
+    import torch
+    p = dict(inputs.AIR)
+    rho, vel = 0.83, (0.31, -0.47, 0.19)
+    Q = inputs.uniform_state(shape, T=1.3, rho=rho, velocity=vel, params=p)
+    g = nopcs.make_grid(shape, nseg)
+    Qd = torch.from_numpy(Q).to("cuda")
+    Rd = torch.empty_like(Qd)
+    nopcs.nse_rhs(nopcs.make_params(p), g, Qd, Rd, precision=nopcs.MIXED)
+    torch.cuda.synchronize()
+    R = Rd.cpu().numpy()
+    Ro = oracle.rhs(p, Q)
+    for c in (0, 1, 3):
+        assert np.all(R[c] == 0.0), (c, np.max(np.abs(R[c])))
+    for c in (2, 4):
+        scale = np.max(np.abs(Ro[c]))
+        assert scale > 0
+        assert np.max(np.abs(R[c] - Ro[c])) <= 2.0 ** -23 * scale, (c, np.max(np.abs(R[c] - Ro[c])) / scale)
+
+
 # Per-field bound of mixed-precision RK4 stepping, relative to the largest change
 # of the field over the run: each stage's right-hand side carries about 3e-7
 # of its components' maxima (see the module docstring) and the change over the
