@@ -51,11 +51,14 @@ enum {
 enum {
     NOPCS_FP64 = 0,   /* every step in FP64 */
     NOPCS_MIXED = 1   /* nse_rhs, rk_step: the Thomas eliminations of the y and z sweeps
-                         run in FP32 on (B f)_i rounded once from FP64; the RHS
-                         register of rk_step is stored in FP32; fluxes, closure rows,
-                         wall rows, viscous terms and the RK registers (state,
-                         accumulator, stage state) stay FP64.  The x sweep (and any
-                         line that falls back to the LDS pencil) computes in FP64. */
+                         run in FP32 on (B f)_i rounded once from FP64; the x sweep
+                         (and any line that falls back to the LDS pencil) stages and
+                         solves in FP32 each flux less its line's first-row value;
+                         the viscous differences, stresses, heat fluxes and their
+                         divergence run in FP32 from primitives rounded once; the
+                         RHS register is FP32.  Closure rows, wall rows, the gravity
+                         source and the RK registers (state, accumulator, stage
+                         state) stay FP64. */
 };
 
 /* Uniform box.  n[d] >= 8 points along x, y, z; len[d] > 0 non-dimensional edge

@@ -25,7 +25,10 @@ def _rel(a, b):
     return np.max(np.abs(a - b)) / (s if s > 0 else 1.0)
 
 
-@pytest.mark.parametrize("shape, nseg", [((40, 130, 97), (1, 3, 2)), ((64, 64, 64), (2, 2, 2))])
+@pytest.mark.parametrize("shape, nseg", [((40, 130, 97), (1, 3, 2)), ((64, 64, 64), (2, 2, 2)),
+                                         ((1024, 10, 9), (5, 1, 1)),    # longest x lines: FP32 1024-point pencils
+                                         ((10, 1024, 9), (1, 7, 1)),    # longest y lines
+                                         ((9, 10, 1024), (1, 1, 9))])   # longest z lines
 def test_rhs_mixed_against_oracle(shape, nseg):
     import torch
     p = dict(inputs.AIR)
