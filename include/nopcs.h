@@ -50,15 +50,16 @@ enum {
 
 enum {
     NOPCS_FP64 = 0,   /* every step in FP64 */
-    NOPCS_MIXED = 1   /* nse_rhs, rk_step: the Thomas eliminations of the y and z sweeps
-                         run in FP32 on (B f)_i rounded once from FP64; the x sweep
-                         (and any line that falls back to the LDS pencil) stages and
-                         solves in FP32 each flux less its line's first-row value;
-                         the viscous differences, stresses, heat fluxes and their
-                         divergence run in FP32 from primitives rounded once; the
-                         RHS register is FP32.  Closure rows, wall rows, the gravity
-                         source and the RK registers (state, accumulator, stage
-                         state) stay FP64. */
+    NOPCS_MIXED = 1   /* rk_step: the Thomas eliminations of the y and z sweeps run in
+                         FP32 on (B f)_i rounded once from FP64; the x sweep (and any
+                         line that falls back to the LDS pencil) stages and solves in
+                         FP32 each flux less its line's first-row value; the viscous
+                         differences, stresses, heat fluxes and their divergence run
+                         in FP32 from primitives rounded once; the RHS register is
+                         FP32.  Closure rows, wall rows, the gravity source and the
+                         RK registers (state, accumulator, stage state) stay FP64.
+                         nse_rhs, whose R is the caller's FP64 array: only the y and
+                         z eliminations (line marches) run in FP32. */
 };
 
 /* Uniform box.  n[d] >= 8 points along x, y, z; len[d] > 0 non-dimensional edge

@@ -261,13 +261,11 @@ def test_emulated_batch_step(driver, tmp_path, mixed):
 
 
 def test_emulated_rhs_mixed_precision(driver, tmp_path):
-    """Mixed precision (FP32 eliminations along y and z, the x sweep in FP32 on
-    offset fluxes, FP32 viscous differences and stresses, FP64 known rows)
+    """nse_rhs in mixed precision (FP32 eliminations along y and z; its R is
+    the caller's FP64 array, so the x sweep and viscous terms stay FP64)
     against the oracle's FP64 right-hand side.  Error budget: the FP32 runs
-    see their right-hand side rounded once (relative 6e-8 of (B f)_i along y
-    and z, of the line's own flux variation along x) and amplify it by at most
-    the row sum of |A^-1| (< 4.4); the viscous terms carry FP32 roundings of
-    their own size; the RHS error stays below 1e-6 of each component's
+    see (B f)_i rounded once (relative 6e-8) and amplify it by at most the row
+    sum of |A^-1| (< 4.4); the RHS error stays below 1e-6 of each component's
     maximum (measured 2.4e-7)."""
     p = dict(inputs.AIR)
     shape = (12, 40, 70)
@@ -284,11 +282,11 @@ def test_emulated_rhs_mixed_precision(driver, tmp_path):
 
 
 def test_emulated_rhs_mixed_uniform_motion(driver, tmp_path):
-    """Mixed precision on a uniform state in uniform motion: every derivative
-    vanishes exactly (offset x fluxes of zero, (B f)_i and the closure and wall
-    rows of the y and z runs from equal values, FP32 viscous differences of
-    equal numbers), so rho, rho u, rho w are exactly zero and the gravity
-    source components within one FP32 rounding of the oracle's closed form."""
+    """nse_rhs in mixed precision on a uniform state in uniform motion: every
+    derivative vanishes exactly ((B f)_i and the closure and wall rows of the
+    FP32 y and z runs formed from equal FP64 values), so rho, rho u, rho w are
+    exactly zero and the gravity source components within one FP32 rounding of
+    the oracle's closed form."""
     p = dict(inputs.AIR)
     shape = (12, 40, 70)
     Q = inputs.uniform_state(shape, T=1.3, rho=0.83, velocity=(0.31, -0.47, 0.19), params=p)

@@ -1,8 +1,9 @@
-"""Mixed precision (NOPCS_MIXED) on the GPU: FP32 eliminations along y and z,
-the x sweep staged and solved in FP32 on offset fluxes (each flux less its
-line's first-row value), the viscous differences, stresses, heat fluxes and
-their divergence in FP32, an FP32 RHS register; state, primitives, known rows
-and the RK registers in FP64.
+"""Mixed precision (NOPCS_MIXED) on the GPU.  rk_step: FP32 eliminations along
+y and z, the x sweep staged and solved in FP32 on offset fluxes (each flux
+less its line's first-row value), the viscous differences, stresses, heat
+fluxes and their divergence in FP32, an FP32 RHS register; state, primitives,
+known rows and the RK registers in FP64.  nse_rhs (FP64 output): the FP32
+eliminations along y and z only.
 
 Error budget: each FP32 run sees its right-hand side rounded once (unit
 roundoff 6e-8: (B f)_i along y and z, the offset flux values along x, whose
@@ -48,12 +49,10 @@ def test_rhs_mixed_against_oracle(shape, nseg):
 @pytest.mark.parametrize("shape, nseg", [((40, 36, 70), (2, 3, 2)), ((130, 24, 40), (3, 1, 2))])
 def test_rhs_mixed_uniform_motion_is_the_gravity_source(shape, nseg):
     """A uniform state in uniform motion has no derivative of any flux (the
-    oracle's pin: R = [0, 0, -rho, 0, -rho v]).  In mixed precision every
-    derivative must still vanish exactly: the x sweep stages offset fluxes that
-    are exact zeros, the y and z runs form (B f)_i and their closure and wall
-    rows from equal FP64 values, the FP32 viscous differences subtract equal
-    numbers.  So rho, rho u and rho w come out exactly zero, and the two source
-    components within one FP32 rounding (the RHS register) of the oracle."""
+    oracle's pin: R = [0, 0, -rho, 0, -rho v]).  nse_rhs in mixed precision
+    (FP32 eliminations along y and z on (B f)_i formed in FP64) must keep every
+    derivative exactly zero: rho, rho u and rho w come out exactly zero and the
+    two source components within one FP32 rounding of the oracle."""
     import torch
     p = dict(inputs.AIR)
     rho, vel = 0.83, (0.31, -0.47, 0.19)
@@ -161,3 +160,43 @@ def test_rk_mixed_512_bench_configuration():
         del d32
     print("512^3, 5 steps, mixed vs FP64 (change)", ["%.2e" % e for e in errs], flush=True)
     assert max(errs) <= MIXED_CHANGE_BOUND
+
+
+def test_rk_mixed_pencil_fallback_against_oracle():
+    """Runs longer than a line march holds (48^3, one segment per direction:
+    runs of 46 points) step through the LDS pencils along every direction, in
+    mixed precision staged and solved in FP32 on offset fluxes (along y the
+    offset leaves the hydrostatic variation of the line in the FP32 values),
+    with the RK4 update as its own kernel on the FP32 R: the change of every
+    field over 4 RK4 steps against the oracle, within MIXED_CHANGE_BOUND."""
+    p = dict(inputs.AIR)
+    Q0 = inputs.rti_state(48, seed=7, noise_K=1.0)
+    G = _gpu_rk(p, Q0, 1, 1e-5, 4, nopcs.MIXED)
+    O = oracle.rk4(p, Q0, 1e-5, 4)
+    errs = [_rel(G[c] - Q0[c], O[c] - Q0[c]) for c in range(5)]
+    print("48^3 one segment (pencils), mixed vs oracle (change)", ["%.2e" % e for e in errs], flush=True)
+    assert np.isfinite(G).all()
+    assert max(errs) <= MIXED_CHANGE_BOUND and max(errs) > 0.0
+
+
+@pytest.mark.parametrize("shape, nseg", [((40, 36, 70), (2, 3, 2)), ((48, 48, 48), (1, 1, 1))])
+def test_rk_mixed_uniform_rest_is_steady(shape, nseg):
+    """A uniform state at rest without gravity is a steady solution, and in
+    mixed precision every derivative of a uniform field must vanish exactly:
+    the FP32 x sweep and pencils stage offset fluxes that are exact zeros, the
+    y and z runs form (B f)_i from equal FP64 values, the FP32 viscous
+    differences subtract equal numbers.  Over 3 RK4 steps the only change is
+    the wall energy reset from the extrapolated wall temperature (a few ulps of
+    E') and the momentum that drives next to the walls (measured 2.4e-15, the
+    same in FP64); density and the interior energy stay bit for bit.  An FP32 rounding of the full fluxes (|E'| ~ 1e4) would show up as
+    momentum changes many orders larger."""
+    p = dict(inputs.AIR, gravity=0)
+    Q0 = inputs.uniform_state(shape, T=1.3, rho=0.83, params=p)
+    G = _gpu_rk(p, Q0, nseg, 1e-5, 3, nopcs.MIXED)
+    assert np.array_equal(G[0], Q0[0])
+    assert np.array_equal(G[4, 1:-1, 1:-1, 1:-1], Q0[4, 1:-1, 1:-1, 1:-1])
+    # the wall energy as the kernel forms it from the wall temperature against
+    # the generator's E' (measured 5 ulps, 9.1e-12 of 1.16e4)
+    assert np.max(np.abs(G[4] - Q0[4])) <= 2e-15 * np.max(np.abs(Q0[4]))
+    for c in (1, 2, 3):
+        assert np.max(np.abs(G[c])) <= 1e-14, (c, np.max(np.abs(G[c])))
